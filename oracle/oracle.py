@@ -1,0 +1,178 @@
+"""ctypes wrapper of the C oracle (test infrastructure only; see ``spin_oracle.c``).
+
+Every function mirrors one C function; numpy arrays carry the spins (int8,
+site index ``x + L*(y + L*z)``) and couplings (int8, layout ``[dir][site]``).
+``OracleLib(path)`` binds any build of ``spin_oracle.c`` (the tests use this
+to load deliberately broken copies); the module-level functions use the
+default build next to this file.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "spin_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def compile_oracle(src, out):
+    """gcc build of one oracle source file into a shared library."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force=True):
+    """Compile spin_oracle.c into liboracle.so next to it."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(SOURCE):
+        return _LIB
+    return compile_oracle(SOURCE, _LIB)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class OracleLib:
+    """One loaded build of the oracle."""
+
+    def __init__(self, path):
+        lib = ctypes.CDLL(path)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i8p = ctypes.POINTER(ctypes.c_int8)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_table.argtypes = [ctypes.c_double, ctypes.c_int, u64p]
+        lib.oracle_table.restype = None
+        lib.oracle_init_spins.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, i8p]
+        lib.oracle_init_spins.restype = ctypes.c_int
+        lib.oracle_couplings.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, i8p]
+        lib.oracle_couplings.restype = ctypes.c_int
+        lib.oracle_measure.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, i64p, i64p]
+        lib.oracle_measure.restype = None
+        lib.oracle_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      i64p, i64p, ctypes.c_int, u64p]
+        lib.oracle_sweeps.restype = ctypes.c_int
+        self.lib = lib
+
+    def philox4x32_10(self, ctr, key):
+        """Philox4x32-10 block for counter (c0..c3) and key (k0, k1) -> 4 uint32 words."""
+        c = np.asarray(ctr, dtype=np.uint32).copy()
+        k = np.asarray(key, dtype=np.uint32).copy()
+        out = np.zeros(4, dtype=np.uint32)
+        self.lib.oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                                      _ptr(out, ctypes.c_uint32))
+        return out
+
+    def table(self, beta, d):
+        """Acceptance thresholds T[(k+z)/2] as uint64 (Eq. 2)."""
+        out = np.zeros(2 * d + 1, dtype=np.uint64)
+        self.lib.oracle_table(float(beta), int(d), _ptr(out, ctypes.c_uint64))
+        return out
+
+    def init_spins(self, L, d, seed, replica=0):
+        spins = np.empty(L ** d, dtype=np.int8)
+        if self.lib.oracle_init_spins(L, d, seed, replica, _ptr(spins, ctypes.c_int8)) != 0:
+            raise ValueError("bad lattice shape")
+        return spins
+
+    def couplings(self, L, d, cseed, realisation=0):
+        J = np.empty(d * L ** d, dtype=np.int8)
+        if self.lib.oracle_couplings(L, d, cseed, realisation, _ptr(J, ctypes.c_int8)) != 0:
+            raise ValueError("bad lattice shape")
+        return J
+
+    def measure(self, L, d, J, spins):
+        spins = np.ascontiguousarray(spins, dtype=np.int8)
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        Jp = None if Jarr is None else _ptr(Jarr, ctypes.c_int8)
+        E = ctypes.c_int64()
+        M = ctypes.c_int64()
+        self.lib.oracle_measure(L, d, Jp, _ptr(spins, ctypes.c_int8), ctypes.byref(E), ctypes.byref(M))
+        return E.value, M.value
+
+    def sweeps(self, L, d, J, spins, seed, replica, t0, n, beta, every=0, order=0, stats=None):
+        """Advance ``spins`` in place by n sweeps starting at absolute sweep t0.
+
+        Returns (E, M) int64 arrays with n//every records (empty if every == 0).
+        ``stats`` (uint64 array of 2*(2d+1)) accumulates per-class attempts and
+        acceptances when given.
+        """
+        assert spins.dtype == np.int8 and spins.flags.c_contiguous
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1), dtype=np.int64)
+        M = np.zeros(max(nrec, 1), dtype=np.int64)
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        Jp = None if Jarr is None else _ptr(Jarr, ctypes.c_int8)
+        sp = None
+        if stats is not None:
+            assert stats.dtype == np.uint64 and stats.size == 2 * (2 * d + 1)
+            sp = _ptr(stats, ctypes.c_uint64)
+        rc = self.lib.oracle_sweeps(L, d, Jp, _ptr(spins, ctypes.c_int8), seed, replica, t0, n, float(beta),
+                                    every, _ptr(E, ctypes.c_int64), _ptr(M, ctypes.c_int64), order, sp)
+        if rc != 0:
+            raise ValueError("oracle_sweeps rejected its arguments")
+        return E[:nrec].copy(), M[:nrec].copy()
+
+
+_default = None
+
+
+def default():
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(SOURCE):
+            build()
+        _default = OracleLib(_LIB)
+    return _default
+
+
+def philox4x32_10(ctr, key):
+    return default().philox4x32_10(ctr, key)
+
+
+def table(beta, d):
+    return default().table(beta, d)
+
+
+def init_spins(L, d, seed, replica=0):
+    return default().init_spins(L, d, seed, replica)
+
+
+def couplings(L, d, cseed, realisation=0):
+    return default().couplings(L, d, cseed, realisation)
+
+
+def measure(L, d, J, spins):
+    return default().measure(L, d, J, spins)
+
+
+def sweeps(L, d, J, spins, seed, replica, t0, n, beta, every=0, order=0, stats=None):
+    return default().sweeps(L, d, J, spins, seed, replica, t0, n, beta, every, order, stats)
+
+
+class Chain:
+    """Convenience state holder: one lattice advanced by an oracle build."""
+
+    def __init__(self, L, d, seed, replica=0, J=None, spins=None, lib=None):
+        self.lib = lib or default()
+        self.L, self.d, self.seed, self.replica, self.J = L, d, seed, replica, J
+        self.spins = (self.lib.init_spins(L, d, seed, replica) if spins is None
+                      else np.array(spins, dtype=np.int8))
+        self.t = 0
+
+    def sweep(self, n, beta, every=0, order=0, stats=None):
+        E, M = self.lib.sweeps(self.L, self.d, self.J, self.spins, self.seed, self.replica, self.t, n, beta,
+                               every, order, stats)
+        self.t += n
+        return E, M
+
+    def measure(self):
+        return self.lib.measure(self.L, self.d, self.J, self.spins)

@@ -1,0 +1,288 @@
+/*
+ * spin_oracle.c -- plain, single-threaded CPU oracle for checkerboard
+ * Metropolis sweeps of the 2D/3D Ising ferromagnet and the +-J
+ * Edwards-Anderson spin glass.
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it.  It shares no code, header,
+ * table or constant with the GPU library; it is written to be read against
+ * the paper (Weigel, "Simulating spin models on GPU"), not to be fast.
+ *
+ * What it computes (the canonical chain):
+ *
+ *  Lattice (Sec. 3, Eq. 1 and the sentence after it): edge L (even), d = 2
+ *  or 3, periodic boundaries, site index s = x + L*(y + L*z) with x
+ *  fastest.  Colour of a site = (x + y + z) mod 2.
+ *
+ *  Energy (Sec. 3, Eq. 1, with J = 1 absorbed into beta; the +-J glass of
+ *  Sec. 4, last paragraph, replaces J by a bond variable J_ij):
+ *      E = - sum_s sum_dir J[dir][s] * s_s * s_{s + e_dir}
+ *  every bond counted once.  For the ferromagnet J == 1.
+ *
+ *  Metropolis rule (Sec. 3, Eq. 2): flipping s_i changes the energy by
+ *  dE = 2*k with k = s_i * h_i, h_i = sum of J-weighted neighbour spins.
+ *  The move is accepted with probability min(1, exp(-beta*dE)).  With a
+ *  uniform 32-bit integer r this is decided exactly as  r < T[k]  where
+ *      T[k] = 2^32                                 for k <= 0,
+ *      T[k] = floor(2^32 * exp(-(beta*(2k))))      for k  > 0,
+ *  evaluated in IEEE double (one rounding of the product beta*dE, libm exp,
+ *  exact scaling by 2^32, floor) and stored as a 64-bit integer, so the
+ *  compare is between 64-bit integers.  The table is indexed by (k+z)/2,
+ *  z = 2d.
+ *
+ *  Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel
+ *  random numbers: as easy as 1, 2, 3", SC'11) with key (seed_lo, seed_hi).
+ *  The paper's per-thread LCG array (Sec. 4, first paragraph) is replaced
+ *  by this counter-based generator; its period concerns are the reason.
+ *  Counter layouts (c0, c1, c2, c3), word index in brackets:
+ *      update of site s in sweep t, colour c : (s>>3, t, replica, c) [(s>>1)&3]
+ *      hot-start spin of site s               : (s>>2, 0, replica, 2) [s&3]
+ *      coupling J[dir][s] (key = coupling seed): (s>>2, dir, realisation, 3) [s&3]
+ *  A hot-start spin is +1 when bit 31 of its word is set, else -1; a
+ *  coupling is -1 when bit 31 of its word is set, else +1.
+ *
+ *  Sweep t (Sec. 3, steps 1-7, read as the plain red/black chain): first
+ *  every colour-0 site, then every colour-1 site, each site updated from
+ *  the current spins; the order inside a colour does not matter because no
+ *  two sites of one colour are neighbours (Sec. 3, the sentence on the
+ *  independence of sub-lattice sites).  The paper's coarse-tile ordering
+ *  and its k-fold multi-hit repetition change the chain and are not part
+ *  of it.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+/* ---------------------------------------------------------------- Philox */
+
+/* One Philox4x32-10 block: ten rounds of the S-box below, with the key
+ * bumped by the Weyl constants between rounds (SC'11, Sec. 3.2). */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                          uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    if (round < 9) { k0 += W0; k1 += W1; }
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                     uint32_t c3, unsigned word) {
+  uint32_t ctr[4] = {c0, c1, c2, c3};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  oracle_philox4x32_10(ctr, key, out);
+  return out[word];
+}
+
+/* ------------------------------------------------------ threshold table */
+
+/* T[(k+z)/2] for k = -z, -z+2, ..., z (Sec. 3, Eq. 2). */
+void oracle_table(double beta, int d, uint64_t* T) {
+  int z = 2 * d;
+  for (int k = -z; k <= z; k += 2) {
+    uint64_t v;
+    if (k <= 0) {
+      v = (uint64_t)1 << 32;
+    } else {
+      double dE = (double)(2 * k);
+      double p = exp(-(beta * dE));
+      v = (uint64_t)floor(ldexp(p, 32));
+    }
+    T[(k + z) / 2] = v;
+  }
+}
+
+/* ------------------------------------------------------------- lattice */
+
+static int64_t site_count(int L, int d) {
+  int64_t n = 1;
+  for (int i = 0; i < d; ++i) n *= L;
+  return n;
+}
+
+/* Coordinates of site s. */
+static void coords(int64_t s, int L, int d, int64_t x[3]) {
+  x[0] = s % L;
+  x[1] = (s / L) % L;
+  x[2] = (d == 3) ? s / ((int64_t)L * L) : 0;
+}
+
+static int64_t index_of(const int64_t x[3], int L, int d) {
+  int64_t s = x[0] + (int64_t)L * x[1];
+  if (d == 3) s += (int64_t)L * L * x[2];
+  return s;
+}
+
+/* Neighbour of s one step along +dir (sign=+1) or -dir (sign=-1). */
+static int64_t neighbour(int64_t s, int dir, int sign, int L, int d) {
+  int64_t x[3];
+  coords(s, L, d, x);
+  x[dir] = (x[dir] + sign + L) % L;
+  return index_of(x, L, d);
+}
+
+static int colour_of(int64_t s, int L, int d) {
+  int64_t x[3];
+  coords(s, L, d, x);
+  return (int)((x[0] + x[1] + x[2]) % 2);
+}
+
+static int valid_shape(int L, int d) {
+  if (d != 2 && d != 3) return 0;
+  if (L < 4 || (L % 2) != 0) return 0;
+  if (site_count(L, d) / 8 >= ((int64_t)1 << 32)) return 0;
+  return 1;
+}
+
+/* ---------------------------------------------------- inputs of the chain */
+
+/* Seeded uniform hot start. */
+int oracle_init_spins(int L, int d, uint64_t seed, uint32_t replica,
+                      int8_t* spins) {
+  if (!valid_shape(L, d)) return -1;
+  int64_t N = site_count(L, d);
+  for (int64_t s = 0; s < N; ++s) {
+    uint32_t r = draw(seed, (uint32_t)(s >> 2), 0u, replica, 2u,
+                      (unsigned)(s & 3));
+    spins[s] = (r >> 31) ? (int8_t)1 : (int8_t)-1;
+  }
+  return 0;
+}
+
+/* +-J couplings, each sign with probability 1/2; layout [dir][site]. */
+int oracle_couplings(int L, int d, uint64_t cseed, uint32_t realisation,
+                     int8_t* J) {
+  if (!valid_shape(L, d)) return -1;
+  int64_t N = site_count(L, d);
+  for (int dir = 0; dir < d; ++dir)
+    for (int64_t s = 0; s < N; ++s) {
+      uint32_t r = draw(cseed, (uint32_t)(s >> 2), (uint32_t)dir, realisation,
+                        3u, (unsigned)(s & 3));
+      J[(int64_t)dir * N + s] = (r >> 31) ? (int8_t)-1 : (int8_t)1;
+    }
+  return 0;
+}
+
+static int coupling(const int8_t* J, int dir, int64_t s, int64_t N) {
+  return J ? (int)J[(int64_t)dir * N + s] : 1;
+}
+
+/* --------------------------------------------------------- observables */
+
+/* E = -sum over bonds J s s (Eq. 1), M = sum of spins. */
+void oracle_measure(int L, int d, const int8_t* J, const int8_t* spins,
+                    int64_t* E, int64_t* M) {
+  int64_t N = site_count(L, d);
+  int64_t e = 0, m = 0;
+  for (int64_t s = 0; s < N; ++s) {
+    m += spins[s];
+    for (int dir = 0; dir < d; ++dir) {
+      int64_t t = neighbour(s, dir, +1, L, d);
+      e -= (int64_t)coupling(J, dir, s, N) * spins[s] * spins[t];
+    }
+  }
+  *E = e;
+  *M = m;
+}
+
+/* Local field h_s = sum over the 2d neighbours of J_bond * s_neighbour. */
+static int local_field(int64_t s, int L, int d, const int8_t* J,
+                       const int8_t* spins, int64_t N) {
+  int h = 0;
+  for (int dir = 0; dir < d; ++dir) {
+    int64_t up = neighbour(s, dir, +1, L, d);
+    int64_t dn = neighbour(s, dir, -1, L, d);
+    h += coupling(J, dir, s, N) * spins[up];   /* bond (s, s+e_dir)  */
+    h += coupling(J, dir, dn, N) * spins[dn];  /* bond (s-e_dir, s)  */
+  }
+  return h;
+}
+
+/* ------------------------------------------------------------- sweeps */
+
+/* Visiting order inside one colour: 0 forward, 1 reverse, 2 a seeded
+ * shuffle.  All three give the same bits; the option exists so that the
+ * tests can show it. */
+static void visit_order(int64_t* list, int64_t n, int order, uint64_t salt) {
+  if (order == 1) {
+    for (int64_t i = 0; i < n / 2; ++i) {
+      int64_t tmp = list[i];
+      list[i] = list[n - 1 - i];
+      list[n - 1 - i] = tmp;
+    }
+  } else if (order == 2) {
+    uint64_t x = salt * 0x9E3779B97F4A7C15ull + 1;
+    for (int64_t i = n - 1; i > 0; --i) {
+      x ^= x << 13; x ^= x >> 7; x ^= x << 17;  /* xorshift64 */
+      int64_t j = (int64_t)(x % (uint64_t)(i + 1));
+      int64_t tmp = list[i];
+      list[i] = list[j];
+      list[j] = tmp;
+    }
+  }
+}
+
+/*
+ * Run n sweeps, the first one with absolute index t0.  If every > 0,
+ * (E, M) is written after each every-th sweep of this call (n/every
+ * records).  stats, if not NULL, receives per class i = (k+z)/2 the number
+ * of attempts stats[i] and acceptances stats[z+1+i].
+ * Returns 0, or -1 on bad arguments.
+ */
+int oracle_sweeps(int L, int d, const int8_t* J, int8_t* spins, uint64_t seed,
+                  uint32_t replica, uint64_t t0, int n, double beta, int every,
+                  int64_t* E, int64_t* M, int order, uint64_t* stats) {
+  if (!valid_shape(L, d) || n < 0) return -1;
+  if (isnan(beta) || beta < 0) return -1;
+  if (t0 + (uint64_t)n > ((uint64_t)1 << 32)) return -1;
+  int z = 2 * d;
+  uint64_t T[7];
+  oracle_table(beta, d, T);
+  int64_t N = site_count(L, d);
+  int64_t* list = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N / 2 + 1));
+  if (!list) return -1;
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    uint32_t t = (uint32_t)(t0 + (uint64_t)i);
+    for (int c = 0; c < 2; ++c) {
+      int64_t cnt = 0;
+      for (int64_t s = 0; s < N; ++s)
+        if (colour_of(s, L, d) == c) list[cnt++] = s;
+      visit_order(list, cnt, order, (uint64_t)t * 2 + (uint64_t)c);
+      for (int64_t q = 0; q < cnt; ++q) {
+        int64_t s = list[q];
+        int h = local_field(s, L, d, J, spins, N);
+        int k = spins[s] * h;
+        int cls = (k + z) / 2;
+        uint32_t r = draw(seed, (uint32_t)(s >> 3), t, replica, (uint32_t)c,
+                          (unsigned)((s >> 1) & 3));
+        int accept = (uint64_t)r < T[cls];
+        if (stats) {
+          stats[cls] += 1;
+          if (accept) stats[z + 1 + cls] += 1;
+        }
+        if (accept) spins[s] = (int8_t)(-spins[s]);
+      }
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      oracle_measure(L, d, J, spins, &E[rec], &M[rec]);
+      ++rec;
+    }
+  }
+  free(list);
+  return 0;
+}

@@ -1,0 +1,97 @@
+"""Plant plausible mistakes in copies of the oracle and show the pins catch each.
+
+Every mutant is a text edit of ``oracle/spin_oracle.c`` (a dropped term, a
+wrong sign, a swapped operand or index, a wrong counter word, a wrong
+colour order...).  Each is compiled on the CPU and run through a quick
+subset of the pins of ``test_oracle_pins.py``; at least one pin must fail.
+The unmodified source must pass the same subset.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import oracle
+
+MUTANTS = {
+    "drop_backward_neighbour": ("h += coupling(J, dir, dn, N) * spins[dn];", "(void)dn;"),
+    "wrong_sign_of_k": ("int k = spins[s] * h;", "int k = -spins[s] * h;"),
+    "dE_is_k_not_2k": ("double dE = (double)(2 * k);", "double dE = (double)k;"),
+    "colour_order_swapped": ("for (int c = 0; c < 2; ++c) {", "for (int c = 1; c >= 0; --c) {"),
+    "update_counter_word_s_over_4": ("draw(seed, (uint32_t)(s >> 3), t, replica", "draw(seed, (uint32_t)(s >> 2), t, replica"),
+    "update_word_index": ("(unsigned)((s >> 1) & 3));", "(unsigned)(s & 3));"),
+    "philox_swapped_high_words": ("uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;"),
+    "philox_key_not_bumped": ("if (round < 9) { k0 += W0; k1 += W1; }", "if (round < 9) { k0 += W0; }"),
+    "energy_sign": ("e -= (int64_t)coupling(J, dir, s, N) * spins[s] * spins[t];",
+                    "e += (int64_t)coupling(J, dir, s, N) * spins[s] * spins[t];"),
+    "hot_start_inverted": ("spins[s] = (r >> 31) ? (int8_t)1 : (int8_t)-1;",
+                           "spins[s] = (r >> 31) ? (int8_t)-1 : (int8_t)1;"),
+    "coupling_of_wrong_bond": ("h += coupling(J, dir, s, N) * spins[up];", "h += coupling(J, dir, up, N) * spins[up];"),
+    "y_coordinate_wraps_wrong": ("x[1] = (s / L) % L;", "x[1] = (s / L) % (L - 1);"),
+    "table_index_off_by_one": ("int accept = (uint64_t)r < T[cls];", "int accept = (uint64_t)r < T[cls > 0 ? cls - 1 : 0];"),
+    "table_ceil": ("v = (uint64_t)floor(ldexp(p, 32));", "v = (uint64_t)ceil(ldexp(p, 32));"),
+}
+
+
+def _quick_pins(lib, rocrand_philox):
+    """Raise AssertionError on the first pin that fails."""
+    # Philox against rocRAND
+    ctrs = np.array([[0, 0, 0, 0], [7, 3, 2, 1], [0xFFFFFFFF] * 4], dtype=np.uint64)
+    key = (0x00000001, 0x10063865)
+    np.testing.assert_array_equal(np.array([lib.philox4x32_10(c, key) for c in ctrs]), rocrand_philox(ctrs, key))
+    # table closed form at a few betas
+    for beta in (0.3, 0.5, 2.0):
+        T = lib.table(beta, 3)
+        for i, k in enumerate(range(-6, 7, 2)):
+            want = 1 << 32 if k <= 0 else math.floor(math.ldexp(math.exp(-beta * 2 * k), 32))
+            assert int(T[i]) == want
+    # inputs of the chain against rocRAND bit rules
+    L, d, seed = 4, 2, 0x1006386500000003
+    words = rocrand_philox([(s >> 2, 0, 0, 2) for s in range(L * L)], (seed & 0xFFFFFFFF, seed >> 32))
+    expect = np.array([1 if words[s, s & 3] >> 31 else -1 for s in range(L * L)], dtype=np.int8)
+    np.testing.assert_array_equal(lib.init_spins(L, d, seed, 0), expect)
+    # measurement against brute force
+    rng = np.random.default_rng(0)
+    for (L, d) in ((6, 2), (4, 3)):
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=L ** d)
+        J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d)
+        assert lib.measure(L, d, J, s) == (bf.energy(s, L, d, J), bf.magnetisation(s))
+    # sweeps against the brute-force restatement with rocRAND draws
+    for (L, d, ea, beta) in ((4, 2, False, 0.44), (6, 2, True, 0.8), (4, 3, True, 0.5)):
+        seed, rep, t0, n = 0x1006386500000009, 1, 2, 2
+        J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d) if ea else None
+        s0 = rng.choice(np.array([-1, 1], dtype=np.int8), size=L ** d)
+        got = s0.copy()
+        lib.sweeps(L, d, J, got, seed, rep, t0, n, beta)
+        N = L ** d
+        ctrs, keys = [], []
+        for t in range(t0, t0 + n):
+            for c in (0, 1):
+                for g in range((N + 7) // 8):
+                    ctrs.append((g, t, rep, c))
+                    keys.append((g, t, c))
+        w = dict(zip(keys, rocrand_philox(ctrs, (seed & 0xFFFFFFFF, seed >> 32))))
+        ref = s0.copy()
+        for t in range(t0, t0 + n):
+            bf.sweep(ref, L, d, J, beta, t, lambda s, tt, c: int(w[(s >> 3, tt, c)][(s >> 1) & 3]))
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_unmodified_oracle_passes_quick_pins(oracle_mod, rocrand_philox):
+    _quick_pins(oracle_mod.default(), rocrand_philox)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path, rocrand_philox):
+    src = open(oracle.SOURCE).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, "mutation anchor must match exactly once: " + old
+    path = os.path.join(str(tmp_path), "mutant.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = oracle.compile_oracle(path, os.path.join(str(tmp_path), "libmutant.so"))
+    lib = oracle.OracleLib(so)
+    with pytest.raises(AssertionError):
+        _quick_pins(lib, rocrand_philox)
