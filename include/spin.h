@@ -1,0 +1,171 @@
+/*
+ * spin.h -- C ABI of the MI355X (gfx950) checkerboard Metropolis library.
+ *
+ * The library advances 2D (square) and 3D (simple cubic) lattices of +-1
+ * spins, edge L, periodic boundaries, with single-spin-flip Metropolis
+ * updates in red/black (checkerboard) order: the Ising ferromagnet of
+ * Weigel, "Simulating spin models on GPU", Sec. 3, Eq. 1, and the +-J
+ * Edwards-Anderson glass (same paper, Sec. 4, last paragraph).
+ *
+ * Definition of the chain computed (identical bits on every code path):
+ *   - site s = x + L*(y + L*z), x fastest; colour(s) = (x+y+z) mod 2;
+ *   - E = -sum_bonds J_b s_i s_j (each bond once; J_b = 1 for Ising),
+ *     M = sum_i s_i, both exact 64-bit integers;
+ *   - a sweep with absolute index t updates every colour-0 site, then every
+ *     colour-1 site; site s flips iff r < T[(k+2d)/2], k = s_i*h_i, h_i the
+ *     J-weighted neighbour sum (Sec. 3, Eq. 2: dE = 2k), where
+ *     T = 2^32 for k <= 0 and floor(2^32*exp(-(beta*2k))) otherwise,
+ *     computed on the host in IEEE double and compared as 64-bit integers;
+ *   - r is word (s>>1)&3 of Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed_lo, seed_hi) and counter (s>>3, t, replica, colour);
+ *   - hot start: spin s = +1 iff bit 31 of word s&3 of Philox with counter
+ *     (s>>2, 0, replica, 2) is set;
+ *   - generated couplings: J[dir][s] = -1 iff bit 31 of word s&3 of
+ *     Philox(key = coupling seed, counter (s>>2, dir, realisation, 3)).
+ *
+ * Layouts: spins are int8 (+1/-1), N = L^d of them in site order.
+ * Couplings are int8 (+1/-1), layout [dir][site]: J[dir*N + s] is the bond
+ * between s and its +1 neighbour along dir (dir 0 = x, 1 = y, 2 = z).
+ *
+ * Errors: functions returning int give SPIN_OK (0) or a negative
+ * spin_status; constructors return NULL.  spin_last_error() then holds a
+ * message for the calling thread.  Work is enqueued on the handle's HIP
+ * stream; a device fault surfaces at the next call that synchronises.
+ *
+ * Threading: a handle must not be used by two threads at once; different
+ * handles are independent.  All host buffers belong to the caller and are
+ * only read/written during the call.  Device memory belongs to the library.
+ */
+#ifndef SPIN_H
+#define SPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spin_lattice spin_lattice;
+
+enum spin_model { SPIN_ISING = 0, SPIN_EA_PMJ = 1 };
+
+enum spin_status {
+  SPIN_OK = 0,
+  SPIN_EINVAL = -1,  /* bad argument (message says which) */
+  SPIN_ENOMEM = -2,  /* device allocation failed */
+  SPIN_EDEVICE = -3, /* HIP runtime or kernel error */
+  SPIN_ESTATE = -4   /* call not valid in the handle's state */
+};
+
+/* Kernel families; the chain (and so every bit of output) is the same. */
+enum spin_kernel {
+  SPIN_KERNEL_AUTO = 0,     /* library picks */
+  SPIN_KERNEL_GENERIC = 1,  /* per-site, global memory, any even L */
+  SPIN_KERNEL_RESIDENT = 2, /* whole lattice in one workgroup's LDS, all sweeps in one launch */
+  SPIN_KERNEL_TILED = 3,    /* LDS tile + halo per colour phase, needs L % 8 == 0 */
+  SPIN_KERNEL_FUSED = 4     /* 2D Ising: both colours per launch, ping-pong buffers, needs L % 8 == 0 */
+};
+
+/* Full set of creation parameters. */
+typedef struct {
+  int model;                 /* spin_model */
+  int L;                     /* edge, even, >= 4; L^d/8 < 2^32 */
+  int d;                     /* 2 or 3 */
+  const int8_t* couplings;   /* host, d*L^d values +-1 ([dir][site]); copied.
+                                Ising: must be NULL.  EA: NULL means generate
+                                from coupling_seed / realisation on the device. */
+  uint64_t coupling_seed;    /* EA with couplings == NULL only */
+  uint32_t realisation;      /* EA with couplings == NULL only */
+  uint64_t seed;             /* Philox key of the hot start and of the updates */
+  uint32_t replica;          /* third counter word of the hot start and updates */
+  void* stream;              /* hipStream_t to enqueue on; NULL = null stream */
+} spin_config;
+
+/* Sec. 3 and Sec. 4: create a lattice in the seeded hot start (replica 0,
+ * null stream).  couplings: NULL for SPIN_ISING; for SPIN_EA_PMJ a host
+ * array of d*L^d values +-1, copied before return.  NULL on error. */
+spin_lattice* spin_create(int model, int L, int d, const int8_t* couplings, uint64_t seed);
+
+/* Same with every parameter (replica, stream, generated couplings). */
+spin_lattice* spin_create_config(const spin_config* cfg);
+
+/* Release a handle and its device memory; NULL is ignored.  Waits for the
+ * handle's queued work first. */
+void spin_free(spin_lattice* h);
+
+/* Sec. 3, steps 1-7 (read as the plain red/black chain) with Eq. 2:
+ * enqueue n >= 0 sweeps at inverse temperature beta (finite and >= 0, or
+ * +inf for a zero-temperature quench; NaN or negative is SPIN_EINVAL).
+ * Asynchronous.  The handle's sweep counter advances by n, so
+ * spin_sweep(h,a,b); spin_sweep(h,c,b) equals spin_sweep(h,a+c,b). */
+int spin_sweep(spin_lattice* h, int n, double beta);
+
+/* As spin_sweep, and record (E, M) after every every-th sweep of this call
+ * (n/every records; every >= 1).  E and M are HOST arrays of n/every int64;
+ * the call synchronises before returning. */
+int spin_sweep_record(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M);
+
+/* As spin_sweep_record, but E and M are DEVICE arrays (n/every int64 each)
+ * written asynchronously on the handle's stream. */
+int spin_sweep_record_device(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M);
+
+/* Sec. 4 (the energy and magnetisation measured between sweeps): current
+ * E and M into host int64s.  Synchronises. */
+int spin_measure(spin_lattice* h, int64_t* E, int64_t* M);
+
+/* Copy the L^d spins to / from host memory (n must equal L^d; values put
+ * must be +-1).  Synchronous. */
+int spin_get_spins(const spin_lattice* h, int8_t* out, size_t n);
+int spin_set_spins(spin_lattice* h, const int8_t* in, size_t n);
+
+/* Couplings actually used (d*L^d int8, [dir][site]) into a host array.
+ * SPIN_ESTATE for the Ising model. */
+int spin_get_couplings(const spin_lattice* h, int8_t* out, size_t n);
+
+/* Absolute index of the next sweep (number of sweeps done so far). */
+uint64_t spin_sweeps_done(const spin_lattice* h);
+
+/* Set the absolute sweep index of the next sweep (resume from a saved
+ * state together with spin_set_spins).  index + later sweeps < 2^32. */
+int spin_set_sweeps_done(spin_lattice* h, uint64_t t);
+
+/* Enqueue later work on this hipStream_t (NULL = null stream). */
+int spin_set_stream(spin_lattice* h, void* stream);
+
+/* Choose the kernel family and tile shape: tile_x (bytes, multiple of 8),
+ * tile_y, tile_z (rows/planes) and threads per workgroup (multiple of 64).
+ * 0 means the library default.  SPIN_EINVAL if the family cannot run this
+ * lattice.  Results are bit-identical for every accepted choice. */
+int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads);
+
+/* Kernel family that spin_sweep will use next (spin_kernel value). */
+int spin_get_kernel(const spin_lattice* h);
+
+/* Wait for the handle's queued work. */
+int spin_synchronize(spin_lattice* h);
+
+/* Device pointer to the current spins (valid until the next sweep call,
+ * which may swap buffers).  NULL on error. */
+const int8_t* spin_device_spins(const spin_lattice* h);
+
+/* Sec. 3, Eq. 2: the acceptance table the library uses, T[(k+2d)/2] for
+ * k = -2d..2d step 2 (2d+1 uint64 values written to T).  Host only. */
+int spin_threshold_table(double beta, int d, uint64_t* T);
+
+/* Install device allocation callbacks (NULL, NULL restores hipMalloc /
+ * hipFree).  alloc(bytes, ctx) returns a device pointer or NULL;
+ * release(ptr, ctx) frees it.  Affects handles created afterwards. */
+void spin_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* spin_last_error(void);
+
+/* Library version string. */
+const char* spin_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIN_H */

@@ -1,0 +1,123 @@
+// spin_device.h -- device-side building blocks for gfx950: Philox4x32-10,
+// the byte-parallel (four sites per 32-bit register) Metropolis update of an
+// aligned 8-site group, and wavefront reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spin_internal.h"
+
+namespace spin {
+
+// Three-input XOR in one VALU op (v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products (one v_mad_u64_u32 each) and two three-way XORs with
+// the precomputed round keys.
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       const RoundKeys& K, uint32_t r[4]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, K.k0[i]);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, K.k1[i]);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
+}
+
+// ---------------------------------------------------------------------------
+// Byte-parallel update of one aligned group of 8 sites along x.
+//
+// Spin bytes are 0x01 (+1) or 0xFF (-1): every bit from 1 to 7 carries the
+// sign, so (a ^ b) & 0x04 per byte is 4 exactly when the two spins differ.
+// Summing that over the 2d neighbours gives 4*u per byte, u = number of
+// unsatisfied bonds (u <= 6, so no byte overflows).  For a +-J bond the
+// coupling byte joins the XOR: the bond is unsatisfied iff s_i J s_j = -1.
+// With k = s_i h_i = 2d - 2u the Metropolis rule r < T[k] becomes a lookup
+// of a 32-bit bound by the byte value 4u in a small LDS table:
+//   bound[u] = T - 1         (accept iff r <= bound; T in [1, 2^32])
+//   bound[u] = 0 with u < never_level for T == 0 (rejected separately).
+// The flip itself XORs the byte with 0xFE (0x01 <-> 0xFF).
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kSignBit = 0x04040404u;
+
+// 4u per byte for the two centre dwords.  lw / rw: the dword left of c0 and
+// right of c1; o0 / o1: the other 2d-2 neighbour dwords (rows / planes).
+template <int NO>
+__device__ __forceinline__ void unsat_ising(uint32_t c0, uint32_t c1, uint32_t lw, uint32_t rw,
+                                            const uint32_t (&o0)[NO], const uint32_t (&o1)[NO],
+                                            uint32_t& S0, uint32_t& S1) {
+  const uint32_t L0 = __builtin_amdgcn_alignbyte(c0, lw, 3);
+  const uint32_t L1 = __builtin_amdgcn_alignbyte(c1, c0, 3);
+  const uint32_t R0 = __builtin_amdgcn_alignbyte(c1, c0, 1);
+  const uint32_t R1 = __builtin_amdgcn_alignbyte(rw, c1, 1);
+  S0 = ((c0 ^ L0) & kSignBit) + ((c0 ^ R0) & kSignBit);
+  S1 = ((c1 ^ L1) & kSignBit) + ((c1 ^ R1) & kSignBit);
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    S0 += (c0 ^ o0[i]) & kSignBit;
+    S1 += (c1 ^ o1[i]) & kSignBit;
+  }
+}
+
+// Accept decision for the active byte at bit offset sh of S, word r.
+template <bool NEVER>
+__device__ __forceinline__ uint32_t flip_bits(uint32_t S, uint32_t sh, uint32_t r,
+                                              const uint32_t* bound_lds, uint32_t never4) {
+  const uint32_t i4 = (S >> sh) & 0xffu;  // 4u
+  const uint32_t b = *(const uint32_t*)((const char*)bound_lds + i4);
+  bool acc = r <= b;
+  if (NEVER) acc = acc && (i4 >= never4);
+  return acc ? (0xFEu << sh) : 0u;
+}
+
+// New value of the 8-site group given 4u per byte, the parity p of the
+// active bytes (p, p+2, p+4, p+6) and the four Philox words.
+template <bool NEVER>
+__device__ __forceinline__ void apply_group(uint32_t& c0, uint32_t& c1, uint32_t S0, uint32_t S1,
+                                            uint32_t p, const uint32_t r[4],
+                                            const uint32_t* bound_lds, uint32_t never4) {
+  const uint32_t sa = 8u * p, sb = 8u * p + 16u;
+  const uint32_t f0 = flip_bits<NEVER>(S0, sa, r[0], bound_lds, never4);
+  const uint32_t f1 = flip_bits<NEVER>(S0, sb, r[1], bound_lds, never4);
+  const uint32_t f2 = flip_bits<NEVER>(S1, sa, r[2], bound_lds, never4);
+  const uint32_t f3 = flip_bits<NEVER>(S1, sb, r[3], bound_lds, never4);
+  c0 = xor3(c0, f0, f1);
+  c1 = xor3(c1, f2, f3);
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread must call it; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* scratch /* NT/64 */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  int64_t s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += scratch[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+}  // namespace spin

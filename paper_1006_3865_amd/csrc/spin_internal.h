@@ -1,0 +1,69 @@
+// spin_internal.h -- types shared by the host runtime and the kernels, and
+// the launch functions the runtime calls.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spin {
+
+// Philox4x32-10 round keys: key (k0, k1) plus i times the Weyl constants
+// (0x9E3779B9, 0xBB67AE85) for round i, precomputed on the host.
+struct RoundKeys {
+  uint32_t k0[10];
+  uint32_t k1[10];
+};
+
+// Acceptance data for one (beta, d): the 64-bit table of Eq. 2 and the
+// 32-bit bounds indexed by u = number of unsatisfied bonds (see spin_device.h).
+struct Accept {
+  uint64_t T[8];       // T[(k+z)/2], z+1 entries
+  uint32_t bound[8];   // bound[u], z+1 entries
+  uint32_t never_level;  // classes u < never_level have T == 0
+};
+
+// Everything one colour phase (or a resident run) of one lattice needs.
+struct Lat {
+  int8_t* spins;
+  const int8_t* J;     // [dir][site] or nullptr (Ising)
+  uint32_t L;
+  uint32_t d;
+  uint64_t N;
+  uint32_t replica;
+  RoundKeys keys;
+};
+
+RoundKeys make_round_keys(uint64_t seed);
+Accept make_accept(double beta, int d);
+
+// Kernel tile shapes (bytes along x, rows along y, planes along z, threads).
+struct Tile {
+  int x, y, z, threads;
+};
+
+// ---- launchers (all asynchronous on `stream`, return the launch status) ----
+hipError_t launch_init_spins(const Lat& lat, hipStream_t stream);
+hipError_t launch_couplings(int8_t* J, uint32_t L, uint32_t d, uint64_t N, uint64_t cseed,
+                            uint32_t realisation, hipStream_t stream);
+hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t stream);
+// Adds E and M of the lattice into *E, *M (which must hold 0 beforehand).
+hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t stream);
+
+// One colour phase with the per-site generic kernel, any even L.
+hipError_t launch_generic_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
+                                hipStream_t stream);
+// n sweeps with the whole lattice in one workgroup's LDS; E/M written to
+// E[i], M[i] after every every-th sweep (every == 0: no records).
+size_t resident_lds_bytes(const Lat& lat);
+hipError_t launch_resident(const Lat& lat, uint32_t t0, int n, const Accept& acc, int every,
+                           int64_t* E, int64_t* M, int threads, hipStream_t stream);
+// One colour phase, LDS tile + one-site halo, in place; Ising, L % 8 == 0.
+bool tiled_supported(const Lat& lat, const Tile& tile);
+hipError_t launch_tiled_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
+                              const Tile& tile, hipStream_t stream);
+// One whole sweep of a 2D Ising lattice from `src` into `dst` (ping-pong).
+bool fused_supported(const Lat& lat, const Tile& tile);
+hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
+                              const Accept& acc, const Tile& tile, hipStream_t stream);
+
+}  // namespace spin

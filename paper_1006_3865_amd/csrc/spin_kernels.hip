@@ -1,0 +1,665 @@
+// spin_kernels.hip -- gfx950 kernels of the checkerboard Metropolis path.
+//
+// Families (all produce the same bits; the chain is stated in include/spin.h):
+//   generic   one colour phase, per site, global memory, any even L;
+//   resident  whole lattice in one workgroup's LDS, many sweeps per launch
+//             (small lattices: one launch per call);
+//   tiled     one colour phase, an LDS tile plus a one-site halo, updated in
+//             place, 8-site groups processed four sites per register (2D/3D
+//             Ising, L % 8 == 0);
+//   fused     2D Ising, a whole sweep per launch: tile plus a two-site halo,
+//             colour 0 on the tile and its one-site ring, barrier, colour 1
+//             on the tile, written to the other buffer of a ping-pong pair.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spin_device.h"
+#include "spin_internal.h"
+
+namespace spin {
+
+// ============================================================ hot start etc.
+
+__global__ void k_init_spins(int8_t* __restrict__ spins, uint64_t nquads, RoundKeys K,
+                             uint32_t replica) {
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nquads;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t r[4];
+    philox((uint32_t)q, 0u, replica, 2u, K, r);
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v |= ((r[j] >> 31) ? 0x01u : 0xFFu) << (8 * j);
+    reinterpret_cast<uint32_t*>(spins)[q] = v;
+  }
+}
+
+__global__ void k_couplings(int8_t* __restrict__ J, uint64_t nquads, uint32_t d, RoundKeys K,
+                            uint32_t realisation) {
+  for (uint32_t dir = 0; dir < d; ++dir)
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nquads;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+      uint32_t r[4];
+      philox((uint32_t)q, dir, realisation, 3u, K, r);
+      uint32_t v = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v |= ((r[j] >> 31) ? 0xFFu : 0x01u) << (8 * j);
+      reinterpret_cast<uint32_t*>(J)[dir * nquads + q] = v;
+    }
+}
+
+__global__ void k_zero(int64_t* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+static unsigned grid_for(uint64_t work, int threads, unsigned cap = 65536) {
+  uint64_t g = (work + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_init_spins(const Lat& lat, hipStream_t stream) {
+  const uint64_t nq = lat.N / 4;
+  hipLaunchKernelGGL(k_init_spins, dim3(grid_for(nq, 256)), dim3(256), 0, stream, lat.spins, nq,
+                     lat.keys, lat.replica);
+  return hipGetLastError();
+}
+
+hipError_t launch_couplings(int8_t* J, uint32_t L, uint32_t d, uint64_t N, uint64_t cseed,
+                            uint32_t realisation, hipStream_t stream) {
+  (void)L;
+  const uint64_t nq = N / 4;
+  hipLaunchKernelGGL(k_couplings, dim3(grid_for(nq, 256)), dim3(256), 0, stream, J, nq, d,
+                     make_round_keys(cseed), realisation);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(n, 256, 1024)), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+// ================================================================ geometry
+
+// (v - back) mod L for 0 <= v < L + 2L and back <= L: the coordinate `back`
+// sites before v, wrapped periodically.
+__device__ __forceinline__ uint32_t wrap_row(uint32_t v, uint32_t back, uint32_t L) {
+  uint32_t w = v + L - back;  // in [0, 3L)
+  if (w >= L) w -= L;
+  if (w >= L) w -= L;
+  return w;
+}
+
+// Coordinates and wrapped neighbours of site s (generic paths).
+struct Site {
+  uint32_t x, y, z;
+};
+
+__device__ __forceinline__ Site site_coords(uint64_t s, uint32_t L, uint32_t d) {
+  Site c;
+  c.x = (uint32_t)(s % L);
+  const uint64_t q = s / L;
+  c.y = (uint32_t)(q % L);
+  c.z = (d == 3) ? (uint32_t)(q / L) : 0u;
+  return c;
+}
+
+// Neighbour of s one step along +dir / -dir; coordinate cd along dir,
+// stride st = L^dir.
+__device__ __forceinline__ uint64_t nb_plus(uint64_t s, uint32_t cd, uint32_t L, uint64_t st) {
+  return (cd + 1 == L) ? s - (uint64_t)(L - 1) * st : s + st;
+}
+__device__ __forceinline__ uint64_t nb_minus(uint64_t s, uint32_t cd, uint32_t L, uint64_t st) {
+  return (cd == 0) ? s + (uint64_t)(L - 1) * st : s - st;
+}
+
+// k = s_i * h_i for site s in spin array sp (LDS or global).
+__device__ __forceinline__ int local_k(const int8_t* sp, const int8_t* __restrict__ J, uint64_t s,
+                                       uint32_t L, uint32_t d, uint64_t N) {
+  const Site c = site_coords(s, L, d);
+  const uint32_t cd[3] = {c.x, c.y, c.z};
+  int h = 0;
+  uint64_t st = 1;
+  for (uint32_t dir = 0; dir < d; ++dir) {
+    const uint64_t up = nb_plus(s, cd[dir], L, st);
+    const uint64_t dn = nb_minus(s, cd[dir], L, st);
+    const int jf = J ? (int)J[dir * N + s] : 1;
+    const int jb = J ? (int)J[dir * N + dn] : 1;
+    h += jf * (int)sp[up] + jb * (int)sp[dn];
+    st *= L;
+  }
+  return (int)sp[s] * h;
+}
+
+// One 8-site group g in colour `colour` of sweep t: every active site of the
+// group is decided with its own Philox word and flipped in place.
+__device__ __forceinline__ void generic_group(int8_t* sp, const int8_t* __restrict__ J,
+                                              uint32_t L, uint32_t d, uint64_t N, uint64_t g,
+                                              uint32_t t, uint32_t colour, uint32_t replica,
+                                              const RoundKeys& K, const uint64_t* T) {
+  uint32_t r[4];
+  philox((uint32_t)g, t, replica, colour, K, r);
+  const int z = 2 * (int)d;
+  for (int j = 0; j < 8; ++j) {
+    const uint64_t s = g * 8 + j;
+    if (s >= N) break;
+    const Site c = site_coords(s, L, d);
+    if (((c.x + c.y + c.z) & 1u) != colour) continue;
+    const int k = local_k(sp, J, s, L, d, N);
+    if ((uint64_t)r[(s >> 1) & 3] < T[(k + z) / 2]) sp[s] = (int8_t)(-sp[s]);
+  }
+}
+
+// ============================================================ measurement
+
+// E and M of a lattice: per site (generic) when L % 4 != 0, per 4-site dword
+// otherwise; each workgroup adds its partial sums into *E, *M.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_measure_sites(const int8_t* __restrict__ sp,
+                                                      const int8_t* __restrict__ J, uint32_t L,
+                                                      uint32_t d, uint64_t N, int64_t* E,
+                                                      int64_t* M) {
+  __shared__ int64_t red[NT / 64];
+  int64_t e = 0, m = 0;
+  for (uint64_t s = blockIdx.x * (uint64_t)NT + threadIdx.x; s < N; s += (uint64_t)gridDim.x * NT) {
+    const Site c = site_coords(s, L, d);
+    const uint32_t cd[3] = {c.x, c.y, c.z};
+    uint64_t st = 1;
+    const int si = sp[s];
+    m += si;
+    for (uint32_t dir = 0; dir < d; ++dir) {
+      const uint64_t up = nb_plus(s, cd[dir], L, st);
+      e -= (int64_t)(J ? J[dir * N + s] : 1) * si * sp[up];
+      st *= L;
+    }
+  }
+  const int64_t be = block_sum<NT>(e, red);
+  const int64_t bm = block_sum<NT>(m, red);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)E, (unsigned long long)be);
+    atomicAdd((unsigned long long*)M, (unsigned long long)bm);
+  }
+}
+
+// Dword version (L % 4 == 0): popcounts of sign bits.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_measure_quads(const uint32_t* __restrict__ sp,
+                                                      const uint32_t* __restrict__ J, uint32_t L,
+                                                      uint32_t d, uint64_t N, int64_t* E,
+                                                      int64_t* M) {
+  __shared__ int64_t red[NT / 64];
+  const uint32_t Lq = L / 4;
+  const uint64_t nq = N / 4;
+  const uint64_t Nq = nq;
+  const uint32_t msb = 0x80808080u;
+  int64_t unsat = 0, neg = 0;
+  for (uint64_t q = blockIdx.x * (uint64_t)NT + threadIdx.x; q < nq; q += (uint64_t)gridDim.x * NT) {
+    const uint32_t c = sp[q];
+    neg += __popc(c & msb);
+    const uint32_t xq = (uint32_t)(q % Lq);
+    const uint64_t row = q / Lq;
+    const uint64_t nxq = (xq + 1 == Lq) ? q - (Lq - 1) : q + 1;
+    const uint32_t R = __builtin_amdgcn_alignbyte(sp[nxq], c, 1);
+    uint32_t jx = J ? J[q] : 0u;
+    unsat += __popc((c ^ R ^ jx) & msb);
+    const uint32_t y = (uint32_t)(row % L);
+    const uint64_t yq = (y + 1 == L) ? q - (uint64_t)(L - 1) * Lq : q + Lq;
+    uint32_t jy = J ? J[Nq + q] : 0u;
+    unsat += __popc((c ^ sp[yq] ^ jy) & msb);
+    if (d == 3) {
+      const uint32_t z = (uint32_t)(row / L);
+      const uint64_t plane = (uint64_t)L * Lq;
+      const uint64_t zq = (z + 1 == L) ? q - (uint64_t)(L - 1) * plane : q + plane;
+      uint32_t jz = J ? J[2 * Nq + q] : 0u;
+      unsat += __popc((c ^ sp[zq] ^ jz) & msb);
+    }
+  }
+  // per dword: E part = sum_dir (-4 + 2 unsat_dir), M part = 4 - 2 neg
+  const int64_t bu = block_sum<NT>(unsat, red);
+  const int64_t bn = block_sum<NT>(neg, red);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)E, (unsigned long long)(2 * bu));
+    atomicAdd((unsigned long long*)M, (unsigned long long)(-2 * bn));
+  }
+}
+
+__global__ void k_add_const(int64_t* E, int64_t* M, int64_t e0, int64_t m0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *E += e0;
+    *M += m0;
+  }
+}
+
+hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t stream) {
+  constexpr int NT = 256;
+  if (lat.L % 4 == 0) {
+    const uint64_t nq = lat.N / 4;
+    hipLaunchKernelGGL(k_measure_quads<NT>, dim3(grid_for(nq, NT, 4096)), dim3(NT), 0, stream,
+                       (const uint32_t*)lat.spins, (const uint32_t*)lat.J, lat.L, lat.d, lat.N, E, M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // constants: E = -d N + 2 unsat, M = N - 2 neg
+    hipLaunchKernelGGL(k_add_const, dim3(1), dim3(64), 0, stream, E, M,
+                       -(int64_t)lat.d * (int64_t)lat.N, (int64_t)lat.N);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_measure_sites<NT>, dim3(grid_for(lat.N, NT, 4096)), dim3(NT), 0, stream,
+                     (const int8_t*)lat.spins, lat.J, lat.L, lat.d, lat.N, E, M);
+  return hipGetLastError();
+}
+
+// ========================================================= generic phase
+
+__global__ __launch_bounds__(256) void k_generic_phase(Lat lat, uint32_t t, uint32_t colour,
+                                                       Accept acc) {
+  __shared__ uint64_t T[8];
+  if (threadIdx.x < 8) T[threadIdx.x] = acc.T[threadIdx.x];
+  __syncthreads();
+  const uint64_t ngroups = (lat.N + 7) / 8;
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ngroups;
+       g += (uint64_t)gridDim.x * blockDim.x)
+    generic_group(lat.spins, lat.J, lat.L, lat.d, lat.N, g, t, colour, lat.replica, lat.keys, T);
+}
+
+hipError_t launch_generic_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
+                                hipStream_t stream) {
+  const uint64_t ngroups = (lat.N + 7) / 8;
+  hipLaunchKernelGGL(k_generic_phase, dim3(grid_for(ngroups, 256)), dim3(256), 0, stream, lat, t,
+                     colour, acc);
+  return hipGetLastError();
+}
+
+// ============================================================ resident
+
+// One workgroup holds the whole lattice in LDS and runs n sweeps; records
+// (E, M) after every every-th sweep into E[i], M[i].
+__global__ void k_resident(Lat lat, uint32_t t0, int n, Accept acc, int every, int64_t* E,
+                           int64_t* M) {
+  extern __shared__ __align__(16) int8_t lds[];
+  __shared__ uint64_t T[8];
+  __shared__ int64_t red[32];
+  const int NT = blockDim.x;
+  if (threadIdx.x < 8) T[threadIdx.x] = acc.T[threadIdx.x];
+  const uint64_t N = lat.N;
+  for (uint64_t q = threadIdx.x; q < N / 4; q += NT)
+    reinterpret_cast<uint32_t*>(lds)[q] = reinterpret_cast<const uint32_t*>(lat.spins)[q];
+  __syncthreads();
+  const uint64_t ngroups = (N + 7) / 8;
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint32_t t = t0 + (uint32_t)i;
+    for (uint32_t colour = 0; colour < 2; ++colour) {
+      for (uint64_t g = threadIdx.x; g < ngroups; g += NT)
+        generic_group(lds, lat.J, lat.L, lat.d, N, g, t, colour, lat.replica, lat.keys, T);
+      __syncthreads();
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      int64_t e = 0, m = 0;
+      for (uint64_t s = threadIdx.x; s < N; s += NT) {
+        const Site c = site_coords(s, lat.L, lat.d);
+        const uint32_t cd[3] = {c.x, c.y, c.z};
+        uint64_t st = 1;
+        const int si = lds[s];
+        m += si;
+        for (uint32_t dir = 0; dir < lat.d; ++dir) {
+          const uint64_t up = nb_plus(s, cd[dir], lat.L, st);
+          e -= (int64_t)(lat.J ? lat.J[dir * N + s] : 1) * si * lds[up];
+          st *= lat.L;
+        }
+      }
+      // block reduction for a runtime thread count (<= 1024)
+      e = wave_sum(e);
+      m = wave_sum(m);
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+      if (lane == 0) {
+        red[wid] = e;
+        red[16 + wid] = m;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t se = 0, sm = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+          se += red[w];
+          sm += red[16 + w];
+        }
+        E[rec] = se;
+        M[rec] = sm;
+      }
+      __syncthreads();
+      ++rec;
+    }
+  }
+  for (uint64_t q = threadIdx.x; q < N / 4; q += NT)
+    reinterpret_cast<uint32_t*>(lat.spins)[q] = reinterpret_cast<const uint32_t*>(lds)[q];
+}
+
+size_t resident_lds_bytes(const Lat& lat) { return (size_t)lat.N; }
+
+hipError_t launch_resident(const Lat& lat, uint32_t t0, int n, const Accept& acc, int every,
+                           int64_t* E, int64_t* M, int threads, hipStream_t stream) {
+  const size_t bytes = resident_lds_bytes(lat);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_resident,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (threads <= 0) threads = 512;
+  hipLaunchKernelGGL(k_resident, dim3(1), dim3(threads), bytes, stream, lat, t0, n, acc, every, E,
+                     M);
+  return hipGetLastError();
+}
+
+// =============================================================== tiled
+
+// Kernel arguments of the register-parallel phase kernels.
+struct PhaseArgs {
+  RoundKeys keys;
+  uint32_t bound[8];
+  uint32_t never4;  // 4 * never_level
+  uint32_t L;
+  uint32_t t;
+  uint32_t colour;
+  uint32_t replica;
+};
+
+static PhaseArgs phase_args(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc) {
+  PhaseArgs a;
+  a.keys = lat.keys;
+  for (int i = 0; i < 8; ++i) a.bound[i] = acc.bound[i];
+  a.never4 = 4u * acc.never_level;
+  a.L = lat.L;
+  a.t = t;
+  a.colour = colour;
+  a.replica = lat.replica;
+  return a;
+}
+
+// 2D colour phase.  LDS row (TW+32 bytes): byte q <-> x = x0 - 16 + q, so the
+// tile occupies bytes [16, 16+TW), its halo dwords [12,16) and [16+TW, 20+TW).
+// LDS row r <-> y = y0 - 1 + r, r in [0, TH+2).
+template <int TW, int TH, int NT, bool NEVER>
+__global__ __launch_bounds__(NT) void k_tiled2d(int8_t* __restrict__ spins, PhaseArgs a) {
+  constexpr int RB = TW + 32;
+  constexpr int GPR = TW / 8;
+  __shared__ __align__(16) int8_t tile[(TH + 2) * RB];
+  __shared__ uint32_t bound[8];
+  if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
+  const uint32_t L = a.L;
+  const uint32_t x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  // tile interior, 16 bytes per load
+  for (int i = threadIdx.x; i < (TH + 2) * (TW / 16); i += NT) {
+    const int r = i / (TW / 16), q = i - r * (TW / 16);
+    const uint32_t y = wrap_row(y0 + r, 1u, L);
+    const uint4 v = *reinterpret_cast<const uint4*>(spins + (uint64_t)y * L + x0 + 16 * q);
+    *reinterpret_cast<uint4*>(tile + r * RB + 16 + 16 * q) = v;
+  }
+  // halo dwords left and right
+  for (int i = threadIdx.x; i < 2 * (TH + 2); i += NT) {
+    const int r = i >> 1, side = i & 1;
+    const uint32_t y = wrap_row(y0 + r, 1u, L);
+    const uint32_t x = side ? ((x0 + TW == L) ? 0u : x0 + TW) : ((x0 == 0) ? L - 4 : x0 - 4);
+    *reinterpret_cast<uint32_t*>(tile + r * RB + (side ? 16 + TW : 12)) =
+        *reinterpret_cast<const uint32_t*>(spins + (uint64_t)y * L + x);
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < GPR * TH; u += NT) {
+    const int r = u / GPR + 1, g = u - (r - 1) * GPR;
+    const int8_t* row = tile + r * RB + 16 + 8 * g;
+    const uint2 c = *reinterpret_cast<const uint2*>(row);
+    const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+    const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+    const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+    const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+    const uint32_t y = y0 + r - 1, x = x0 + 8 * g;
+    const uint64_t s = (uint64_t)y * L + x;
+    uint32_t rnd[4];
+    philox((uint32_t)(s >> 3), a.t, a.replica, a.colour, a.keys, rnd);
+    const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+    uint32_t S0, S1;
+    unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+    uint32_t c0 = c.x, c1 = c.y;
+    apply_group<NEVER>(c0, c1, S0, S1, (a.colour + y) & 1u, rnd, bound, a.never4);
+    *reinterpret_cast<uint2*>(spins + s) = make_uint2(c0, c1);
+  }
+}
+
+// 3D colour phase.  LDS rows indexed (zz, yy), zz in [0, TZ+2) <-> z = z0-1+zz,
+// yy in [0, TH+2) <-> y = y0-1+yy; row layout as in 2D.
+template <int TW, int TH, int TZ, int NT, bool NEVER>
+__global__ __launch_bounds__(NT) void k_tiled3d(int8_t* __restrict__ spins, PhaseArgs a) {
+  constexpr int RB = TW + 32;
+  constexpr int GPR = TW / 8;
+  constexpr int RY = TH + 2;
+  __shared__ __align__(16) int8_t tile[(TZ + 2) * RY * RB];
+  __shared__ uint32_t bound[8];
+  if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
+  const uint32_t L = a.L;
+  const uint64_t plane = (uint64_t)L * L;
+  const uint32_t x0 = blockIdx.x * TW, y0 = blockIdx.y * TH, z0 = blockIdx.z * TZ;
+  for (int i = threadIdx.x; i < (TZ + 2) * RY * (TW / 16); i += NT) {
+    const int rr = i / (TW / 16), q = i - rr * (TW / 16);
+    const int zz = rr / RY, yy = rr - zz * RY;
+    const uint32_t y = wrap_row(y0 + yy, 1u, L);
+    const uint32_t z = wrap_row(z0 + zz, 1u, L);
+    const uint4 v =
+        *reinterpret_cast<const uint4*>(spins + z * plane + (uint64_t)y * L + x0 + 16 * q);
+    *reinterpret_cast<uint4*>(tile + rr * RB + 16 + 16 * q) = v;
+  }
+  for (int i = threadIdx.x; i < 2 * (TZ + 2) * RY; i += NT) {
+    const int rr = i >> 1, side = i & 1;
+    const int zz = rr / RY, yy = rr - zz * RY;
+    const uint32_t y = wrap_row(y0 + yy, 1u, L);
+    const uint32_t z = wrap_row(z0 + zz, 1u, L);
+    const uint32_t x = side ? ((x0 + TW == L) ? 0u : x0 + TW) : ((x0 == 0) ? L - 4 : x0 - 4);
+    *reinterpret_cast<uint32_t*>(tile + rr * RB + (side ? 16 + TW : 12)) =
+        *reinterpret_cast<const uint32_t*>(spins + z * plane + (uint64_t)y * L + x);
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < GPR * TH * TZ; u += NT) {
+    const int rr0 = u / GPR, g = u - rr0 * GPR;
+    const int zi = rr0 / TH, yi = rr0 - zi * TH;  // interior coordinates
+    const int rr = (zi + 1) * RY + (yi + 1);
+    const int8_t* row = tile + rr * RB + 16 + 8 * g;
+    const uint2 c = *reinterpret_cast<const uint2*>(row);
+    const uint2 yu = *reinterpret_cast<const uint2*>(row - RB);
+    const uint2 yd = *reinterpret_cast<const uint2*>(row + RB);
+    const uint2 zu = *reinterpret_cast<const uint2*>(row - RY * RB);
+    const uint2 zd = *reinterpret_cast<const uint2*>(row + RY * RB);
+    const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+    const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+    const uint32_t y = y0 + yi, z = z0 + zi, x = x0 + 8 * g;
+    const uint64_t s = z * plane + (uint64_t)y * L + x;
+    uint32_t rnd[4];
+    philox((uint32_t)(s >> 3), a.t, a.replica, a.colour, a.keys, rnd);
+    const uint32_t o0[4] = {yu.x, yd.x, zu.x, zd.x}, o1[4] = {yu.y, yd.y, zu.y, zd.y};
+    uint32_t S0, S1;
+    unsat_ising<4>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+    uint32_t c0 = c.x, c1 = c.y;
+    apply_group<NEVER>(c0, c1, S0, S1, (a.colour + y + z) & 1u, rnd, bound, a.never4);
+    *reinterpret_cast<uint2*>(spins + s) = make_uint2(c0, c1);
+  }
+}
+
+// Supported tile shapes (compile-time instantiations).
+struct Tiled2DShape {
+  int tw, th, nt;
+};
+struct Tiled3DShape {
+  int tw, th, tz, nt;
+};
+
+bool tiled_supported(const Lat& lat, const Tile& tile) {
+  if (lat.J != nullptr) return false;
+  if (lat.L % 8 != 0) return false;
+  if (lat.L % tile.x != 0 || lat.L % tile.y != 0) return false;
+  if (lat.d == 3 && lat.L % tile.z != 0) return false;
+  if (lat.d == 2) {
+    return (tile.x == 256 && tile.y == 32 && tile.threads == 256) ||
+           (tile.x == 128 && tile.y == 16 && tile.threads == 256) ||
+           (tile.x == 512 && tile.y == 32 && tile.threads == 512) ||
+           (tile.x == 64 && tile.y == 8 && tile.threads == 64) ||
+           (tile.x == 16 && tile.y == 8 && tile.threads == 64);
+  }
+  return (tile.x == 64 && tile.y == 8 && tile.z == 8 && tile.threads == 256) ||
+         (tile.x == 32 && tile.y == 8 && tile.z == 4 && tile.threads == 128) ||
+         (tile.x == 128 && tile.y == 8 && tile.z == 4 && tile.threads == 256) ||
+         (tile.x == 16 && tile.y == 4 && tile.z == 4 && tile.threads == 64);
+}
+
+template <int TW, int TH, int NT>
+static hipError_t go2d(const Lat& lat, const PhaseArgs& a, bool never, hipStream_t stream) {
+  dim3 grid(lat.L / TW, lat.L / TH);
+  if (never)
+    hipLaunchKernelGGL((k_tiled2d<TW, TH, NT, true>), grid, dim3(NT), 0, stream, lat.spins, a);
+  else
+    hipLaunchKernelGGL((k_tiled2d<TW, TH, NT, false>), grid, dim3(NT), 0, stream, lat.spins, a);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int TZ, int NT>
+static hipError_t go3d(const Lat& lat, const PhaseArgs& a, bool never, hipStream_t stream) {
+  dim3 grid(lat.L / TW, lat.L / TH, lat.L / TZ);
+  if (never)
+    hipLaunchKernelGGL((k_tiled3d<TW, TH, TZ, NT, true>), grid, dim3(NT), 0, stream, lat.spins, a);
+  else
+    hipLaunchKernelGGL((k_tiled3d<TW, TH, TZ, NT, false>), grid, dim3(NT), 0, stream, lat.spins, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiled_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
+                              const Tile& tile, hipStream_t stream) {
+  if (!tiled_supported(lat, tile)) return hipErrorInvalidValue;
+  const PhaseArgs a = phase_args(lat, t, colour, acc);
+  const bool never = acc.never_level > 0;
+  if (lat.d == 2) {
+    if (tile.x == 256 && tile.y == 32) return go2d<256, 32, 256>(lat, a, never, stream);
+    if (tile.x == 128 && tile.y == 16) return go2d<128, 16, 256>(lat, a, never, stream);
+    if (tile.x == 512 && tile.y == 32) return go2d<512, 32, 512>(lat, a, never, stream);
+    if (tile.x == 64 && tile.y == 8) return go2d<64, 8, 64>(lat, a, never, stream);
+    return go2d<16, 8, 64>(lat, a, never, stream);
+  }
+  if (tile.x == 64 && tile.y == 8 && tile.z == 8) return go3d<64, 8, 8, 256>(lat, a, never, stream);
+  if (tile.x == 32 && tile.y == 8 && tile.z == 4) return go3d<32, 8, 4, 128>(lat, a, never, stream);
+  if (tile.x == 128 && tile.y == 8 && tile.z == 4) return go3d<128, 8, 4, 256>(lat, a, never, stream);
+  return go3d<16, 4, 4, 64>(lat, a, never, stream);
+}
+
+// ================================================================ fused
+
+// 2D Ising, one whole sweep.  LDS row (TW+32 bytes): byte q <-> x = x0-16+q;
+// LDS row r in [0, TH+4) <-> y = y0-2+r.  LDS group j (bytes [8j, 8j+8)):
+// tile groups j in [2, TW/8+2), halo groups j = 1 and j = TW/8+2.
+template <int TW, int TH, int NT, bool NEVER>
+__global__ __launch_bounds__(NT) void k_fused2d(const int8_t* __restrict__ src,
+                                               int8_t* __restrict__ dst, PhaseArgs a) {
+  constexpr int RB = TW + 32;
+  constexpr int GPR = TW / 8;
+  constexpr int RT = TH + 4;
+  __shared__ __align__(16) int8_t tile[RT * RB];
+  __shared__ uint32_t bound[8];
+  if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
+  const uint32_t L = a.L;
+  const uint32_t x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  // rows: every 16-byte chunk of [x0-16, x0+TW+16)
+  constexpr int CPR = TW / 16 + 2;
+  for (int i = threadIdx.x; i < RT * CPR; i += NT) {
+    const int r = i / CPR, q = i - r * CPR;
+    const uint32_t y = wrap_row(y0 + r, 2u, L);
+    const uint32_t x = wrap_row(x0 + 16 * q, 16u, L);
+    *reinterpret_cast<uint4*>(tile + r * RB + 16 * q) =
+        *reinterpret_cast<const uint4*>(src + (uint64_t)y * L + x);
+  }
+  __syncthreads();
+  // colour 0 on the tile rows plus the ring: units are (row r, LDS group j)
+  //   rows 2..TH+1: groups 1..GPR+2 ; rows 1 and TH+2: groups 2..GPR+1
+  {
+    constexpr int WIDE = GPR + 2;
+    constexpr int NU = TH * WIDE + 2 * GPR;
+    for (int u = threadIdx.x; u < NU; u += NT) {
+      int r, j;
+      if (u < TH * WIDE) {
+        r = u / WIDE + 2;
+        j = u - (r - 2) * WIDE + 1;
+      } else {
+        const int v = u - TH * WIDE;
+        r = (v < GPR) ? 1 : TH + 2;
+        j = (v < GPR ? v : v - GPR) + 2;
+      }
+      int8_t* row = tile + r * RB + 8 * j;
+      const uint2 c = *reinterpret_cast<const uint2*>(row);
+      const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+      const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+      const uint32_t y = wrap_row(y0 + r, 2u, L);
+      const uint32_t x = wrap_row(x0 + 8 * j, 16u, L);
+      const uint64_t s = (uint64_t)y * L + x;
+      uint32_t rnd[4];
+      philox((uint32_t)(s >> 3), a.t, a.replica, 0u, a.keys, rnd);
+      const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = c.x, c1 = c.y;
+      apply_group<NEVER>(c0, c1, S0, S1, y & 1u, rnd, bound, a.never4);
+      *reinterpret_cast<uint2*>(row) = make_uint2(c0, c1);
+    }
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < GPR * TH; u += NT) {
+    const int r = u / GPR + 2, g = u - (r - 2) * GPR;
+    const int8_t* row = tile + r * RB + 16 + 8 * g;
+    const uint2 c = *reinterpret_cast<const uint2*>(row);
+    const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+    const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+    const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+    const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+    const uint32_t y = y0 + r - 2, x = x0 + 8 * g;
+    const uint64_t s = (uint64_t)y * L + x;
+    uint32_t rnd[4];
+    philox((uint32_t)(s >> 3), a.t, a.replica, 1u, a.keys, rnd);
+    const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+    uint32_t S0, S1;
+    unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+    uint32_t c0 = c.x, c1 = c.y;
+    apply_group<NEVER>(c0, c1, S0, S1, (1u + y) & 1u, rnd, bound, a.never4);
+    *reinterpret_cast<uint2*>(dst + s) = make_uint2(c0, c1);
+  }
+}
+
+bool fused_supported(const Lat& lat, const Tile& tile) {
+  if (lat.J != nullptr || lat.d != 2) return false;
+  if (lat.L % 16 != 0 || lat.L < 32) return false;
+  if (lat.L % tile.x != 0 || lat.L % tile.y != 0) return false;
+  return (tile.x == 256 && tile.y == 32 && tile.threads == 256) ||
+         (tile.x == 512 && tile.y == 32 && tile.threads == 512) ||
+         (tile.x == 128 && tile.y == 16 && tile.threads == 256) ||
+         (tile.x == 16 && tile.y == 8 && tile.threads == 64);
+}
+
+template <int TW, int TH, int NT>
+static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
+                          bool never, hipStream_t stream) {
+  dim3 grid(lat.L / TW, lat.L / TH);
+  if (never)
+    hipLaunchKernelGGL((k_fused2d<TW, TH, NT, true>), grid, dim3(NT), 0, stream, src, dst, a);
+  else
+    hipLaunchKernelGGL((k_fused2d<TW, TH, NT, false>), grid, dim3(NT), 0, stream, src, dst, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
+                              const Accept& acc, const Tile& tile, hipStream_t stream) {
+  if (!fused_supported(lat, tile)) return hipErrorInvalidValue;
+  const PhaseArgs a = phase_args(lat, t, 0u, acc);
+  const bool never = acc.never_level > 0;
+  if (tile.x == 256) return gofused<256, 32, 256>(lat, src, dst, a, never, stream);
+  if (tile.x == 512) return gofused<512, 32, 512>(lat, src, dst, a, never, stream);
+  if (tile.x == 128) return gofused<128, 16, 256>(lat, src, dst, a, never, stream);
+  return gofused<16, 8, 64>(lat, src, dst, a, never, stream);
+}
+
+}  // namespace spin

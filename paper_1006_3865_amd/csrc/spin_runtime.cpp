@@ -1,0 +1,526 @@
+// spin_runtime.cpp -- host side of the C ABI declared in include/spin.h:
+// argument checks, device memory, the FP64 threshold table, kernel choice
+// and the per-sweep launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spin.h"
+#include "spin_internal.h"
+
+namespace spin {
+
+RoundKeys make_round_keys(uint64_t seed) {
+  RoundKeys K;
+  uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  for (int i = 0; i < 10; ++i) {
+    K.k0[i] = k0;
+    K.k1[i] = k1;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return K;
+}
+
+// Eq. 2 of the paper, exact in integers: accept iff r < T with
+// T = floor(2^32 exp(-beta dE)), dE = 2k, evaluated in IEEE double.
+Accept make_accept(double beta, int d) {
+  Accept a;
+  std::memset(&a, 0, sizeof(a));
+  const int z = 2 * d;
+  for (int k = -z; k <= z; k += 2) {
+    uint64_t T;
+    if (k <= 0) {
+      T = (uint64_t)1 << 32;
+    } else {
+      const double dE = (double)(2 * k);
+      T = (uint64_t)std::floor(std::ldexp(std::exp(-(beta * dE)), 32));
+    }
+    a.T[(k + z) / 2] = T;
+  }
+  // u = unsatisfied bonds, k = z - 2u, table index z - u
+  a.never_level = 0;
+  for (int u = 0; u <= z; ++u) {
+    const uint64_t T = a.T[z - u];
+    a.bound[u] = (T == 0) ? 0u : (uint32_t)(T - 1);
+    if (T == 0) a.never_level = (uint32_t)(u + 1);
+  }
+  return a;
+}
+
+}  // namespace spin
+
+using namespace spin;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_error;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(SPIN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------- allocator
+
+static void* (*g_alloc)(size_t, void*) = nullptr;
+static void (*g_release)(void*, void*) = nullptr;
+static void* g_ctx = nullptr;
+
+struct Allocator {
+  void* (*alloc)(size_t, void*);
+  void (*release)(void*, void*);
+  void* ctx;
+
+  void* get(size_t bytes) const {
+    if (bytes == 0) bytes = 16;
+    if (alloc) return alloc(bytes, ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void put(void* p) const {
+    if (!p) return;
+    if (release)
+      release(p, ctx);
+    else
+      (void)hipFree(p);
+  }
+};
+
+// ------------------------------------------------------------------ handle
+
+struct spin_lattice {
+  int model;
+  int L;
+  int d;
+  uint64_t N;
+  int8_t* buf[2];
+  int cur;
+  int8_t* J;
+  int64_t* em;  // 2 int64 for spin_measure
+  uint64_t seed;
+  uint32_t replica;
+  uint64_t t;
+  hipStream_t stream;
+  int kernel;  // requested family
+  Tile tile;   // requested shape (0 = default)
+  Allocator mem;
+};
+
+static const uint64_t kMaxSweepIndex = (uint64_t)1 << 32;
+static const uint64_t kResidentMaxSites = 150 * 1024;   // LDS budget of the resident kernel
+static const uint64_t kResidentAutoSites = 32768;       // auto choice for a lone lattice
+
+static Lat lat_of(const spin_lattice* h) {
+  Lat l;
+  l.spins = h->buf[h->cur];
+  l.J = h->J;
+  l.L = (uint32_t)h->L;
+  l.d = (uint32_t)h->d;
+  l.N = h->N;
+  l.replica = h->replica;
+  l.keys = make_round_keys(h->seed);
+  return l;
+}
+
+static int check_shape(int model, int L, int d) {
+  if (model != SPIN_ISING && model != SPIN_EA_PMJ) return fail(SPIN_EINVAL, "model must be 0 (Ising) or 1 (EA +-J)");
+  if (d != 2 && d != 3) return fail(SPIN_EINVAL, "d must be 2 or 3 (got %d)", d);
+  if (L < 4 || (L % 2) != 0) return fail(SPIN_EINVAL, "L must be even and >= 4 (got %d)", L);
+  uint64_t N = 1;
+  for (int i = 0; i < d; ++i) N *= (uint64_t)L;
+  if (N / 8 >= ((uint64_t)1 << 32)) return fail(SPIN_EINVAL, "L^d/8 must be < 2^32");
+  return SPIN_OK;
+}
+
+static void destroy(spin_lattice* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  h->mem.put(h->buf[0]);
+  h->mem.put(h->buf[1]);
+  h->mem.put(h->J);
+  h->mem.put(h->em);
+  delete h;
+}
+
+static Tile default_tile(const spin_lattice* h, int kernel) {
+  Tile t = h->tile;
+  if (t.x && t.y && t.threads && (h->d == 2 || t.z)) return t;
+  const int L = h->L;
+  if (kernel == SPIN_KERNEL_FUSED) {
+    if (L % 256 == 0) return Tile{256, 32, 0, 256};
+    if (L % 128 == 0) return Tile{128, 16, 0, 256};
+    return Tile{16, 8, 0, 64};
+  }
+  if (kernel == SPIN_KERNEL_TILED) {
+    if (h->d == 2) {
+      if (L % 256 == 0) return Tile{256, 32, 0, 256};
+      if (L % 128 == 0) return Tile{128, 16, 0, 256};
+      if (L % 64 == 0) return Tile{64, 8, 0, 64};
+      return Tile{16, 8, 0, 64};
+    }
+    if (L % 64 == 0) return Tile{64, 8, 8, 256};
+    if (L % 32 == 0) return Tile{32, 8, 4, 128};
+    return Tile{16, 4, 4, 64};
+  }
+  if (kernel == SPIN_KERNEL_RESIDENT) return Tile{0, 0, 0, t.threads ? t.threads : 512};
+  return Tile{0, 0, 0, 256};
+}
+
+static bool family_ok(const spin_lattice* h, int kernel, const Tile& tile) {
+  const Lat l = lat_of(h);
+  switch (kernel) {
+    case SPIN_KERNEL_GENERIC: return true;
+    case SPIN_KERNEL_RESIDENT:
+      return h->N <= kResidentMaxSites && tile.threads >= 64 && tile.threads <= 1024 &&
+             tile.threads % 64 == 0;
+    case SPIN_KERNEL_TILED: return tiled_supported(l, tile);
+    case SPIN_KERNEL_FUSED: return fused_supported(l, tile);
+    default: return false;
+  }
+}
+
+// Family and tile that the next sweep uses.
+static int resolve(const spin_lattice* h, Tile* tile) {
+  if (h->kernel != SPIN_KERNEL_AUTO) {
+    *tile = default_tile(h, h->kernel);
+    return h->kernel;
+  }
+  if (h->N <= kResidentAutoSites) {
+    *tile = default_tile(h, SPIN_KERNEL_RESIDENT);
+    return SPIN_KERNEL_RESIDENT;
+  }
+  const int order[2] = {SPIN_KERNEL_FUSED, SPIN_KERNEL_TILED};
+  for (int k : order) {
+    Tile t = default_tile(h, k);
+    if (family_ok(h, k, t)) {
+      *tile = t;
+      return k;
+    }
+  }
+  *tile = default_tile(h, SPIN_KERNEL_GENERIC);
+  return SPIN_KERNEL_GENERIC;
+}
+
+static int check_beta(double beta) {
+  if (std::isnan(beta) || beta < 0) return fail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
+  return SPIN_OK;
+}
+
+// Enqueue n sweeps; if every > 0 write records into device arrays dE, dM.
+static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (n < 0) return fail(SPIN_EINVAL, "n must be >= 0");
+  if (int rc = check_beta(beta)) return rc;
+  if (h->t + (uint64_t)n > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index would exceed 2^32");
+  if (n == 0) return SPIN_OK;
+  const Accept acc = make_accept(beta, h->d);
+  Tile tile;
+  const int kernel = resolve(h, &tile);
+  hipError_t e = hipSuccess;
+  const int nrec = every > 0 ? n / every : 0;
+  if (nrec > 0) {
+    if ((e = launch_zero(dE, (uint64_t)nrec, h->stream)) != hipSuccess) return hip_fail(e, "zero");
+    if ((e = launch_zero(dM, (uint64_t)nrec, h->stream)) != hipSuccess) return hip_fail(e, "zero");
+  }
+  if (kernel == SPIN_KERNEL_RESIDENT) {
+    const Lat l = lat_of(h);
+    e = launch_resident(l, (uint32_t)h->t, n, acc, every, dE, dM, tile.threads, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
+    h->t += (uint64_t)n;
+    return SPIN_OK;
+  }
+  if (kernel == SPIN_KERNEL_FUSED && !h->buf[1]) {
+    h->buf[1] = (int8_t*)h->mem.get(h->N);
+    if (!h->buf[1]) return fail(SPIN_ENOMEM, "allocation of the second spin buffer failed");
+  }
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint32_t t = (uint32_t)(h->t + (uint64_t)i);
+    Lat l = lat_of(h);
+    if (kernel == SPIN_KERNEL_FUSED) {
+      e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
+      h->cur = 1 - h->cur;
+    } else {
+      for (uint32_t c = 0; c < 2; ++c) {
+        e = (kernel == SPIN_KERNEL_TILED) ? launch_tiled_phase(l, t, c, acc, tile, h->stream)
+                                          : launch_generic_phase(l, t, c, acc, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "colour phase launch");
+      }
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      e = launch_measure(lat_of(h), dE + rec, dM + rec, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "measure launch");
+      ++rec;
+    }
+  }
+  h->t += (uint64_t)n;
+  return SPIN_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* spin_last_error(void) { return g_error.c_str(); }
+
+const char* spin_version(void) { return "spin-gfx950 0.1"; }
+
+void spin_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+  g_alloc = alloc;
+  g_release = release;
+  g_ctx = ctx;
+}
+
+int spin_threshold_table(double beta, int d, uint64_t* T) {
+  if (d != 2 && d != 3) return fail(SPIN_EINVAL, "d must be 2 or 3");
+  if (!T) return fail(SPIN_EINVAL, "NULL output");
+  if (int rc = check_beta(beta)) return rc;
+  const Accept a = make_accept(beta, d);
+  for (int i = 0; i <= 2 * d; ++i) T[i] = a.T[i];
+  return SPIN_OK;
+}
+
+spin_lattice* spin_create_config(const spin_config* cfg) {
+  if (!cfg) {
+    fail(SPIN_EINVAL, "NULL config");
+    return nullptr;
+  }
+  if (check_shape(cfg->model, cfg->L, cfg->d) != SPIN_OK) return nullptr;
+  uint64_t N = 1;
+  for (int i = 0; i < cfg->d; ++i) N *= (uint64_t)cfg->L;
+  if (cfg->model == SPIN_ISING && cfg->couplings) {
+    fail(SPIN_EINVAL, "couplings must be NULL for the Ising model");
+    return nullptr;
+  }
+  if (cfg->model == SPIN_EA_PMJ && cfg->couplings) {
+    for (uint64_t i = 0; i < (uint64_t)cfg->d * N; ++i)
+      if (cfg->couplings[i] != 1 && cfg->couplings[i] != -1) {
+        fail(SPIN_EINVAL, "coupling %llu is %d, must be +-1", (unsigned long long)i, (int)cfg->couplings[i]);
+        return nullptr;
+      }
+  }
+  spin_lattice* h = new spin_lattice();
+  h->model = cfg->model;
+  h->L = cfg->L;
+  h->d = cfg->d;
+  h->N = N;
+  h->buf[0] = h->buf[1] = nullptr;
+  h->cur = 0;
+  h->J = nullptr;
+  h->em = nullptr;
+  h->seed = cfg->seed;
+  h->replica = cfg->replica;
+  h->t = 0;
+  h->stream = (hipStream_t)cfg->stream;
+  h->kernel = SPIN_KERNEL_AUTO;
+  h->tile = Tile{0, 0, 0, 0};
+  h->mem = Allocator{g_alloc, g_release, g_ctx};
+  h->buf[0] = (int8_t*)h->mem.get(N);
+  h->em = (int64_t*)h->mem.get(2 * sizeof(int64_t));
+  if (!h->buf[0] || !h->em) {
+    fail(SPIN_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)N);
+    destroy(h);
+    return nullptr;
+  }
+  hipError_t e;
+  if (h->model == SPIN_EA_PMJ) {
+    h->J = (int8_t*)h->mem.get((size_t)cfg->d * N);
+    if (!h->J) {
+      fail(SPIN_ENOMEM, "device allocation of couplings failed");
+      destroy(h);
+      return nullptr;
+    }
+    if (cfg->couplings) {
+      e = hipMemcpyAsync(h->J, cfg->couplings, (size_t)cfg->d * N, hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    } else {
+      e = launch_couplings(h->J, (uint32_t)h->L, (uint32_t)h->d, N, cfg->coupling_seed,
+                           cfg->realisation, h->stream);
+    }
+    if (e != hipSuccess) {
+      hip_fail(e, "couplings");
+      destroy(h);
+      return nullptr;
+    }
+  }
+  e = launch_init_spins(lat_of(h), h->stream);
+  if (e != hipSuccess) {
+    hip_fail(e, "hot start");
+    destroy(h);
+    return nullptr;
+  }
+  return h;
+}
+
+spin_lattice* spin_create(int model, int L, int d, const int8_t* couplings, uint64_t seed) {
+  spin_config c;
+  std::memset(&c, 0, sizeof(c));
+  c.model = model;
+  c.L = L;
+  c.d = d;
+  c.couplings = couplings;
+  c.seed = seed;
+  if (model == SPIN_EA_PMJ && !couplings) {
+    fail(SPIN_EINVAL, "EA model needs couplings (use spin_create_config to generate them)");
+    return nullptr;
+  }
+  return spin_create_config(&c);
+}
+
+void spin_free(spin_lattice* h) { destroy(h); }
+
+int spin_sweep(spin_lattice* h, int n, double beta) { return run_sweeps(h, n, beta, 0, nullptr, nullptr); }
+
+int spin_sweep_record_device(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M) {
+  if (every < 1) return fail(SPIN_EINVAL, "every must be >= 1");
+  if (n / every > 0 && (!E || !M)) return fail(SPIN_EINVAL, "NULL record arrays");
+  return run_sweeps(h, n, beta, every, E, M);
+}
+
+int spin_sweep_record(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (every < 1) return fail(SPIN_EINVAL, "every must be >= 1");
+  if (n < 0) return fail(SPIN_EINVAL, "n must be >= 0");
+  const int nrec = n / every;
+  if (nrec > 0 && (!E || !M)) return fail(SPIN_EINVAL, "NULL record arrays");
+  int64_t* d = nullptr;
+  if (nrec > 0) {
+    d = (int64_t*)h->mem.get(2 * sizeof(int64_t) * (size_t)nrec);
+    if (!d) return fail(SPIN_ENOMEM, "record buffer allocation failed");
+  }
+  int rc = run_sweeps(h, n, beta, every, d, d ? d + nrec : nullptr);
+  if (rc == SPIN_OK && nrec > 0) {
+    hipError_t e = hipMemcpyAsync(E, d, sizeof(int64_t) * nrec, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(M, d + nrec, sizeof(int64_t) * nrec, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "record copy");
+  } else if (rc == SPIN_OK) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "synchronize");
+  }
+  if (d) {
+    (void)hipStreamSynchronize(h->stream);
+    h->mem.put(d);
+  }
+  return rc;
+}
+
+int spin_measure(spin_lattice* h, int64_t* E, int64_t* M) {
+  if (!h || !E || !M) return fail(SPIN_EINVAL, "NULL argument");
+  hipError_t e = launch_zero(h->em, 2, h->stream);
+  if (e == hipSuccess) e = launch_measure(lat_of(h), h->em, h->em + 1, h->stream);
+  int64_t v[2];
+  if (e == hipSuccess) e = hipMemcpyAsync(v, h->em, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "measure");
+  *E = v[0];
+  *M = v[1];
+  return SPIN_OK;
+}
+
+int spin_get_spins(const spin_lattice* h, int8_t* out, size_t n) {
+  if (!h || !out) return fail(SPIN_EINVAL, "NULL argument");
+  if (n != h->N) return fail(SPIN_EINVAL, "n must equal L^d = %llu", (unsigned long long)h->N);
+  hipError_t e = hipMemcpyAsync(out, h->buf[h->cur], n, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "get spins");
+  return SPIN_OK;
+}
+
+int spin_set_spins(spin_lattice* h, const int8_t* in, size_t n) {
+  if (!h || !in) return fail(SPIN_EINVAL, "NULL argument");
+  if (n != h->N) return fail(SPIN_EINVAL, "n must equal L^d = %llu", (unsigned long long)h->N);
+  for (size_t i = 0; i < n; ++i)
+    if (in[i] != 1 && in[i] != -1) return fail(SPIN_EINVAL, "spin %zu is %d, must be +-1", i, (int)in[i]);
+  hipError_t e = hipMemcpyAsync(h->buf[h->cur], in, n, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "set spins");
+  return SPIN_OK;
+}
+
+int spin_get_couplings(const spin_lattice* h, int8_t* out, size_t n) {
+  if (!h || !out) return fail(SPIN_EINVAL, "NULL argument");
+  if (!h->J) return fail(SPIN_ESTATE, "the Ising model has no couplings");
+  if (n != (size_t)h->d * h->N) return fail(SPIN_EINVAL, "n must equal d*L^d");
+  hipError_t e = hipMemcpyAsync(out, h->J, n, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "get couplings");
+  return SPIN_OK;
+}
+
+uint64_t spin_sweeps_done(const spin_lattice* h) { return h ? h->t : 0; }
+
+int spin_set_sweeps_done(spin_lattice* h, uint64_t t) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (t > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index must be <= 2^32");
+  h->t = t;
+  return SPIN_OK;
+}
+
+int spin_set_stream(spin_lattice* h, void* stream) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  h->stream = (hipStream_t)stream;
+  return SPIN_OK;
+}
+
+int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (kernel < SPIN_KERNEL_AUTO || kernel > SPIN_KERNEL_FUSED) return fail(SPIN_EINVAL, "unknown kernel family %d", kernel);
+  const int old_kernel = h->kernel;
+  const Tile old_tile = h->tile;
+  h->kernel = kernel;
+  h->tile = Tile{tile_x, tile_y, tile_z, threads};
+  if (kernel != SPIN_KERNEL_AUTO) {
+    const Tile t = default_tile(h, kernel);
+    if (!family_ok(h, kernel, t)) {
+      h->kernel = old_kernel;
+      h->tile = old_tile;
+      return fail(SPIN_EINVAL, "kernel family %d with tile (%d,%d,%d,%d) cannot run L=%d d=%d model=%d",
+                  kernel, t.x, t.y, t.z, t.threads, h->L, h->d, h->model);
+    }
+  }
+  return SPIN_OK;
+}
+
+int spin_get_kernel(const spin_lattice* h) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  Tile t;
+  return resolve(h, &t);
+}
+
+int spin_synchronize(spin_lattice* h) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  return SPIN_OK;
+}
+
+const int8_t* spin_device_spins(const spin_lattice* h) {
+  if (!h) {
+    fail(SPIN_EINVAL, "NULL handle");
+    return nullptr;
+  }
+  return h->buf[h->cur];
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+"""ctypes binding of libspin.so: the C ABI of include/spin.h under the same names.
+
+Argument marshalling only; every step of the path runs in the library's HIP
+kernels.  Loading fails loudly (``RuntimeError``) when the built library is
+missing: there is no CPU fallback.  PyTorch is used only for device memory
+(``use_torch_allocator``) and streams (``Lattice(..., stream=...)``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspin.so")
+
+SPIN_ISING, SPIN_EA_PMJ = 0, 1
+SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EDEVICE, SPIN_ESTATE = 0, -1, -2, -3, -4
+SPIN_KERNEL_AUTO, SPIN_KERNEL_GENERIC, SPIN_KERNEL_RESIDENT, SPIN_KERNEL_TILED, SPIN_KERNEL_FUSED = 0, 1, 2, 3, 4
+KERNEL_NAMES = {0: "auto", 1: "generic", 2: "resident", 3: "tiled", 4: "fused"}
+
+# Every symbol include/spin.h declares, with (restype, argtypes).
+_c = ctypes
+_P = _c.c_void_p
+_i8p = _c.POINTER(_c.c_int8)
+_i64p = _c.POINTER(_c.c_int64)
+_u64p = _c.POINTER(_c.c_uint64)
+ALLOC_FN = _c.CFUNCTYPE(_c.c_void_p, _c.c_size_t, _c.c_void_p)
+RELEASE_FN = _c.CFUNCTYPE(None, _c.c_void_p, _c.c_void_p)
+
+
+class spin_config(_c.Structure):
+    _fields_ = [("model", _c.c_int), ("L", _c.c_int), ("d", _c.c_int), ("couplings", _i8p),
+                ("coupling_seed", _c.c_uint64), ("realisation", _c.c_uint32), ("seed", _c.c_uint64),
+                ("replica", _c.c_uint32), ("stream", _c.c_void_p)]
+
+
+SIGNATURES = {
+    "spin_create": (_P, [_c.c_int, _c.c_int, _c.c_int, _i8p, _c.c_uint64]),
+    "spin_create_config": (_P, [_c.POINTER(spin_config)]),
+    "spin_free": (None, [_P]),
+    "spin_sweep": (_c.c_int, [_P, _c.c_int, _c.c_double]),
+    "spin_sweep_record": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _i64p, _i64p]),
+    "spin_sweep_record_device": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p]),
+    "spin_measure": (_c.c_int, [_P, _i64p, _i64p]),
+    "spin_get_spins": (_c.c_int, [_P, _i8p, _c.c_size_t]),
+    "spin_set_spins": (_c.c_int, [_P, _i8p, _c.c_size_t]),
+    "spin_get_couplings": (_c.c_int, [_P, _i8p, _c.c_size_t]),
+    "spin_sweeps_done": (_c.c_uint64, [_P]),
+    "spin_set_sweeps_done": (_c.c_int, [_P, _c.c_uint64]),
+    "spin_set_stream": (_c.c_int, [_P, _c.c_void_p]),
+    "spin_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "spin_get_kernel": (_c.c_int, [_P]),
+    "spin_synchronize": (_c.c_int, [_P]),
+    "spin_device_spins": (_c.c_void_p, [_P]),
+    "spin_threshold_table": (_c.c_int, [_c.c_double, _c.c_int, _u64p]),
+    "spin_set_allocator": (None, [ALLOC_FN, RELEASE_FN, _c.c_void_p]),
+    "spin_last_error": (_c.c_char_p, []),
+    "spin_version": (_c.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libspin.so (built by ``paper_1006_3865_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libspin.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        lib = _c.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class SpinError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("spin error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != SPIN_OK:
+        raise SpinError(rc, load().spin_last_error().decode())
+    return rc
+
+
+def _i8(a):
+    return a.ctypes.data_as(_i8p)
+
+
+# --------------------------------------------------------------- C names
+
+def spin_create(model, L, d, couplings, seed):
+    lib = load()
+    J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
+    h = lib.spin_create(model, L, d, None if J is None else _i8(J), seed)
+    if not h:
+        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+    return h
+
+
+def spin_create_config(model, L, d, couplings=None, coupling_seed=0, realisation=0, seed=0, replica=0,
+                       stream=None):
+    lib = load()
+    J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
+    cfg = spin_config(model, L, d, None if J is None else _i8(J), coupling_seed, realisation, seed, replica,
+                      stream)
+    h = lib.spin_create_config(_c.byref(cfg))
+    if not h:
+        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+    return h
+
+
+def spin_free(h):
+    load().spin_free(h)
+
+
+def spin_sweep(h, n, beta):
+    return _check(load().spin_sweep(h, n, beta))
+
+
+def spin_sweep_record(h, n, beta, every):
+    nrec = n // every if every > 0 else 0
+    E = np.zeros(max(nrec, 1), dtype=np.int64)
+    M = np.zeros(max(nrec, 1), dtype=np.int64)
+    _check(load().spin_sweep_record(h, n, beta, every, E.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p)))
+    return E[:nrec], M[:nrec]
+
+
+def spin_sweep_record_device(h, n, beta, every, E_ptr, M_ptr):
+    return _check(load().spin_sweep_record_device(h, n, beta, every, E_ptr, M_ptr))
+
+
+def spin_measure(h):
+    E, M = _c.c_int64(), _c.c_int64()
+    _check(load().spin_measure(h, _c.byref(E), _c.byref(M)))
+    return E.value, M.value
+
+
+def spin_get_spins(h, n):
+    out = np.empty(n, dtype=np.int8)
+    _check(load().spin_get_spins(h, _i8(out), n))
+    return out
+
+
+def spin_set_spins(h, spins):
+    a = np.ascontiguousarray(spins, dtype=np.int8)
+    return _check(load().spin_set_spins(h, _i8(a), a.size))
+
+
+def spin_get_couplings(h, n):
+    out = np.empty(n, dtype=np.int8)
+    _check(load().spin_get_couplings(h, _i8(out), n))
+    return out
+
+
+def spin_sweeps_done(h):
+    return int(load().spin_sweeps_done(h))
+
+
+def spin_set_sweeps_done(h, t):
+    return _check(load().spin_set_sweeps_done(h, t))
+
+
+def spin_set_stream(h, stream):
+    return _check(load().spin_set_stream(h, stream))
+
+
+def spin_set_kernel(h, kernel, tile_x=0, tile_y=0, tile_z=0, threads=0):
+    return _check(load().spin_set_kernel(h, kernel, tile_x, tile_y, tile_z, threads))
+
+
+def spin_get_kernel(h):
+    k = load().spin_get_kernel(h)
+    if k < 0:
+        _check(k)
+    return k
+
+
+def spin_synchronize(h):
+    return _check(load().spin_synchronize(h))
+
+
+def spin_device_spins(h):
+    return load().spin_device_spins(h)
+
+
+def spin_threshold_table(beta, d):
+    T = np.zeros(2 * d + 1, dtype=np.uint64)
+    _check(load().spin_threshold_table(beta, d, T.ctypes.data_as(_u64p)))
+    return T
+
+
+def spin_last_error():
+    return load().spin_last_error().decode()
+
+
+def spin_version():
+    return load().spin_version().decode()
+
+
+# ------------------------------------------------- torch device memory hook
+
+_torch_hooks = None
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching allocator."""
+    global _torch_hooks
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+        except Exception:
+            return None
+
+    def _release(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    _torch_hooks = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+    load().spin_set_allocator(_torch_hooks[0], _torch_hooks[1], None)
+
+
+def use_hip_allocator():
+    load().spin_set_allocator(ALLOC_FN(), RELEASE_FN(), None)
+
+
+# ---------------------------------------------------------------- wrapper
+
+class Lattice:
+    """One lattice owned by the library.  Mirrors the C calls one to one."""
+
+    def __init__(self, model, L, d, seed, couplings=None, coupling_seed=None, realisation=0, replica=0,
+                 stream=None):
+        if model == SPIN_EA_PMJ and couplings is None and coupling_seed is None:
+            raise ValueError("EA lattice needs couplings or a coupling_seed")
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        self.h = spin_create_config(model, L, d, couplings, coupling_seed or 0, realisation, seed, replica, sp)
+        self.model, self.L, self.d, self.N = model, L, d, L ** d
+
+    def close(self):
+        if self.h:
+            spin_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n, beta):
+        spin_sweep(self.h, n, beta)
+
+    def sweep_record(self, n, beta, every):
+        return spin_sweep_record(self.h, n, beta, every)
+
+    def sweep_record_device(self, n, beta, every, E, M):
+        """E, M: torch int64 CUDA tensors with >= n//every elements."""
+        spin_sweep_record_device(self.h, n, beta, every, E.data_ptr(), M.data_ptr())
+
+    def measure(self):
+        return spin_measure(self.h)
+
+    def spins(self):
+        return spin_get_spins(self.h, self.N)
+
+    def set_spins(self, s):
+        spin_set_spins(self.h, s)
+
+    def couplings(self):
+        return spin_get_couplings(self.h, self.d * self.N)
+
+    @property
+    def t(self):
+        return spin_sweeps_done(self.h)
+
+    @t.setter
+    def t(self, value):
+        spin_set_sweeps_done(self.h, value)
+
+    def set_kernel(self, kernel, tile_x=0, tile_y=0, tile_z=0, threads=0):
+        spin_set_kernel(self.h, kernel, tile_x, tile_y, tile_z, threads)
+
+    @property
+    def kernel(self):
+        return spin_get_kernel(self.h)
+
+    def set_stream(self, stream):
+        spin_set_stream(self.h, stream if isinstance(stream, int) or stream is None else stream.cuda_stream)
+
+    def synchronize(self):
+        spin_synchronize(self.h)

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for bit.
+
+Spins, E and M are integers, so the bar is exact equality everywhere.  Every
+kernel family and tile shape is run on the same seeded inputs; sizes span
+several tiles and ragged (L % 8 != 0) lattices, the degenerate inverse
+temperatures (beta = 0 flips every spin, beta = inf is a quench, beta = 3
+has T = 0 entries) and the full benchmark sizes (sampled by sweeps).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1006_3865_amd import spin, workloads
+
+pytestmark = pytest.mark.gpu
+
+B_CRIT = workloads.BETA_2D_CRIT
+B_3D = workloads.BETA_3D
+GEN, RES, TIL, FUS = (spin.SPIN_KERNEL_GENERIC, spin.SPIN_KERNEL_RESIDENT, spin.SPIN_KERNEL_TILED,
+                      spin.SPIN_KERNEL_FUSED)
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    spin.load()
+    return torch
+
+
+def make(model, L, d, seed, replica=0, J=None, cseed=None, kernel=spin.SPIN_KERNEL_AUTO, tile=(0, 0, 0, 0)):
+    lat = spin.Lattice(model, L, d, seed, couplings=J, coupling_seed=cseed, replica=replica)
+    if kernel != spin.SPIN_KERNEL_AUTO:
+        lat.set_kernel(kernel, *tile)
+    return lat
+
+
+def compare_runs(oracle_mod, model, L, d, seed, schedule, replica=0, J=None, cseed=None, kernel=0,
+                 tile=(0, 0, 0, 0), tag=""):
+    """schedule: list of (n, beta, every); compares records and spins after every call."""
+    note("parity", tag, "model", model, "L", L, "d", d, "kernel", kernel, "tile", tile)
+    lat = make(model, L, d, seed, replica, J, cseed, kernel, tile)
+    Jo = J
+    if model == 1 and J is None:
+        Jo = oracle_mod.couplings(L, d, cseed, 0)
+        np.testing.assert_array_equal(lat.couplings(), Jo)
+    ch = oracle_mod.Chain(L, d, seed, replica, J=Jo)
+    np.testing.assert_array_equal(lat.spins(), ch.spins)
+    for (n, beta, every) in schedule:
+        if every:
+            Eg, Mg = lat.sweep_record(n, beta, every)
+            Eo, Mo = ch.sweep(n, beta, every=every)
+            np.testing.assert_array_equal(Eg, Eo)
+            np.testing.assert_array_equal(Mg, Mo)
+        else:
+            lat.sweep(n, beta)
+            ch.sweep(n, beta)
+        got = lat.spins()
+        if not np.array_equal(got, ch.spins):
+            bad = np.flatnonzero(got != ch.spins)
+            raise AssertionError("spins differ at %d sites, first %s (t=%d)" % (bad.size, bad[:8], ch.t))
+        assert lat.t == ch.t
+        assert lat.measure() == ch.measure()
+    lat.close()
+
+
+# ----------------------------------------------------------- hot start etc.
+
+@pytest.mark.parametrize("L,d,replica", [(4, 2, 0), (6, 2, 3), (64, 2, 0), (8192, 2, 0), (10, 3, 1), (64, 3, 7)])
+def test_hot_start_matches_oracle(oracle_mod, L, d, replica):
+    s = workloads.seed(2)
+    lat = make(0, L, d, s, replica)
+    np.testing.assert_array_equal(lat.spins(), oracle_mod.init_spins(L, d, s, replica))
+    E, M = lat.measure()
+    assert (E, M) == oracle_mod.measure(L, d, None, oracle_mod.init_spins(L, d, s, replica))
+    lat.close()
+
+
+@pytest.mark.parametrize("L,d,real", [(6, 2, 0), (16, 3, 4), (64, 3, 511)])
+def test_generated_couplings_match_oracle(oracle_mod, L, d, real):
+    lat = spin.Lattice(1, L, d, 5, coupling_seed=workloads.seed(0x11), realisation=real)
+    np.testing.assert_array_equal(lat.couplings(), oracle_mod.couplings(L, d, workloads.seed(0x11), real))
+    lat.close()
+
+
+# ------------------------------------------------- small-lattice configs
+
+def test_ising2d_L64_full_record(oracle_mod):
+    """2D Ising L=64 at 0.4406868, 1000 sweeps, E/M every sweep, spins at 1,2,10,100,1000."""
+    cfg = workloads.CONFIGS["ising2d_L64"]
+    sched = [(1, B_CRIT, 1), (1, B_CRIT, 1), (8, B_CRIT, 1), (90, B_CRIT, 1), (900, B_CRIT, 1)]
+    compare_runs(oracle_mod, 0, 64, 2, cfg["seed"], sched, tag="ising2d_L64")
+
+
+def test_L4_parity(oracle_mod):
+    compare_runs(oracle_mod, 0, 4, 2, workloads.seed(4), [(1000, B_CRIT, 1)], tag="L4")
+
+
+# ---------------------------------------------- every family, every tile
+
+BETAS = [0.30, B_CRIT, 0.60, 0.0, math.inf, 3.0]
+
+CASES_2D = [
+    (GEN, (0, 0, 0, 0), 32), (GEN, (0, 0, 0, 0), 34),
+    (RES, (0, 0, 0, 64), 32), (RES, (0, 0, 0, 1024), 64), (RES, (0, 0, 0, 256), 18),
+    (TIL, (16, 8, 0, 64), 32), (TIL, (64, 8, 0, 64), 128), (TIL, (128, 16, 0, 256), 256),
+    (TIL, (256, 32, 0, 256), 512), (TIL, (512, 32, 0, 512), 1024),
+    (FUS, (16, 8, 0, 64), 32), (FUS, (16, 8, 0, 64), 48), (FUS, (128, 16, 0, 256), 256),
+    (FUS, (256, 32, 0, 256), 512), (FUS, (512, 32, 0, 512), 1024), (FUS, (256, 32, 0, 256), 256),
+]
+
+
+@pytest.mark.parametrize("kernel,tile,L", CASES_2D)
+def test_ising2d_all_kernels(oracle_mod, kernel, tile, L):
+    sched = [(3, b, 1) for b in BETAS] + [(4, B_CRIT, 2)]
+    compare_runs(oracle_mod, 0, L, 2, workloads.seed(20 + L), sched, replica=2, kernel=kernel, tile=tile,
+                 tag="2d")
+
+
+CASES_3D = [
+    (GEN, (0, 0, 0, 0), 16), (GEN, (0, 0, 0, 0), 10),
+    (RES, (0, 0, 0, 256), 16), (RES, (0, 0, 0, 512), 32), (RES, (0, 0, 0, 128), 6),
+    (TIL, (16, 4, 4, 64), 16), (TIL, (16, 4, 4, 64), 32), (TIL, (32, 8, 4, 128), 64),
+    (TIL, (64, 8, 8, 256), 64), (TIL, (128, 8, 4, 256), 128),
+]
+
+
+@pytest.mark.parametrize("kernel,tile,L", CASES_3D)
+def test_ising3d_all_kernels(oracle_mod, kernel, tile, L):
+    sched = [(2, b, 1) for b in [B_3D, 0.5, 0.0, math.inf, 3.0]]
+    compare_runs(oracle_mod, 0, L, 3, workloads.seed(30 + L), sched, replica=1, kernel=kernel, tile=tile,
+                 tag="3d")
+
+
+@pytest.mark.parametrize("kernel,tile,L,d", [
+    (GEN, (0, 0, 0, 0), 16, 2), (GEN, (0, 0, 0, 0), 10, 3), (GEN, (0, 0, 0, 0), 24, 3),
+    (RES, (0, 0, 0, 256), 14, 2), (RES, (0, 0, 0, 512), 16, 3), (RES, (0, 0, 0, 1024), 24, 3),
+])
+def test_ea_all_kernels(oracle_mod, kernel, tile, L, d):
+    sched = [(3, b, 1) for b in [0.5, 1.2, 0.0, math.inf, 3.0]]
+    compare_runs(oracle_mod, 1, L, d, workloads.seed(40 + L), sched, replica=5, cseed=workloads.seed(0x11),
+                 kernel=kernel, tile=tile, tag="ea")
+
+
+def test_ea_host_couplings(oracle_mod):
+    rng = np.random.default_rng(9)
+    L, d = 12, 3
+    J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d)
+    compare_runs(oracle_mod, 1, L, d, 77, [(5, 0.8, 1)], J=J, tag="ea-host")
+
+
+def test_auto_choice_and_switching(oracle_mod):
+    """Switch families between calls of one chain; bits must not change."""
+    L, s = 64, workloads.seed(50)
+    lat = make(0, L, 2, s)
+    ch = oracle_mod.Chain(L, 2, s)
+    for kern, tile in [(FUS, (16, 8, 0, 64)), (TIL, (16, 8, 0, 64)), (GEN, (0, 0, 0, 0)), (RES, (0, 0, 0, 256)),
+                       (FUS, (16, 8, 0, 64)), (spin.SPIN_KERNEL_AUTO, (0, 0, 0, 0))]:
+        lat.set_kernel(kern, *tile)
+        E, M = lat.sweep_record(3, B_CRIT, 1)
+        Eo, Mo = ch.sweep(3, B_CRIT, every=1)
+        np.testing.assert_array_equal(E, Eo)
+        np.testing.assert_array_equal(M, Mo)
+        np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
+
+
+def test_resume_from_saved_state(oracle_mod):
+    L, s = 256, workloads.seed(51)
+    a = make(0, L, 2, s)
+    a.sweep(7, 0.5)
+    saved, t = a.spins(), a.t
+    a.sweep(5, 0.5)
+    b = make(0, L, 2, s)
+    b.set_spins(saved)
+    b.t = t
+    b.sweep(5, 0.5)
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    a.close()
+    b.close()
+
+
+def test_device_records_and_torch_stream(oracle_mod, gpu):
+    torch = gpu
+    L, s = 512, workloads.seed(52)
+    stream = torch.cuda.Stream()
+    E = torch.full((10,), -7, dtype=torch.int64, device="cuda")
+    M = torch.full((10,), -7, dtype=torch.int64, device="cuda")
+    stream.wait_stream(torch.cuda.current_stream())
+    lat = spin.Lattice(0, L, 2, s, stream=stream)
+    lat.sweep_record_device(20, B_CRIT, 2, E, M)
+    lat.synchronize()
+    ch = oracle_mod.Chain(L, 2, s)
+    Eo, Mo = ch.sweep(20, B_CRIT, every=2)
+    np.testing.assert_array_equal(E.cpu().numpy(), Eo)
+    np.testing.assert_array_equal(M.cpu().numpy(), Mo)
+    lat.close()
+
+
+def test_torch_allocator(oracle_mod, gpu):
+    spin.use_torch_allocator()
+    try:
+        compare_runs(oracle_mod, 0, 128, 2, 3, [(4, 0.4, 1)], kernel=FUS, tile=(16, 8, 0, 64), tag="torch-alloc")
+    finally:
+        spin.use_hip_allocator()
+
+
+# ------------------------------------------------------ full-size configs
+
+@pytest.mark.parametrize("beta", workloads.BETA_2D)
+def test_ising2d_L8192_first_sweeps(oracle_mod, beta):
+    """Full benchmark size, the kernel the benchmark times: two sweeps, records each sweep."""
+    cfg = workloads.CONFIGS["ising2d_L8192"]
+    lat = make(0, 8192, 2, cfg["seed"])
+    note("L8192 beta", beta, "kernel", spin.KERNEL_NAMES[lat.kernel])
+    assert lat.kernel == FUS
+    E, M = lat.sweep_record(2, beta, 1)
+    ch = oracle_mod.Chain(8192, 2, cfg["seed"])
+    Eo, Mo = ch.sweep(2, beta, every=1)
+    np.testing.assert_array_equal(E, Eo)
+    np.testing.assert_array_equal(M, Mo)
+    np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
+
+
+def test_ising3d_L512_first_sweep(oracle_mod):
+    cfg = workloads.CONFIGS["ising3d_L512"]
+    lat = make(0, 512, 3, cfg["seed"])
+    note("L512 3d kernel", spin.KERNEL_NAMES[lat.kernel])
+    E, M = lat.sweep_record(1, B_3D, 1)
+    ch = oracle_mod.Chain(512, 3, cfg["seed"])
+    Eo, Mo = ch.sweep(1, B_3D, every=1)
+    np.testing.assert_array_equal(E, Eo)
+    np.testing.assert_array_equal(M, Mo)
+    np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
