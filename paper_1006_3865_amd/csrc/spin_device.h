@@ -34,6 +34,60 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
   r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
 }
 
+// Uniform part of a Philox4x32-10 evaluation whose counter words c1, c2, c3
+// are the same for the whole wavefront (sweep, replica, colour) and only c0
+// varies by lane: the first two rounds are half scalar, so their uniform
+// halves are computed once (on the scalar unit) and folded with the round
+// keys into single operands.
+struct PhiloxUniform {
+  uint32_t x1;      // round 1: hi(M0*c0) ^ x1          -> c2 after round 1
+  uint32_t x2;      // round 2: hi(M1*c2) ^ x2          -> c0 after round 2
+  uint32_t x3;      // round 2: c3_after_round1 ^ x3    -> c2 after round 2 (x3 = hi(M0*u0) ^ k1[1])
+  uint32_t u3;      // round 2: lo(M0*u0)               -> c3 after round 2
+};
+
+__device__ __forceinline__ PhiloxUniform philox_uniform(uint32_t c1, uint32_t c2, uint32_t c3,
+                                                        const RoundKeys& K) {
+  PhiloxUniform U;
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+  const uint32_t u0 = (uint32_t)(p1 >> 32) ^ c1 ^ K.k0[0];  // c0 after round 1
+  const uint32_t u1 = (uint32_t)p1;                         // c1 after round 1
+  U.x1 = c3 ^ K.k1[0];
+  U.x2 = u1 ^ K.k0[1];
+  const uint64_t q0 = (uint64_t)0xD2511F53u * u0;
+  U.x3 = (uint32_t)(q0 >> 32) ^ K.k1[1];
+  U.u3 = (uint32_t)q0;
+  return U;
+}
+
+// Philox4x32-10 of counter (c0, c1, c2, c3) given U = philox_uniform(c1, c2, c3).
+__device__ __forceinline__ void philox_lane(uint32_t c0, const PhiloxUniform& U, const RoundKeys& K,
+                                            uint32_t r[4]) {
+  // round 1
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+  const uint32_t a2 = (uint32_t)(p0 >> 32) ^ U.x1;
+  const uint32_t a3 = (uint32_t)p0;
+  // round 2 (c0 after round 1 is uniform: its product is in U)
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * a2;
+  uint32_t d0 = (uint32_t)(p1 >> 32) ^ U.x2;
+  uint32_t d1 = (uint32_t)p1;
+  uint32_t d2 = a3 ^ U.x3;
+  uint32_t d3 = U.u3;
+  // rounds 3..10
+#pragma unroll
+  for (int i = 2; i < 10; ++i) {
+    const uint64_t q0 = (uint64_t)0xD2511F53u * d0;
+    const uint64_t q1 = (uint64_t)0xCD9E8D57u * d2;
+    const uint32_t n0 = xor3((uint32_t)(q1 >> 32), d1, K.k0[i]);
+    const uint32_t n2 = xor3((uint32_t)(q0 >> 32), d3, K.k1[i]);
+    d1 = (uint32_t)q1;
+    d3 = (uint32_t)q0;
+    d0 = n0;
+    d2 = n2;
+  }
+  r[0] = d0; r[1] = d1; r[2] = d2; r[3] = d3;
+}
+
 // ---------------------------------------------------------------------------
 // Byte-parallel update of one aligned group of 8 sites along x.
 //
@@ -74,7 +128,7 @@ __device__ __forceinline__ void unsat_ising(uint32_t c0, uint32_t c1, uint32_t l
 template <bool NEVER>
 __device__ __forceinline__ uint32_t flip_bits(uint32_t S, uint32_t sh, uint32_t r,
                                               const uint32_t* bound_lds, uint32_t never4) {
-  const uint32_t i4 = (S >> sh) & 0xffu;  // 4u
+  const uint32_t i4 = __builtin_amdgcn_ubfe(S, sh, 8);  // 4u
   const uint32_t b = *(const uint32_t*)((const char*)bound_lds + i4);
   bool acc = r <= b;
   if (NEVER) acc = acc && (i4 >= never4);
@@ -88,6 +142,20 @@ __device__ __forceinline__ void apply_group(uint32_t& c0, uint32_t& c1, uint32_t
                                             uint32_t p, const uint32_t r[4],
                                             const uint32_t* bound_lds, uint32_t never4) {
   const uint32_t sa = 8u * p, sb = 8u * p + 16u;
+  const uint32_t f0 = flip_bits<NEVER>(S0, sa, r[0], bound_lds, never4);
+  const uint32_t f1 = flip_bits<NEVER>(S0, sb, r[1], bound_lds, never4);
+  const uint32_t f2 = flip_bits<NEVER>(S1, sa, r[2], bound_lds, never4);
+  const uint32_t f3 = flip_bits<NEVER>(S1, sb, r[3], bound_lds, never4);
+  c0 = xor3(c0, f0, f1);
+  c1 = xor3(c1, f2, f3);
+}
+
+// apply_group with the parity of the active bytes known at compile time.
+template <uint32_t P, bool NEVER>
+__device__ __forceinline__ void apply_group_p(uint32_t& c0, uint32_t& c1, uint32_t S0, uint32_t S1,
+                                              const uint32_t r[4], const uint32_t* bound_lds,
+                                              uint32_t never4) {
+  constexpr uint32_t sa = 8u * P, sb = 8u * P + 16u;
   const uint32_t f0 = flip_bits<NEVER>(S0, sa, r[0], bound_lds, never4);
   const uint32_t f1 = flip_bits<NEVER>(S0, sb, r[1], bound_lds, never4);
   const uint32_t f2 = flip_bits<NEVER>(S1, sa, r[2], bound_lds, never4);

@@ -183,40 +183,57 @@ __global__ __launch_bounds__(NT) void k_measure_sites(const int8_t* __restrict__
   }
 }
 
-// Dword version (L % 4 == 0): popcounts of sign bits.
+// Row-structured version (L % 16 == 0): each workgroup takes RPB lattice rows
+// (a row = L sites along x at fixed y, z); a thread takes 16 sites of a row,
+// counts negative spins and unsatisfied +x/+y/+z bonds from sign bits, with
+// 32-bit index arithmetic (rows < 2^32, bytes per row < 2^17).
 template <int NT>
-__global__ __launch_bounds__(NT) void k_measure_quads(const uint32_t* __restrict__ sp,
-                                                      const uint32_t* __restrict__ J, uint32_t L,
-                                                      uint32_t d, uint64_t N, int64_t* E,
-                                                      int64_t* M) {
+__global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ sp,
+                                                     const int8_t* __restrict__ J, uint32_t L,
+                                                     uint32_t d, uint64_t N, uint32_t nrows,
+                                                     uint32_t rpb, int64_t* E, int64_t* M) {
   __shared__ int64_t red[NT / 64];
-  const uint32_t Lq = L / 4;
-  const uint64_t nq = N / 4;
-  const uint64_t Nq = nq;
   const uint32_t msb = 0x80808080u;
+  const uint32_t cpr = L / 16;
   int64_t unsat = 0, neg = 0;
-  for (uint64_t q = blockIdx.x * (uint64_t)NT + threadIdx.x; q < nq; q += (uint64_t)gridDim.x * NT) {
-    const uint32_t c = sp[q];
-    neg += __popc(c & msb);
-    const uint32_t xq = (uint32_t)(q % Lq);
-    const uint64_t row = q / Lq;
-    const uint64_t nxq = (xq + 1 == Lq) ? q - (Lq - 1) : q + 1;
-    const uint32_t R = __builtin_amdgcn_alignbyte(sp[nxq], c, 1);
-    uint32_t jx = J ? J[q] : 0u;
-    unsat += __popc((c ^ R ^ jx) & msb);
-    const uint32_t y = (uint32_t)(row % L);
-    const uint64_t yq = (y + 1 == L) ? q - (uint64_t)(L - 1) * Lq : q + Lq;
-    uint32_t jy = J ? J[Nq + q] : 0u;
-    unsat += __popc((c ^ sp[yq] ^ jy) & msb);
-    if (d == 3) {
-      const uint32_t z = (uint32_t)(row / L);
-      const uint64_t plane = (uint64_t)L * Lq;
-      const uint64_t zq = (z + 1 == L) ? q - (uint64_t)(L - 1) * plane : q + plane;
-      uint32_t jz = J ? J[2 * Nq + q] : 0u;
-      unsat += __popc((c ^ sp[zq] ^ jz) & msb);
+  const uint32_t row_end = min(nrows, (blockIdx.x + 1) * rpb);
+  for (uint32_t row = blockIdx.x * rpb; row < row_end; ++row) {
+    const uint32_t y = row % L;
+    const uint32_t z = row / L;  // 0 in 2D
+    const uint64_t base = (uint64_t)row * L;
+    const uint64_t below = base + ((y + 1 == L) ? -(int64_t)(L - 1) * L : (int64_t)L);
+    const uint64_t plane = (uint64_t)L * L;
+    const uint64_t behind = (d == 3) ? (base + ((z + 1 == L) ? -(int64_t)(L - 1) * plane : (int64_t)plane)) : 0;
+    for (uint32_t cx = threadIdx.x; cx < cpr; cx += NT) {
+      const uint32_t x = 16 * cx;
+      const uint4 c = *reinterpret_cast<const uint4*>(sp + base + x);
+      const uint32_t nx = *reinterpret_cast<const uint32_t*>(sp + base + ((x + 16 == L) ? 0 : x + 16));
+      const uint4 dy = *reinterpret_cast<const uint4*>(sp + below + x);
+      const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+      const uint32_t yw[4] = {dy.x, dy.y, dy.z, dy.w};
+      const uint32_t rw[4] = {__builtin_amdgcn_alignbyte(c.y, c.x, 1), __builtin_amdgcn_alignbyte(c.z, c.y, 1),
+                              __builtin_amdgcn_alignbyte(c.w, c.z, 1), __builtin_amdgcn_alignbyte(nx, c.w, 1)};
+      uint4 jx = make_uint4(0, 0, 0, 0), jy = jx, jz = jx;
+      if (J) {
+        jx = *reinterpret_cast<const uint4*>(J + base + x);
+        jy = *reinterpret_cast<const uint4*>(J + N + base + x);
+        if (d == 3) jz = *reinterpret_cast<const uint4*>(J + 2 * N + base + x);
+      }
+      const uint32_t jxw[4] = {jx.x, jx.y, jx.z, jx.w}, jyw[4] = {jy.x, jy.y, jy.z, jy.w};
+      const uint32_t jzw[4] = {jz.x, jz.y, jz.z, jz.w};
+      uint4 dz = make_uint4(0, 0, 0, 0);
+      if (d == 3) dz = *reinterpret_cast<const uint4*>(sp + behind + x);
+      const uint32_t zw[4] = {dz.x, dz.y, dz.z, dz.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        neg += __popc(cw[k] & msb);
+        unsat += __popc(xor3(cw[k], rw[k], jxw[k]) & msb);
+        unsat += __popc(xor3(cw[k], yw[k], jyw[k]) & msb);
+        if (d == 3) unsat += __popc(xor3(cw[k], zw[k], jzw[k]) & msb);
+      }
     }
   }
-  // per dword: E part = sum_dir (-4 + 2 unsat_dir), M part = 4 - 2 neg
+  // per site: E part = sum_dir (-1 + 2 unsat_dir), M part = 1 - 2 neg; constants added later
   const int64_t bu = block_sum<NT>(unsat, red);
   const int64_t bn = block_sum<NT>(neg, red);
   if (threadIdx.x == 0) {
@@ -234,10 +251,14 @@ __global__ void k_add_const(int64_t* E, int64_t* M, int64_t e0, int64_t m0) {
 
 hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t stream) {
   constexpr int NT = 256;
-  if (lat.L % 4 == 0) {
-    const uint64_t nq = lat.N / 4;
-    hipLaunchKernelGGL(k_measure_quads<NT>, dim3(grid_for(nq, NT, 4096)), dim3(NT), 0, stream,
-                       (const uint32_t*)lat.spins, (const uint32_t*)lat.J, lat.L, lat.d, lat.N, E, M);
+  if (lat.L % 16 == 0) {
+    const uint32_t nrows = (uint32_t)(lat.N / lat.L);
+    // about 2048 workgroups, whole rows each
+    uint32_t rpb = (nrows + 2047) / 2048;
+    if (rpb < 1) rpb = 1;
+    const uint32_t blocks = (nrows + rpb - 1) / rpb;
+    hipLaunchKernelGGL(k_measure_rows<NT>, dim3(blocks), dim3(NT), 0, stream, (const int8_t*)lat.spins,
+                       lat.J, lat.L, lat.d, lat.N, nrows, rpb, E, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // constants: E = -d N + 2 unsat, M = N - 2 neg
@@ -630,14 +651,296 @@ __global__ __launch_bounds__(NT) void k_fused2d(const int8_t* __restrict__ src,
   }
 }
 
+// 2D Ising, one whole sweep, tile 512 bytes wide (one 64-lane wave per row:
+// lane l owns the group at x = x0 + 8l) and TH rows.  Everything that depends
+// on the row only (parity of the active bytes, flip constants, addresses,
+// counter base) is wave-uniform.  LDS layout as in k_fused2d with TW = 512.
+// Phase 0: colour 0 on LDS rows 1..TH+2 (tile columns), plus the two halo
+// groups (x0-8, x0+512) on rows 2..TH+1; phase 1: colour 1 on rows 2..TH+1.
+template <int TH, bool NEVER>
+__global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ src,
+                                                   int8_t* __restrict__ dst, PhaseArgs a) {
+  constexpr int TW = 512;
+  constexpr int RB = TW + 32;
+  constexpr int GPR = TW / 8;
+  constexpr int RT = TH + 4;
+  constexpr int CPR = TW / 16 + 2;
+  __shared__ __align__(16) int8_t tile[RT * RB];
+  __shared__ uint32_t bound[8];
+  if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
+  const uint32_t L = a.L;
+  const uint32_t x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int i = threadIdx.x; i < RT * CPR; i += 256) {
+    const int r = i / CPR, q = i - r * CPR;
+    const uint32_t y = wrap_row(y0 + r, 2u, L);
+    const uint32_t x = wrap_row(x0 + 16 * q, 16u, L);
+    *reinterpret_cast<uint4*>(tile + r * RB + 16 * q) =
+        *reinterpret_cast<const uint4*>(src + (uint64_t)y * L + x);
+  }
+  __syncthreads();
+  const uint32_t gq = (x0 >> 3) + (uint32_t)lane;  // counter word of this lane's group, minus row part
+  const uint32_t Lg = L >> 3;                      // groups per lattice row
+  // ---- phase 0: colour 0, tile columns, LDS rows 1..TH+2 (wave-strided)
+  {
+    const int r_first = 1 + wave;
+    const uint32_t p = (y0 + (uint32_t)r_first) & 1u;  // parity of y = y0 + r - 2
+#pragma unroll 2
+    for (int r = r_first; r <= TH + 2; r += 4) {
+      int8_t* row = tile + r * RB + 16 + 8 * lane;
+      const uint2 c = *reinterpret_cast<const uint2*>(row);
+      const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+      const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+      const uint32_t y = wrap_row(y0 + (uint32_t)r, 2u, L);
+      uint32_t rnd[4];
+      philox(y * Lg + gq, a.t, a.replica, 0u, a.keys, rnd);
+      const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = c.x, c1 = c.y;
+      apply_group<NEVER>(c0, c1, S0, S1, p, rnd, bound, a.never4);
+      *reinterpret_cast<uint2*>(row) = make_uint2(c0, c1);
+    }
+  }
+  // ---- phase 0: the halo groups left (LDS group 1) and right (group GPR+2) of rows 2..TH+1
+  for (int u = threadIdx.x; u < 2 * TH; u += 256) {
+    const int r = 2 + (u >> 1), side = u & 1;
+    const int j = side ? GPR + 2 : 1;
+    int8_t* row = tile + r * RB + 8 * j;
+    const uint2 c = *reinterpret_cast<const uint2*>(row);
+    const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+    const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+    const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+    const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+    const uint32_t y = y0 + (uint32_t)r - 2u;
+    const uint32_t x = wrap_row(x0 + 8 * j, 16u, L);
+    uint32_t rnd[4];
+    philox(y * Lg + (x >> 3), a.t, a.replica, 0u, a.keys, rnd);
+    const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+    uint32_t S0, S1;
+    unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+    uint32_t c0 = c.x, c1 = c.y;
+    apply_group<NEVER>(c0, c1, S0, S1, y & 1u, rnd, bound, a.never4);
+    *reinterpret_cast<uint2*>(row) = make_uint2(c0, c1);
+  }
+  __syncthreads();
+  // ---- phase 1: colour 1 on the tile rows, written to dst
+  {
+    const int r_first = 2 + wave;
+    const uint32_t p = (y0 + (uint32_t)r_first + 1u) & 1u;  // parity of (1 + y), y = y0 + r - 2
+    int8_t* out = dst + (uint64_t)(y0 + (uint32_t)r_first - 2u) * L + x0 + 8 * lane;
+#pragma unroll 2
+    for (int r = r_first; r <= TH + 1; r += 4) {
+      const int8_t* row = tile + r * RB + 16 + 8 * lane;
+      const uint2 c = *reinterpret_cast<const uint2*>(row);
+      const uint2 up = *reinterpret_cast<const uint2*>(row - RB);
+      const uint2 dn = *reinterpret_cast<const uint2*>(row + RB);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
+      const uint32_t y = y0 + (uint32_t)r - 2u;
+      uint32_t rnd[4];
+      philox(y * Lg + gq, a.t, a.replica, 1u, a.keys, rnd);
+      const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = c.x, c1 = c.y;
+      apply_group<NEVER>(c0, c1, S0, S1, p, rnd, bound, a.never4);
+      *reinterpret_cast<uint2*>(out) = make_uint2(c0, c1);
+      out += 4 * (uint64_t)L;
+    }
+  }
+}
+
+// 2D Ising, one whole sweep, streaming over full-width rows.  L = 8 * NT * G:
+// thread l owns the groups g = l + NT*j (j < G) of every row (x = 8g).  A
+// workgroup owns the strip of H rows [y0, y0+H) (H even) and keeps a ring of 8
+// rows in LDS (row k of the strip, k = y - (y0-2), lives in slot k & 7; a
+// row's bytes sit at [16, 16+L) with x = L-16..L-1 copied to [0,16) and
+// x = 0..15 to [16+L, 32+L)).  Step i (i = 0..H+2), with a = y0-1+i:
+//   load row a+2 into registers (stored to LDS at the end of the step);
+//   colour 0 on row a (i <= H+1): reads rows a-1..a+1, writes row a in LDS;
+//   colour 1 on row a-2 (i >= 3): reads rows a-3..a-1, writes dst;
+//   barrier.
+// Row a's colour-1 bytes are still the old ones when colour 0 reads them
+// (colour 1 reaches row a two steps later), and colour 1 on row a-2 reads
+// colour-0 bytes finished one or more steps earlier.  The step loop is
+// unrolled over the ring period so that ring slots and row parities (y0 is
+// even) are compile-time constants.
+template <int NT, int G>
+struct StreamCtx {
+  static constexpr uint32_t L = 8u * NT * G;
+  static constexpr uint32_t GPR = L / 8;
+  static constexpr uint32_t RBS = L + 32;
+  const int8_t* __restrict__ src;
+  int8_t* __restrict__ dst;
+  int8_t* ring;
+  const uint32_t* bound;
+  const RoundKeys* keys;
+  PhiloxUniform U0, U1;
+  uint32_t never4, y0, H, t;
+
+  __device__ __forceinline__ void get_row(uint32_t y, uint2 (&v)[G]) const {
+    const int8_t* rowp = src + (uint64_t)y * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) v[j] = *reinterpret_cast<const uint2*>(rowp + 8 * (t + NT * j));
+  }
+  __device__ __forceinline__ void put_row(uint32_t slot, const uint2 (&v)[G]) const {
+    int8_t* row = ring + slot * RBS;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      *reinterpret_cast<uint2*>(row + 16 + 8 * g) = v[j];
+      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row + 8 * (g - (GPR - 2))) = v[j];
+      if (g < 2) *reinterpret_cast<uint2*>(row + 16 + L + 8 * g) = v[j];
+    }
+  }
+};
+
+template <int NT, int G, bool NEVER, uint32_t S>
+__device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t i) {
+  using C = StreamCtx<NT, G>;
+  constexpr uint32_t L = C::L, GPR = C::GPR, RBS = C::RBS;
+  const uint32_t H = c.H, y0 = c.y0, t = c.t;
+  if (i >= H + 3) return;
+  uint2 nxt[G];
+  const bool do_load = (i <= H);
+  if (do_load) c.get_row(wrap_row(y0 + i + 3, 2u, L), nxt);
+  if (i <= H + 1) {
+    // colour 0 on row a = y0 - 1 + i (strip row k = i + 1); parity of a is (i+1) & 1
+    const uint32_t y = wrap_row(y0 + i + 1, 2u, L);
+    int8_t* row = c.ring + ((S + 1) & 7) * RBS + 16;
+    const int8_t* up = c.ring + (S & 7) * RBS + 16;
+    const int8_t* dn = c.ring + ((S + 2) & 7) * RBS + 16;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
+      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
+      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
+      uint32_t rnd[4];
+      philox_lane(y * GPR + g, c.U0, *c.keys, rnd);
+      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = cc.x, c1 = cc.y;
+      apply_group_p<(S + 1) & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
+      *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
+      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
+      if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
+    }
+  }
+  if (i >= 3) {
+    // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1
+    const uint32_t y = y0 + i - 3u;
+    const int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
+    const int8_t* up = c.ring + ((S + 6) & 7) * RBS + 16;
+    const int8_t* dn = c.ring + (S & 7) * RBS + 16;
+    int8_t* out = c.dst + (uint64_t)y * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
+      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
+      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
+      uint32_t rnd[4];
+      philox_lane(y * GPR + g, c.U1, *c.keys, rnd);
+      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = cc.x, c1 = cc.y;
+      apply_group_p<S & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
+      *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(c0, c1);
+    }
+  }
+  if (do_load) c.put_row((S + 3) & 7, nxt);
+  __syncthreads();
+}
+
+template <int NT, int G, bool NEVER>
+__global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
+                                                 int8_t* __restrict__ dst, PhaseArgs a,
+                                                 uint32_t H) {
+  using C = StreamCtx<NT, G>;
+  // one LDS block: the bound table at byte 0 (a lookup address is just 4u),
+  // then the 8-row ring
+  __shared__ __align__(16) int8_t lds[32 + 8 * C::RBS];
+  C c;
+  c.src = src;
+  c.dst = dst;
+  c.ring = lds + 32;
+  c.bound = reinterpret_cast<const uint32_t*>(lds);
+  c.keys = &a.keys;
+  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
+  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
+  c.never4 = a.never4;
+  c.y0 = blockIdx.x * H;
+  c.H = H;
+  c.t = threadIdx.x;
+  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
+  // prologue: rows k = 0, 1, 2 (y0-2, y0-1, y0)
+  for (uint32_t k = 0; k < 3; ++k) {
+    uint2 v[G];
+    c.get_row(wrap_row(c.y0 + k, 2u, C::L), v);
+    c.put_row(k, v);
+  }
+  __syncthreads();
+  const uint32_t steps = H + 3;
+  for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
+    stream_step<NT, G, NEVER, 0>(c, i0 + 0);
+    stream_step<NT, G, NEVER, 1>(c, i0 + 1);
+    stream_step<NT, G, NEVER, 2>(c, i0 + 2);
+    stream_step<NT, G, NEVER, 3>(c, i0 + 3);
+    stream_step<NT, G, NEVER, 4>(c, i0 + 4);
+    stream_step<NT, G, NEVER, 5>(c, i0 + 5);
+    stream_step<NT, G, NEVER, 6>(c, i0 + 6);
+    stream_step<NT, G, NEVER, 7>(c, i0 + 7);
+  }
+}
+
+// Streaming variants: tile.x == L (full rows), tile.y = strip height H,
+// tile.threads = NT with L = 8 * NT * G.
+static bool stream_shape(uint32_t L, int threads, int* G) {
+  if (threads != 256 && threads != 512 && threads != 1024) return false;
+  if (L % (8u * (uint32_t)threads) != 0) return false;
+  const uint32_t g = L / (8u * (uint32_t)threads);
+  if (g != 1 && g != 2) return false;
+  if (threads == 256 && g != 2) return false;  // instantiated: (1024,1) (1024,2) (512,1) (512,2) (256,2)
+  *G = (int)g;
+  return true;
+}
+
 bool fused_supported(const Lat& lat, const Tile& tile) {
   if (lat.J != nullptr || lat.d != 2) return false;
+  if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
+    int G;
+    return stream_shape(lat.L, tile.threads, &G) && tile.y >= 4 && tile.y % 2 == 0 &&
+           lat.L % (uint32_t)tile.y == 0 && (uint32_t)tile.y <= lat.L;
+  }
   if (lat.L % 16 != 0 || lat.L < 32) return false;
   if (lat.L % tile.x != 0 || lat.L % tile.y != 0) return false;
   return (tile.x == 256 && tile.y == 32 && tile.threads == 256) ||
          (tile.x == 512 && tile.y == 32 && tile.threads == 512) ||
          (tile.x == 128 && tile.y == 16 && tile.threads == 256) ||
-         (tile.x == 16 && tile.y == 8 && tile.threads == 64);
+         (tile.x == 16 && tile.y == 8 && tile.threads == 64) ||
+         (tile.x == 512 && (tile.y == 16 || tile.y == 32 || tile.y == 64) && tile.threads == 256);
+}
+
+template <int TH>
+static hipError_t gofused_w(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
+                            bool never, hipStream_t stream) {
+  dim3 grid(lat.L / 512, lat.L / TH);
+  if (never)
+    hipLaunchKernelGGL((k_fused2d_w<TH, true>), grid, dim3(256), 0, stream, src, dst, a);
+  else
+    hipLaunchKernelGGL((k_fused2d_w<TH, false>), grid, dim3(256), 0, stream, src, dst, a);
+  return hipGetLastError();
 }
 
 template <int TW, int TH, int NT>
@@ -651,11 +954,37 @@ static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const 
   return hipGetLastError();
 }
 
+template <int NT, int G>
+static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
+                           bool never, uint32_t H, hipStream_t stream) {
+  dim3 grid(lat.L / H);
+  if (never)
+    hipLaunchKernelGGL((k_stream2d<NT, G, true>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  else
+    hipLaunchKernelGGL((k_stream2d<NT, G, false>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
                               const Accept& acc, const Tile& tile, hipStream_t stream) {
   if (!fused_supported(lat, tile)) return hipErrorInvalidValue;
   const PhaseArgs a = phase_args(lat, t, 0u, acc);
   const bool never = acc.never_level > 0;
+  if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
+    int G = 0;
+    stream_shape(lat.L, tile.threads, &G);
+    const uint32_t H = (uint32_t)tile.y;
+    if (tile.threads == 1024 && G == 1) return gostream<1024, 1>(lat, src, dst, a, never, H, stream);
+    if (tile.threads == 1024 && G == 2) return gostream<1024, 2>(lat, src, dst, a, never, H, stream);
+    if (tile.threads == 512 && G == 1) return gostream<512, 1>(lat, src, dst, a, never, H, stream);
+    if (tile.threads == 512 && G == 2) return gostream<512, 2>(lat, src, dst, a, never, H, stream);
+    return gostream<256, 2>(lat, src, dst, a, never, H, stream);
+  }
+  if (tile.x == 512 && tile.threads == 256) {
+    if (tile.y == 16) return gofused_w<16>(lat, src, dst, a, never, stream);
+    if (tile.y == 32) return gofused_w<32>(lat, src, dst, a, never, stream);
+    return gofused_w<64>(lat, src, dst, a, never, stream);
+  }
   if (tile.x == 256) return gofused<256, 32, 256>(lat, src, dst, a, never, stream);
   if (tile.x == 512) return gofused<512, 32, 512>(lat, src, dst, a, never, stream);
   if (tile.x == 128) return gofused<128, 16, 256>(lat, src, dst, a, never, stream);

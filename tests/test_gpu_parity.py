@@ -115,6 +115,8 @@ CASES_2D = [
     (TIL, (256, 32, 0, 256), 512), (TIL, (512, 32, 0, 512), 1024),
     (FUS, (16, 8, 0, 64), 32), (FUS, (16, 8, 0, 64), 48), (FUS, (128, 16, 0, 256), 256),
     (FUS, (256, 32, 0, 256), 512), (FUS, (512, 32, 0, 512), 1024), (FUS, (256, 32, 0, 256), 256),
+    (FUS, (512, 16, 0, 256), 512), (FUS, (512, 32, 0, 256), 1024), (FUS, (512, 64, 0, 256), 1024),
+    (FUS, (512, 64, 0, 256), 2048),
 ]
 
 
@@ -211,6 +213,17 @@ def test_torch_allocator(oracle_mod, gpu):
         compare_runs(oracle_mod, 0, 128, 2, 3, [(4, 0.4, 1)], kernel=FUS, tile=(16, 8, 0, 64), tag="torch-alloc")
     finally:
         spin.use_hip_allocator()
+
+
+@pytest.mark.parametrize("tile,L", [
+    ((4096, 16, 0, 512), 4096), ((4096, 64, 0, 512), 4096), ((4096, 8, 0, 256), 4096),
+    ((8192, 32, 0, 1024), 8192), ((8192, 16, 0, 512), 8192),
+])
+def test_ising2d_streaming_rows(oracle_mod, tile, L):
+    """Row-streaming fused kernel: several strips, wrap rows, beta with T == 0 entries."""
+    sched = [(2, B_CRIT, 1), (1, 3.0, 1)]
+    compare_runs(oracle_mod, 0, L, 2, workloads.seed(60 + L), sched, replica=4, kernel=FUS, tile=tile,
+                 tag="stream")
 
 
 # ------------------------------------------------------ full-size configs
