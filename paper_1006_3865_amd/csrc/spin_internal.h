@@ -36,6 +36,20 @@ struct Lat {
 RoundKeys make_round_keys(uint64_t seed);
 Accept make_accept(double beta, int d);
 
+// Where one (E, M) record goes.  Kernels add their partial counts into
+// acc[0] (unsatisfied bonds) and acc[1] (negative spins) with device-scope
+// atomics; the last workgroup to finish writes E = e0 + 2*acc[0] and
+// M = m0 - 2*acc[1] to *E, *M and resets acc and counter to 0 (they must be
+// 0 when the kernel starts: the library zeroes them once at creation).
+struct Record {
+  int64_t* acc;       // 2 int64
+  uint32_t* counter;  // 1 uint32
+  int64_t* E;
+  int64_t* M;
+  int64_t e0;         // -d*N
+  int64_t m0;         // N
+};
+
 // Kernel tile shapes (bytes along x, rows along y, planes along z, threads).
 struct Tile {
   int x, y, z, threads;
@@ -46,8 +60,8 @@ hipError_t launch_init_spins(const Lat& lat, hipStream_t stream);
 hipError_t launch_couplings(int8_t* J, uint32_t L, uint32_t d, uint64_t N, uint64_t cseed,
                             uint32_t realisation, hipStream_t stream);
 hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t stream);
-// Adds E and M of the lattice into *E, *M (which must hold 0 beforehand).
-hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t stream);
+// E and M of the lattice into rec.E, rec.M.
+hipError_t launch_measure(const Lat& lat, const Record& rec, hipStream_t stream);
 
 // One colour phase with the per-site generic kernel, any even L.
 hipError_t launch_generic_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
@@ -62,8 +76,11 @@ bool tiled_supported(const Lat& lat, const Tile& tile);
 hipError_t launch_tiled_phase(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc,
                               const Tile& tile, hipStream_t stream);
 // One whole sweep of a 2D Ising lattice from `src` into `dst` (ping-pong).
+// With rec != nullptr the sweep also records E, M of its result if the
+// kernel can (returns true in *measured), else the caller measures.
 bool fused_supported(const Lat& lat, const Tile& tile);
 hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
-                              const Accept& acc, const Tile& tile, hipStream_t stream);
+                              const Accept& acc, const Tile& tile, const Record* rec,
+                              bool* measured, hipStream_t stream);
 
 }  // namespace spin

@@ -159,28 +159,22 @@ __device__ __forceinline__ void generic_group(int8_t* sp, const int8_t* __restri
 template <int NT>
 __global__ __launch_bounds__(NT) void k_measure_sites(const int8_t* __restrict__ sp,
                                                       const int8_t* __restrict__ J, uint32_t L,
-                                                      uint32_t d, uint64_t N, int64_t* E,
-                                                      int64_t* M) {
+                                                      uint32_t d, uint64_t N, Record rec) {
   __shared__ int64_t red[NT / 64];
-  int64_t e = 0, m = 0;
+  int64_t unsat = 0, neg = 0;
   for (uint64_t s = blockIdx.x * (uint64_t)NT + threadIdx.x; s < N; s += (uint64_t)gridDim.x * NT) {
     const Site c = site_coords(s, L, d);
     const uint32_t cd[3] = {c.x, c.y, c.z};
     uint64_t st = 1;
     const int si = sp[s];
-    m += si;
+    neg += (si < 0);
     for (uint32_t dir = 0; dir < d; ++dir) {
       const uint64_t up = nb_plus(s, cd[dir], L, st);
-      e -= (int64_t)(J ? J[dir * N + s] : 1) * si * sp[up];
+      unsat += ((J ? J[dir * N + s] : 1) * si * sp[up] < 0);
       st *= L;
     }
   }
-  const int64_t be = block_sum<NT>(e, red);
-  const int64_t bm = block_sum<NT>(m, red);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)E, (unsigned long long)be);
-    atomicAdd((unsigned long long*)M, (unsigned long long)bm);
-  }
+  record_block<NT>(unsat, neg, rec, red);
 }
 
 // Row-structured version (L % 16 == 0): each workgroup takes RPB lattice rows
@@ -191,7 +185,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ sp,
                                                      const int8_t* __restrict__ J, uint32_t L,
                                                      uint32_t d, uint64_t N, uint32_t nrows,
-                                                     uint32_t rpb, int64_t* E, int64_t* M) {
+                                                     uint32_t rpb, Record rec) {
   __shared__ int64_t red[NT / 64];
   const uint32_t msb = 0x80808080u;
   const uint32_t cpr = L / 16;
@@ -233,23 +227,10 @@ __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ 
       }
     }
   }
-  // per site: E part = sum_dir (-1 + 2 unsat_dir), M part = 1 - 2 neg; constants added later
-  const int64_t bu = block_sum<NT>(unsat, red);
-  const int64_t bn = block_sum<NT>(neg, red);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)E, (unsigned long long)(2 * bu));
-    atomicAdd((unsigned long long*)M, (unsigned long long)(-2 * bn));
-  }
+  record_block<NT>(unsat, neg, rec, red);
 }
 
-__global__ void k_add_const(int64_t* E, int64_t* M, int64_t e0, int64_t m0) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *E += e0;
-    *M += m0;
-  }
-}
-
-hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t stream) {
+hipError_t launch_measure(const Lat& lat, const Record& rec, hipStream_t stream) {
   constexpr int NT = 256;
   if (lat.L % 16 == 0) {
     const uint32_t nrows = (uint32_t)(lat.N / lat.L);
@@ -258,16 +239,11 @@ hipError_t launch_measure(const Lat& lat, int64_t* E, int64_t* M, hipStream_t st
     if (rpb < 1) rpb = 1;
     const uint32_t blocks = (nrows + rpb - 1) / rpb;
     hipLaunchKernelGGL(k_measure_rows<NT>, dim3(blocks), dim3(NT), 0, stream, (const int8_t*)lat.spins,
-                       lat.J, lat.L, lat.d, lat.N, nrows, rpb, E, M);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // constants: E = -d N + 2 unsat, M = N - 2 neg
-    hipLaunchKernelGGL(k_add_const, dim3(1), dim3(64), 0, stream, E, M,
-                       -(int64_t)lat.d * (int64_t)lat.N, (int64_t)lat.N);
+                       lat.J, lat.L, lat.d, lat.N, nrows, rpb, rec);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_measure_sites<NT>, dim3(grid_for(lat.N, NT, 4096)), dim3(NT), 0, stream,
-                     (const int8_t*)lat.spins, lat.J, lat.L, lat.d, lat.N, E, M);
+                     (const int8_t*)lat.spins, lat.J, lat.L, lat.d, lat.N, rec);
   return hipGetLastError();
 }
 
@@ -682,6 +658,8 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
   __syncthreads();
   const uint32_t gq = (x0 >> 3) + (uint32_t)lane;  // counter word of this lane's group, minus row part
   const uint32_t Lg = L >> 3;                      // groups per lattice row
+  const PhiloxUniform U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
+  const PhiloxUniform U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
   // ---- phase 0: colour 0, tile columns, LDS rows 1..TH+2 (wave-strided)
   {
     const int r_first = 1 + wave;
@@ -696,7 +674,7 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
       const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
       const uint32_t y = wrap_row(y0 + (uint32_t)r, 2u, L);
       uint32_t rnd[4];
-      philox(y * Lg + gq, a.t, a.replica, 0u, a.keys, rnd);
+      philox_lane(y * Lg + gq, U0, a.keys, rnd);
       const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
       uint32_t S0, S1;
       unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
@@ -718,7 +696,7 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
     const uint32_t y = y0 + (uint32_t)r - 2u;
     const uint32_t x = wrap_row(x0 + 8 * j, 16u, L);
     uint32_t rnd[4];
-    philox(y * Lg + (x >> 3), a.t, a.replica, 0u, a.keys, rnd);
+    philox_lane(y * Lg + (x >> 3), U0, a.keys, rnd);
     const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
     uint32_t S0, S1;
     unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
@@ -742,7 +720,7 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
       const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8);
       const uint32_t y = y0 + (uint32_t)r - 2u;
       uint32_t rnd[4];
-      philox(y * Lg + gq, a.t, a.replica, 1u, a.keys, rnd);
+      philox_lane(y * Lg + gq, U1, a.keys, rnd);
       const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
       uint32_t S0, S1;
       unsat_ising<2>(c.x, c.y, lw, rw, o0, o1, S0, S1);
@@ -799,8 +777,9 @@ struct StreamCtx {
   }
 };
 
-template <int NT, int G, bool NEVER, uint32_t S>
-__device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t i) {
+template <int NT, int G, bool NEVER, bool MEAS, uint32_t S>
+__device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t i, int& unsat,
+                                            int& neg) {
   using C = StreamCtx<NT, G>;
   constexpr uint32_t L = C::L, GPR = C::GPR, RBS = C::RBS;
   const uint32_t H = c.H, y0 = c.y0, t = c.t;
@@ -837,7 +816,7 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
   if (i >= 3) {
     // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1
     const uint32_t y = y0 + i - 3u;
-    const int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
+    int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
     const int8_t* up = c.ring + ((S + 6) & 7) * RBS + 16;
     const int8_t* dn = c.ring + (S & 7) * RBS + 16;
     int8_t* out = c.dst + (uint64_t)y * L;
@@ -857,16 +836,41 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
       uint32_t c0 = cc.x, c1 = cc.y;
       apply_group_p<S & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
       *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(c0, c1);
+      if (MEAS) {
+        // E and M of the swept lattice, counted on final values:
+        //  - row b's negative spins;
+        //  - bonds (b-1, b): row b-1 in LDS is final when b > y0 (written by the
+        //    previous step); for b == y0 it is the ring row y0-1 whose colour-0
+        //    bytes only are final, so only bonds whose row-b end is colour 1
+        //    are counted (the strip above counts the others);
+        //  - for the last row, bonds to the ring row y0+H, same rule;
+        //  - horizontal bonds of row b-1 (final in LDS);
+        // and row b's final bytes go to LDS for the next step.
+        constexpr uint32_t kMsb = 0x80808080u;
+        constexpr uint32_t kCol1 = (S & 1) ? 0x80008000u : 0x00800080u;  // colour-1 bytes of row b
+        *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
+        if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
+        if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
+        neg += __popc(c0 & kMsb) + __popc(c1 & kMsb);
+        const uint32_t vm = (i == 3) ? kCol1 : kMsb;
+        unsat += __popc((c0 ^ u2.x) & vm) + __popc((c1 ^ u2.y) & vm);
+        if (i == H + 2) unsat += __popc((c0 ^ d2.x) & kCol1) + __popc((c1 ^ d2.y) & kCol1);
+        if (i >= 4) {
+          const uint32_t nx = *reinterpret_cast<const uint32_t*>(up + 8 * g + 8);
+          unsat += __popc((u2.x ^ __builtin_amdgcn_alignbyte(u2.y, u2.x, 1)) & kMsb) +
+                   __popc((u2.y ^ __builtin_amdgcn_alignbyte(nx, u2.y, 1)) & kMsb);
+        }
+      }
     }
   }
   if (do_load) c.put_row((S + 3) & 7, nxt);
   __syncthreads();
 }
 
-template <int NT, int G, bool NEVER>
+template <int NT, int G, bool NEVER, bool MEAS>
 __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
                                                  int8_t* __restrict__ dst, PhaseArgs a,
-                                                 uint32_t H) {
+                                                 uint32_t H, Record rec) {
   using C = StreamCtx<NT, G>;
   // one LDS block: the bound table at byte 0 (a lookup address is just 4u),
   // then the 8-row ring
@@ -892,15 +896,30 @@ __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
   }
   __syncthreads();
   const uint32_t steps = H + 3;
+  int unsat = 0, neg = 0;
   for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
-    stream_step<NT, G, NEVER, 0>(c, i0 + 0);
-    stream_step<NT, G, NEVER, 1>(c, i0 + 1);
-    stream_step<NT, G, NEVER, 2>(c, i0 + 2);
-    stream_step<NT, G, NEVER, 3>(c, i0 + 3);
-    stream_step<NT, G, NEVER, 4>(c, i0 + 4);
-    stream_step<NT, G, NEVER, 5>(c, i0 + 5);
-    stream_step<NT, G, NEVER, 6>(c, i0 + 6);
-    stream_step<NT, G, NEVER, 7>(c, i0 + 7);
+    stream_step<NT, G, NEVER, MEAS, 0>(c, i0 + 0, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 1>(c, i0 + 1, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 2>(c, i0 + 2, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 3>(c, i0 + 3, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 4>(c, i0 + 4, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 5>(c, i0 + 5, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 6>(c, i0 + 6, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 7>(c, i0 + 7, unsat, neg);
+  }
+  if (MEAS) {
+    // horizontal bonds of the strip's last row (final in LDS, strip row k = H + 1)
+    const int8_t* last = c.ring + ((H + 1) & 7) * C::RBS + 16;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = c.t + NT * j;
+      const uint2 v = *reinterpret_cast<const uint2*>(last + 8 * g);
+      const uint32_t nx = *reinterpret_cast<const uint32_t*>(last + 8 * g + 8);
+      unsat += __popc((v.x ^ __builtin_amdgcn_alignbyte(v.y, v.x, 1)) & 0x80808080u) +
+               __popc((v.y ^ __builtin_amdgcn_alignbyte(nx, v.y, 1)) & 0x80808080u);
+    }
+    __shared__ int64_t red[NT / 64];
+    record_block<NT>(unsat, neg, rec, red);
   }
 }
 
@@ -956,17 +975,27 @@ static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const 
 
 template <int NT, int G>
 static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
-                           bool never, uint32_t H, hipStream_t stream) {
+                           bool never, uint32_t H, const Record* rec, hipStream_t stream) {
   dim3 grid(lat.L / H);
-  if (never)
-    hipLaunchKernelGGL((k_stream2d<NT, G, true>), grid, dim3(NT), 0, stream, src, dst, a, H);
-  else
-    hipLaunchKernelGGL((k_stream2d<NT, G, false>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  const Record r = rec ? *rec : Record{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  if (rec) {
+    if (never)
+      hipLaunchKernelGGL((k_stream2d<NT, G, true, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2d<NT, G, false, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  } else {
+    if (never)
+      hipLaunchKernelGGL((k_stream2d<NT, G, true, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2d<NT, G, false, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
-                              const Accept& acc, const Tile& tile, hipStream_t stream) {
+                              const Accept& acc, const Tile& tile, const Record* rec,
+                              bool* measured, hipStream_t stream) {
+  if (measured) *measured = false;
   if (!fused_supported(lat, tile)) return hipErrorInvalidValue;
   const PhaseArgs a = phase_args(lat, t, 0u, acc);
   const bool never = acc.never_level > 0;
@@ -974,11 +1003,12 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
     int G = 0;
     stream_shape(lat.L, tile.threads, &G);
     const uint32_t H = (uint32_t)tile.y;
-    if (tile.threads == 1024 && G == 1) return gostream<1024, 1>(lat, src, dst, a, never, H, stream);
-    if (tile.threads == 1024 && G == 2) return gostream<1024, 2>(lat, src, dst, a, never, H, stream);
-    if (tile.threads == 512 && G == 1) return gostream<512, 1>(lat, src, dst, a, never, H, stream);
-    if (tile.threads == 512 && G == 2) return gostream<512, 2>(lat, src, dst, a, never, H, stream);
-    return gostream<256, 2>(lat, src, dst, a, never, H, stream);
+    if (measured) *measured = (rec != nullptr);
+    if (tile.threads == 1024 && G == 1) return gostream<1024, 1>(lat, src, dst, a, never, H, rec, stream);
+    if (tile.threads == 1024 && G == 2) return gostream<1024, 2>(lat, src, dst, a, never, H, rec, stream);
+    if (tile.threads == 512 && G == 1) return gostream<512, 1>(lat, src, dst, a, never, H, rec, stream);
+    if (tile.threads == 512 && G == 2) return gostream<512, 2>(lat, src, dst, a, never, H, rec, stream);
+    return gostream<256, 2>(lat, src, dst, a, never, H, rec, stream);
   }
   if (tile.x == 512 && tile.threads == 256) {
     if (tile.y == 16) return gofused_w<16>(lat, src, dst, a, never, stream);

@@ -115,7 +115,9 @@ struct spin_lattice {
   int8_t* buf[2];
   int cur;
   int8_t* J;
-  int64_t* em;  // 2 int64 for spin_measure
+  int64_t* em;       // 2 int64: spin_measure's output
+  int64_t* acc;      // 2 int64 + 1 uint32: record accumulators (zero between kernels)
+  uint32_t* counter;
   uint64_t seed;
   uint32_t replica;
   uint64_t t;
@@ -158,6 +160,7 @@ static void destroy(spin_lattice* h) {
   h->mem.put(h->buf[1]);
   h->mem.put(h->J);
   h->mem.put(h->em);
+  h->mem.put(h->acc);
   delete h;
 }
 
@@ -223,6 +226,10 @@ static int resolve(const spin_lattice* h, Tile* tile) {
   return SPIN_KERNEL_GENERIC;
 }
 
+static Record record_into(const spin_lattice* h, int64_t* E, int64_t* M) {
+  return Record{h->acc, h->counter, E, M, -(int64_t)h->d * (int64_t)h->N, (int64_t)h->N};
+}
+
 static int check_beta(double beta) {
   if (std::isnan(beta) || beta < 0) return fail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
   return SPIN_OK;
@@ -239,11 +246,6 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   Tile tile;
   const int kernel = resolve(h, &tile);
   hipError_t e = hipSuccess;
-  const int nrec = every > 0 ? n / every : 0;
-  if (nrec > 0) {
-    if ((e = launch_zero(dE, (uint64_t)nrec, h->stream)) != hipSuccess) return hip_fail(e, "zero");
-    if ((e = launch_zero(dM, (uint64_t)nrec, h->stream)) != hipSuccess) return hip_fail(e, "zero");
-  }
   if (kernel == SPIN_KERNEL_RESIDENT) {
     const Lat l = lat_of(h);
     e = launch_resident(l, (uint32_t)h->t, n, acc, every, dE, dM, tile.threads, h->stream);
@@ -259,8 +261,12 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   for (int i = 0; i < n; ++i) {
     const uint32_t t = (uint32_t)(h->t + (uint64_t)i);
     Lat l = lat_of(h);
+    const bool record_now = every > 0 && (i + 1) % every == 0;
+    const Record r = record_into(h, record_now ? dE + rec : nullptr, record_now ? dM + rec : nullptr);
+    bool measured = false;
     if (kernel == SPIN_KERNEL_FUSED) {
-      e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile, h->stream);
+      e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile,
+                             record_now ? &r : nullptr, &measured, h->stream);
       if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
       h->cur = 1 - h->cur;
     } else {
@@ -270,9 +276,11 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
         if (e != hipSuccess) return hip_fail(e, "colour phase launch");
       }
     }
-    if (every > 0 && (i + 1) % every == 0) {
-      e = launch_measure(lat_of(h), dE + rec, dM + rec, h->stream);
-      if (e != hipSuccess) return hip_fail(e, "measure launch");
+    if (record_now) {
+      if (!measured) {
+        e = launch_measure(lat_of(h), r, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "measure launch");
+      }
       ++rec;
     }
   }
@@ -338,14 +346,23 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   h->kernel = SPIN_KERNEL_AUTO;
   h->tile = Tile{0, 0, 0, 0};
   h->mem = Allocator{g_alloc, g_release, g_ctx};
+  h->acc = nullptr;
+  h->counter = nullptr;
   h->buf[0] = (int8_t*)h->mem.get(N);
   h->em = (int64_t*)h->mem.get(2 * sizeof(int64_t));
-  if (!h->buf[0] || !h->em) {
+  h->acc = (int64_t*)h->mem.get(4 * sizeof(int64_t));
+  if (!h->buf[0] || !h->em || !h->acc) {
     fail(SPIN_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)N);
     destroy(h);
     return nullptr;
   }
-  hipError_t e;
+  h->counter = reinterpret_cast<uint32_t*>(h->acc + 2);
+  hipError_t e = launch_zero(h->acc, 4, h->stream);
+  if (e != hipSuccess) {
+    hip_fail(e, "zero accumulators");
+    destroy(h);
+    return nullptr;
+  }
   if (h->model == SPIN_EA_PMJ) {
     h->J = (int8_t*)h->mem.get((size_t)cfg->d * N);
     if (!h->J) {
@@ -430,8 +447,7 @@ int spin_sweep_record(spin_lattice* h, int n, double beta, int every, int64_t* E
 
 int spin_measure(spin_lattice* h, int64_t* E, int64_t* M) {
   if (!h || !E || !M) return fail(SPIN_EINVAL, "NULL argument");
-  hipError_t e = launch_zero(h->em, 2, h->stream);
-  if (e == hipSuccess) e = launch_measure(lat_of(h), h->em, h->em + 1, h->stream);
+  hipError_t e = launch_measure(lat_of(h), record_into(h, h->em, h->em + 1), h->stream);
   int64_t v[2];
   if (e == hipSuccess) e = hipMemcpyAsync(v, h->em, sizeof(v), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

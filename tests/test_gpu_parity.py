@@ -221,7 +221,7 @@ def test_torch_allocator(oracle_mod, gpu):
 ])
 def test_ising2d_streaming_rows(oracle_mod, tile, L):
     """Row-streaming fused kernel: several strips, wrap rows, beta with T == 0 entries."""
-    sched = [(2, B_CRIT, 1), (1, 3.0, 1)]
+    sched = [(2, B_CRIT, 1), (1, 3.0, 1), (4, 0.6, 2), (1, 0.0, 0)]
     compare_runs(oracle_mod, 0, L, 2, workloads.seed(60 + L), sched, replica=4, kernel=FUS, tile=tile,
                  tag="stream")
 
