@@ -188,29 +188,17 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* scratch /* NT/6
   return s;
 }
 
-// Add this workgroup's counts to the record; the last workgroup writes it.
-// Every thread calls it (it contains barriers).  red: >= NT/64 int64 in LDS.
+// Store this workgroup's counts in its record slots.  Every thread calls it
+// (it contains barriers).  red: >= NT/64 int64 in LDS.
 template <int NT>
 __device__ __forceinline__ void record_block(int64_t unsat, int64_t neg, const Record& R,
                                              int64_t* red) {
   const int64_t bu = block_sum<NT>(unsat, red);
   const int64_t bn = block_sum<NT>(neg, red);
   if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&R.acc[0], (unsigned long long)bu);
-    atomicAdd((unsigned long long*)&R.acc[1], (unsigned long long)bn);
-    __threadfence();
-    const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
-    const unsigned prev = atomicAdd(R.counter, 1u);
-    if (prev == nblocks - 1) {
-      __threadfence();
-      const int64_t u = (int64_t)atomicAdd((unsigned long long*)&R.acc[0], 0ull);
-      const int64_t n = (int64_t)atomicAdd((unsigned long long*)&R.acc[1], 0ull);
-      *R.E = R.e0 + 2 * u;
-      *R.M = R.m0 - 2 * n;
-      atomicExch((unsigned long long*)&R.acc[0], 0ull);
-      atomicExch((unsigned long long*)&R.acc[1], 0ull);
-      atomicExch(R.counter, 0u);
-    }
+    const unsigned wg = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    R.part[2 * wg] = bu;
+    R.part[2 * wg + 1] = bn;
   }
 }
 

@@ -36,31 +36,34 @@ struct Lat {
 RoundKeys make_round_keys(uint64_t seed);
 Accept make_accept(double beta, int d);
 
-// Where one (E, M) record goes.  Kernels add their partial counts into
-// acc[0] (unsatisfied bonds) and acc[1] (negative spins) with device-scope
-// atomics; the last workgroup to finish writes E = e0 + 2*acc[0] and
-// M = m0 - 2*acc[1] to *E, *M and resets acc and counter to 0 (they must be
-// 0 when the kernel starts: the library zeroes them once at creation).
-struct Record {
-  int64_t* acc;       // 2 int64
-  uint32_t* counter;  // 1 uint32
-  int64_t* E;
-  int64_t* M;
-  int64_t e0;         // -d*N
-  int64_t m0;         // N
-};
-
 // Kernel tile shapes (bytes along x, rows along y, planes along z, threads).
 struct Tile {
   int x, y, z, threads;
 };
+
+// Where one (E, M) record goes: every workgroup of the kernel that counts it
+// stores its partial counts (unsatisfied bonds, negative spins) in
+// part[2*wg], part[2*wg + 1]; launch_finalize later turns them into
+// E = -d*N + 2*sum(unsat) and M = N - 2*sum(neg).  No atomics.
+struct Record {
+  int64_t* part;
+};
+
+// Number of partial slots (workgroups) a record of this lattice uses when it
+// is counted by the measure kernel, or by the fused kernel with this tile.
+uint32_t measure_parts(const Lat& lat);
+uint32_t fused_record_parts(const Lat& lat, const Tile& tile);  // 0: the kernel cannot count
+// nrec records, record r's partials at part + r*stride*2 (nparts used), into
+// E[r], M[r] (device arrays).
+hipError_t launch_finalize(const int64_t* part, uint32_t stride, uint32_t nparts, uint32_t nrec,
+                           int64_t* E, int64_t* M, int64_t e0, int64_t m0, hipStream_t stream);
 
 // ---- launchers (all asynchronous on `stream`, return the launch status) ----
 hipError_t launch_init_spins(const Lat& lat, hipStream_t stream);
 hipError_t launch_couplings(int8_t* J, uint32_t L, uint32_t d, uint64_t N, uint64_t cseed,
                             uint32_t realisation, hipStream_t stream);
 hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t stream);
-// E and M of the lattice into rec.E, rec.M.
+// Partial E/M counts of the lattice into rec (measure_parts(lat) slots).
 hipError_t launch_measure(const Lat& lat, const Record& rec, hipStream_t stream);
 
 // One colour phase with the per-site generic kernel, any even L.

@@ -230,20 +230,58 @@ __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ 
   record_block<NT>(unsat, neg, rec, red);
 }
 
+static uint32_t measure_rows_per_block(const Lat& lat) {
+  const uint32_t nrows = (uint32_t)(lat.N / lat.L);
+  uint32_t rpb = (nrows + 2047) / 2048;  // about 2048 workgroups, whole rows each
+  return rpb < 1 ? 1 : rpb;
+}
+
+uint32_t measure_parts(const Lat& lat) {
+  if (lat.L % 16 == 0) {
+    const uint32_t nrows = (uint32_t)(lat.N / lat.L);
+    const uint32_t rpb = measure_rows_per_block(lat);
+    return (nrows + rpb - 1) / rpb;
+  }
+  return grid_for(lat.N, 256, 4096);
+}
+
 hipError_t launch_measure(const Lat& lat, const Record& rec, hipStream_t stream) {
   constexpr int NT = 256;
   if (lat.L % 16 == 0) {
     const uint32_t nrows = (uint32_t)(lat.N / lat.L);
-    // about 2048 workgroups, whole rows each
-    uint32_t rpb = (nrows + 2047) / 2048;
-    if (rpb < 1) rpb = 1;
-    const uint32_t blocks = (nrows + rpb - 1) / rpb;
-    hipLaunchKernelGGL(k_measure_rows<NT>, dim3(blocks), dim3(NT), 0, stream, (const int8_t*)lat.spins,
-                       lat.J, lat.L, lat.d, lat.N, nrows, rpb, rec);
+    const uint32_t rpb = measure_rows_per_block(lat);
+    hipLaunchKernelGGL(k_measure_rows<NT>, dim3(measure_parts(lat)), dim3(NT), 0, stream,
+                       (const int8_t*)lat.spins, lat.J, lat.L, lat.d, lat.N, nrows, rpb, rec);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_measure_sites<NT>, dim3(grid_for(lat.N, NT, 4096)), dim3(NT), 0, stream,
+  hipLaunchKernelGGL(k_measure_sites<NT>, dim3(measure_parts(lat)), dim3(NT), 0, stream,
                      (const int8_t*)lat.spins, lat.J, lat.L, lat.d, lat.N, rec);
+  return hipGetLastError();
+}
+
+// One workgroup per record: sum the partial counts, write E and M.
+__global__ __launch_bounds__(256) void k_finalize(const int64_t* __restrict__ part, uint32_t stride,
+                                                  uint32_t nparts, int64_t* E, int64_t* M,
+                                                  int64_t e0, int64_t m0) {
+  __shared__ int64_t red[4];
+  const int64_t* p = part + (uint64_t)blockIdx.x * stride * 2;
+  int64_t u = 0, n = 0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += 256) {
+    u += p[2 * i];
+    n += p[2 * i + 1];
+  }
+  const int64_t su = block_sum<256>(u, red);
+  const int64_t sn = block_sum<256>(n, red);
+  if (threadIdx.x == 0) {
+    E[blockIdx.x] = e0 + 2 * su;
+    M[blockIdx.x] = m0 - 2 * sn;
+  }
+}
+
+hipError_t launch_finalize(const int64_t* part, uint32_t stride, uint32_t nparts, uint32_t nrec,
+                           int64_t* E, int64_t* M, int64_t e0, int64_t m0, hipStream_t stream) {
+  if (nrec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nrec), dim3(256), 0, stream, part, stride, nparts, E, M, e0, m0);
   return hipGetLastError();
 }
 
@@ -973,11 +1011,17 @@ static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const 
   return hipGetLastError();
 }
 
+uint32_t fused_record_parts(const Lat& lat, const Tile& tile) {
+  if (!fused_supported(lat, tile)) return 0;
+  if ((uint32_t)tile.x == lat.L && tile.x >= 4096) return lat.L / (uint32_t)tile.y;
+  return 0;
+}
+
 template <int NT, int G>
 static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
                            bool never, uint32_t H, const Record* rec, hipStream_t stream) {
   dim3 grid(lat.L / H);
-  const Record r = rec ? *rec : Record{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  const Record r = rec ? *rec : Record{nullptr};
   if (rec) {
     if (never)
       hipLaunchKernelGGL((k_stream2d<NT, G, true, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);

@@ -116,8 +116,8 @@ struct spin_lattice {
   int cur;
   int8_t* J;
   int64_t* em;       // 2 int64: spin_measure's output
-  int64_t* acc;      // 2 int64 + 1 uint32: record accumulators (zero between kernels)
-  uint32_t* counter;
+  int64_t* part;     // partial counts of records (grown on demand)
+  size_t part_slots; // capacity in int64
   uint64_t seed;
   uint32_t replica;
   uint64_t t;
@@ -160,7 +160,7 @@ static void destroy(spin_lattice* h) {
   h->mem.put(h->buf[1]);
   h->mem.put(h->J);
   h->mem.put(h->em);
-  h->mem.put(h->acc);
+  h->mem.put(h->part);
   delete h;
 }
 
@@ -226,9 +226,19 @@ static int resolve(const spin_lattice* h, Tile* tile) {
   return SPIN_KERNEL_GENERIC;
 }
 
-static Record record_into(const spin_lattice* h, int64_t* E, int64_t* M) {
-  return Record{h->acc, h->counter, E, M, -(int64_t)h->d * (int64_t)h->N, (int64_t)h->N};
+// Make room for nrec records of `parts` slots each.
+static int reserve_parts(spin_lattice* h, uint32_t nrec, uint32_t parts) {
+  const size_t need = (size_t)nrec * parts * 2;
+  if (need <= h->part_slots) return SPIN_OK;
+  (void)hipStreamSynchronize(h->stream);
+  h->mem.put(h->part);
+  h->part = (int64_t*)h->mem.get(need * sizeof(int64_t));
+  h->part_slots = h->part ? need : 0;
+  if (!h->part) return fail(SPIN_ENOMEM, "record buffer allocation failed");
+  return SPIN_OK;
 }
+
+static int64_t e_offset(const spin_lattice* h) { return -(int64_t)h->d * (int64_t)h->N; }
 
 static int check_beta(double beta) {
   if (std::isnan(beta) || beta < 0) return fail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
@@ -257,12 +267,18 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
     h->buf[1] = (int8_t*)h->mem.get(h->N);
     if (!h->buf[1]) return fail(SPIN_ENOMEM, "allocation of the second spin buffer failed");
   }
+  // records: partial counts per workgroup, reduced by one kernel at the end
+  const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
+  const uint32_t fparts = (kernel == SPIN_KERNEL_FUSED) ? fused_record_parts(lat_of(h), tile) : 0;
+  const uint32_t parts = fparts ? fparts : measure_parts(lat_of(h));
+  if (nrec > 0)
+    if (int rc = reserve_parts(h, nrec, parts)) return rc;
   int rec = 0;
   for (int i = 0; i < n; ++i) {
     const uint32_t t = (uint32_t)(h->t + (uint64_t)i);
     Lat l = lat_of(h);
     const bool record_now = every > 0 && (i + 1) % every == 0;
-    const Record r = record_into(h, record_now ? dE + rec : nullptr, record_now ? dM + rec : nullptr);
+    const Record r = Record{record_now ? h->part + (size_t)rec * parts * 2 : nullptr};
     bool measured = false;
     if (kernel == SPIN_KERNEL_FUSED) {
       e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile,
@@ -283,6 +299,10 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
       }
       ++rec;
     }
+  }
+  if (nrec > 0) {
+    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "record finalize launch");
   }
   h->t += (uint64_t)n;
   return SPIN_OK;
@@ -346,23 +366,16 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   h->kernel = SPIN_KERNEL_AUTO;
   h->tile = Tile{0, 0, 0, 0};
   h->mem = Allocator{g_alloc, g_release, g_ctx};
-  h->acc = nullptr;
-  h->counter = nullptr;
+  h->part = nullptr;
+  h->part_slots = 0;
   h->buf[0] = (int8_t*)h->mem.get(N);
   h->em = (int64_t*)h->mem.get(2 * sizeof(int64_t));
-  h->acc = (int64_t*)h->mem.get(4 * sizeof(int64_t));
-  if (!h->buf[0] || !h->em || !h->acc) {
+  if (!h->buf[0] || !h->em) {
     fail(SPIN_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)N);
     destroy(h);
     return nullptr;
   }
-  h->counter = reinterpret_cast<uint32_t*>(h->acc + 2);
-  hipError_t e = launch_zero(h->acc, 4, h->stream);
-  if (e != hipSuccess) {
-    hip_fail(e, "zero accumulators");
-    destroy(h);
-    return nullptr;
-  }
+  hipError_t e = hipSuccess;
   if (h->model == SPIN_EA_PMJ) {
     h->J = (int8_t*)h->mem.get((size_t)cfg->d * N);
     if (!h->J) {
@@ -447,7 +460,11 @@ int spin_sweep_record(spin_lattice* h, int n, double beta, int every, int64_t* E
 
 int spin_measure(spin_lattice* h, int64_t* E, int64_t* M) {
   if (!h || !E || !M) return fail(SPIN_EINVAL, "NULL argument");
-  hipError_t e = launch_measure(lat_of(h), record_into(h, h->em, h->em + 1), h->stream);
+  const uint32_t parts = measure_parts(lat_of(h));
+  if (int rc = reserve_parts(h, 1, parts)) return rc;
+  hipError_t e = launch_measure(lat_of(h), Record{h->part}, h->stream);
+  if (e == hipSuccess)
+    e = launch_finalize(h->part, parts, parts, 1, h->em, h->em + 1, e_offset(h), (int64_t)h->N, h->stream);
   int64_t v[2];
   if (e == hipSuccess) e = hipMemcpyAsync(v, h->em, sizeof(v), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
