@@ -1,32 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the checkerboard Metropolis path on one MI355X.
 
-Workload (default ``ising2d_L8192``): three 2D Ising lattices, L = 8192
+Default workload ``ising2d_L8192``: three 2D Ising lattices, L = 8192
 (67,108,864 int8 spins each), one per inverse temperature 0.30, 0.4406868 and
-0.60, all from the same seeded hot start; one *step* advances each lattice
+0.60, all from the same seeded hot start.  One *step* advances each lattice
 by 10 sweeps and records E and M once (the recording cadence of the
-workload).  200 steps are the whole 2000-sweep job.  Lattices are created
-and initialised before the timed region (inputs resident in HBM).
+workload), so the default 200 steps are the whole 2000-sweep job.  Lattices
+are created and initialised before the timed region (inputs resident in HBM).
 
-Printed: one JSON line with the whole-job throughput (spin-flip attempts
-per ns, measurement included), the sweep-only rate, the roofline of the
-dominant kernel (timed with HIP events on the stream it runs on) and the CPU
-oracle timed on a bounded sample.
+Printed: one JSON line with the whole-job throughput (spin-flip attempts per
+ns, measurement included), the sweep-only rate (measurement excluded, the
+paper's timing convention), the roofline of the dominant kernel (its launch
+duration timed with HIP events on the stream it runs on) and the CPU oracle
+timed on a bounded sample of the same workload.
 
 ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (32-bit lane ops)
-PHILOX_OPS_PER_ATTEMPT = 10.0    # 10 rounds x (2 mul-hi/lo + 2 three-way xor) per 4 words
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit lane op per lane per clock
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic 32-bit lane operations per spin-flip attempt: Philox4x32-10 gives 4 words per
+# 10 rounds of (2 32x32->64 multiplies + 2 three-input XORs) = 10 per attempt; the update of an
+# 8-site group (4 attempts) takes 4 byte alignments, 2d mask-XORs, 2d-2 byte adds... for 2D:
+# 4 + 8 + 4 sums + 4 x (extract, compare, select) + 2 flip XORs + 1 counter = 31 -> 7.75.
+ALG_OPS_PER_ATTEMPT = {2: 10.0 + 31 / 4.0, 3: 10.0 + (4 + 12 + 8 + 12 + 2 + 1) / 4.0}
+BYTES_PER_ATTEMPT = 2.0  # int8 spin read once and written once per sweep (Ising)
 
 
 def parse():
@@ -43,25 +52,49 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("spin_kernels.hip", "spin_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1006_3865_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel_tag, L):
+    """HBM bytes per launch from the committed rocprofv3 summary, if the kernel is unchanged."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    sha = kernel_sources_sha()
+    for f in sorted(os.listdir(pdir)):
+        if not f.endswith(".md"):
+            continue
+        for line in open(os.path.join(pdir, f)):
+            m = re.match(r"traffic-record: kernel=(\S+) L=(\d+) bytes_per_launch=(\d+) source_sha256=(\w+)", line)
+            if m and m.group(1) == kernel_tag and int(m.group(2)) == L and m.group(4) == sha:
+                return int(m.group(3))
+    return None
+
+
 def cpu_baseline(cfg, seconds_hint):
     """The C oracle, single-threaded, on a bounded sample of the workload."""
-    import numpy as np
     import oracle
     L, d = cfg["L"], cfg["d"]
     n_sweeps = 2 if L ** d >= 1 << 26 else (20 if L ** d >= 1 << 20 else 200)
     attempts = 0
+    used = 0
     t0 = time.perf_counter()
     for b in cfg["betas"]:
         ch = oracle.Chain(L, d, cfg["seed"])
-        tb = time.perf_counter()
         ch.sweep(n_sweeps, b, every=max(1, min(cfg["every"], n_sweeps)))
         attempts += n_sweeps * L ** d
+        used += 1
         if time.perf_counter() - t0 > seconds_hint:
             break
     dt = time.perf_counter() - t0
-    return {"value": attempts / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": 1, "kind": "oracle",
-            "sample": "%d sweeps (E/M recorded) of the L=%d d=%d lattice at each of %d betas, from the hot start; "
-                      "%.1f s" % (n_sweeps, L, d, len(cfg["betas"]), dt)}
+    return {"value": round(attempts / (dt * 1e9), 5), "unit": "spin-flip attempts/ns", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d sweeps (E/M recorded) of the L=%d d=%d lattice from the hot start at each of %d "
+                      "beta(s); %.1f s on one host core" % (n_sweeps, L, d, used, dt)}
 
 
 def main():
@@ -92,37 +125,31 @@ def main():
             lat.set_kernel(kern, *tile)
         lats.append((lat, b))
     kname = spin.KERNEL_NAMES[lats[0][0].kernel]
-    nrec = args.steps * sweeps_per_step // every
+    recs_per_step = sweeps_per_step // every
+    nrec = args.steps * recs_per_step
     Erec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
     Mrec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
     stream.wait_stream(torch.cuda.current_stream())
     for lat, _ in lats:
         lat.synchronize()
 
-    # warmup (advances the same chains; costs are state-independent)
+    # warmup (advances the same chains; the kernels' cost does not depend on the state)
     for i in range(args.warmup):
         for lat, b in lats:
             lat.sweep(sweeps_per_step, b)
     torch.cuda.synchronize()
 
-    events = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         for j, (lat, b) in enumerate(lats):
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev0.record(stream)
-            lat.sweep_record_device(sweeps_per_step, b, every, Erec[j][i * (sweeps_per_step // every):],
-                                    Mrec[j][i * (sweeps_per_step // every):])
-            ev1 = torch.cuda.Event(enable_timing=True)
-            ev1.record(stream)
-            events.append((ev0, ev1))
+            lat.sweep_record_device(sweeps_per_step, b, every, Erec[j][i * recs_per_step:],
+                                    Mrec[j][i * recs_per_step:])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    step_gpu_ms = sum(a.elapsed_time(b) for a, b in events)
 
-    # sweep-only segment: the same kernel without measurement, timed with events on its stream
-    so_sweeps = min(200, max(20, args.steps))
+    # sweep-only segment (measurement excluded): the same kernel, HIP events on its stream
+    so_sweeps = 200
     ev_a = torch.cuda.Event(enable_timing=True)
     ev_b = torch.cuda.Event(enable_timing=True)
     lat0, b0 = lats[1] if len(lats) > 1 else lats[0]
@@ -131,32 +158,24 @@ def main():
     ev_b.record(stream)
     torch.cuda.synchronize()
     so_ms = ev_a.elapsed_time(ev_b)
-    launches_per_sweep = 1 if kname in ("fused",) else (0 if kname == "resident" else 2)
-    if launches_per_sweep:
-        kernel_avg_ms = so_ms / (so_sweeps * launches_per_sweep)
-    else:
-        kernel_avg_ms = so_ms
-    attempts_per_launch = N if launches_per_sweep == 1 else (N // 2 if launches_per_sweep == 2 else N * so_sweeps)
-    bytes_per_attempt = 2.0
-    # algorithmic bytes per launch: each site read once and written once per sweep
-    alg_bytes = bytes_per_attempt * (N if launches_per_sweep else N * so_sweeps) / max(1, launches_per_sweep)
-    hbm_gbs = alg_bytes / (kernel_avg_ms * 1e-3) / 1e9
-    sweep_only_rate = so_sweeps * N / (so_ms * 1e6)
-    alu_tops = PHILOX_OPS_PER_ATTEMPT * sweep_only_rate * 1e9 / 1e12
+    launches_per_sweep = {"fused": 1, "tiled": 2, "generic": 2}.get(kname, 0)
+    launches = so_sweeps * launches_per_sweep if launches_per_sweep else 1
+    kernel_avg_us = so_ms * 1e3 / launches
+    attempts_per_launch = so_sweeps * N / launches
+    sweep_only_rate = so_sweeps * N / (so_ms * 1e6)  # attempts per ns
 
-    total_attempts = args.steps * sweeps_per_step * N * len(lats)
-    value = total_attempts / (wall * 1e9)
-    hbm_frac = hbm_gbs / HBM_PEAK_GBS
-    alu_frac = alu_tops / VALU_PEAK_TOPS
-    roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(hbm_frac, 4), "traffic": None, "kernel": kname,
-            "kernel_avg_us": round(kernel_avg_ms * 1e3, 2),
-            "alg_bytes_per_launch": int(alg_bytes)}
-    if alu_frac > hbm_frac:
-        roof = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(alu_frac, 4), "traffic": None, "kernel": kname,
-                "kernel_avg_us": round(kernel_avg_ms * 1e3, 2),
-                "alg_ops_per_attempt": PHILOX_OPS_PER_ATTEMPT, "hbm_frac": round(hbm_frac, 4)}
+    alg_ops = ALG_OPS_PER_ATTEMPT[d]
+    alu_tops = alg_ops * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e12
+    hbm_gbs = BYTES_PER_ATTEMPT * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
+    kernel_tag = {("fused", 2): "k_stream2d", ("tiled", 3): "k_tiled3d"}.get((kname, d), kname)
+    traffic = profiled_traffic(kernel_tag, L)
+    roof = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+            "kernel": kernel_tag, "kernel_avg_us": round(kernel_avg_us, 2),
+            "alg_ops_per_attempt": alg_ops, "attempts_per_launch": int(attempts_per_launch),
+            "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                    "alg_bytes_per_launch": int(BYTES_PER_ATTEMPT * attempts_per_launch)}}
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -165,6 +184,8 @@ def main():
         bb.copy_(a)
         torch.cuda.synchronize()
 
+    total_attempts = args.steps * sweeps_per_step * N * len(lats)
+    value = total_attempts / (wall * 1e9)
     out = {
         "metric": "spin-flip attempts/ns + % HBM roofline; batched vs plain flips/ns; p50/p99 job latency",
         "value": round(value, 2),
@@ -178,8 +199,7 @@ def main():
                    "record_every": every, "lattices": len(lats), "kernel": kname,
                    "parallelism": "single GPU"},
         "sweep_only_attempts_per_ns": round(sweep_only_rate, 2),
-        "hbm_frac_sweep_only": round(hbm_frac, 4),
-        "gpu_busy_ms_per_step": round(step_gpu_ms / max(1, args.steps), 4),
+        "hbm_frac_sweep_only": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
