@@ -169,6 +169,7 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
   if (t.x && t.y && t.threads && (h->d == 2 || t.z)) return t;
   const int L = h->L;
   if (kernel == SPIN_KERNEL_FUSED) {
+    if (h->d == 3) return Tile{L, 8, 64, 640};
     if (L == 8192) return Tile{8192, 16, 0, 1024};
     if (L == 4096) return Tile{4096, 16, 0, 512};
     if (L % 512 == 0 && L >= 1024) return Tile{512, 16, 0, 256};

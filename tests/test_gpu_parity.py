@@ -245,13 +245,20 @@ def test_ising2d_L8192_first_sweeps(oracle_mod, beta):
 
 
 def test_ising3d_L512_first_sweep(oracle_mod):
+    """Full benchmark size, the kernel the benchmark times (plane streaming), then the other
+    plane-streaming shapes continuing the same chain."""
     cfg = workloads.CONFIGS["ising3d_L512"]
     lat = make(0, 512, 3, cfg["seed"])
     note("L512 3d kernel", spin.KERNEL_NAMES[lat.kernel])
-    E, M = lat.sweep_record(1, B_3D, 1)
+    assert lat.kernel == FUS
     ch = oracle_mod.Chain(512, 3, cfg["seed"])
-    Eo, Mo = ch.sweep(1, B_3D, every=1)
-    np.testing.assert_array_equal(E, Eo)
-    np.testing.assert_array_equal(M, Mo)
-    np.testing.assert_array_equal(lat.spins(), ch.spins)
+    for tile, beta in [(None, B_3D), ((512, 8, 32, 640), 3.0), ((512, 32, 64, 704), 0.0),
+                       ((512, 16, 16, 384), 0.5), ((512, 8, 64, 320), B_3D)]:
+        if tile:
+            lat.set_kernel(FUS, *tile)
+        E, M = lat.sweep_record(1, beta, 1)
+        Eo, Mo = ch.sweep(1, beta, every=1)
+        np.testing.assert_array_equal(E, Eo)
+        np.testing.assert_array_equal(M, Mo)
+        np.testing.assert_array_equal(lat.spins(), ch.spins)
     lat.close()
