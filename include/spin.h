@@ -164,6 +164,63 @@ const char* spin_last_error(void);
 /* Library version string. */
 const char* spin_version(void);
 
+/* ------------------------------------------------------------------ batches
+ * Sec. 4, last paragraph (parallelism over many disorder realisations):
+ * many independent lattices advanced together.  Every lattice of a batch
+ * lives in one workgroup's LDS while it is swept (L % 8 == 0, L >= 8,
+ * L^d/2 + 160 bytes <= 150 KiB: 2D L <= 552, 3D L <= 67); one persistent
+ * launch per class of (d, model, size) takes the lattices from a queue,
+ * largest work first.  Every lattice follows exactly the chain of a lone
+ * lattice with the same seed, replica and couplings (same bits).
+ */
+typedef struct {
+  int model;                 /* spin_model */
+  int L, d;
+  const int8_t* couplings;   /* host d*L^d +-1 ([dir][site]) copied at create, or NULL:
+                                EA generates from coupling_seed/realisation (shared
+                                by all lattices with the same four values), Ising: NULL */
+  uint64_t coupling_seed;
+  uint32_t realisation;
+  uint64_t seed;
+  uint32_t replica;
+} spin_desc;
+
+typedef struct spin_batch spin_batch;
+
+/* Create count lattices in their hot starts on hipStream_t stream (NULL =
+ * null stream).  NULL on error (spin_last_error says which lattice). */
+spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream);
+void spin_batch_free(spin_batch* b);               /* NULL-safe; waits for queued work */
+int  spin_batch_size(const spin_batch* b);
+
+/* Advance lattice i by n[i] >= 0 sweeps at beta[i] (host arrays of count).
+ * If every >= 1, record (E, M) after every every-th sweep of each lattice;
+ * lattice i's n[i]/every records (one record of the current state when
+ * n[i] == 0) sit in E, M (HOST arrays) at offset sum_{j<i} of the earlier
+ * lattices' counts.  Synchronises. */
+int spin_batch_sweep(spin_batch* b, const int* n, const double* beta, int every, int64_t* E, int64_t* M);
+
+/* As spin_batch_sweep with DEVICE record arrays; asynchronous. */
+int spin_batch_sweep_device(spin_batch* b, const int* n, const double* beta, int every, int64_t* E,
+                            int64_t* M);
+
+/* E, M of every lattice (host arrays of count).  Synchronises. */
+int spin_batch_measure(spin_batch* b, int64_t* E, int64_t* M);
+
+/* Spins of lattice i to / from a host array of n == L^d values.  Synchronous. */
+int spin_batch_get_spins(const spin_batch* b, int i, int8_t* out, size_t n);
+int spin_batch_set_spins(spin_batch* b, int i, const int8_t* in, size_t n);
+
+/* Absolute index of lattice i's next sweep. */
+uint64_t spin_batch_sweeps_done(const spin_batch* b, int i);
+
+/* Workgroups resident per compute unit for the batch launches (0 = as many
+ * as LDS and the workgroup size allow; 1..8 otherwise).  Bits never change. */
+int spin_batch_set_workgroups_per_cu(spin_batch* b, int wgs);
+
+/* Wait for the batch's queued work. */
+int spin_batch_synchronize(spin_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

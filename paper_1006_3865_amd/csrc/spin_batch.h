@@ -1,0 +1,71 @@
+// spin_batch.h -- types and launchers of the batched (many-lattice) path.
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spin_internal.h"
+
+namespace spin {
+
+// Largest dynamic LDS block of the batch kernel (spins packed 2 per byte).
+constexpr size_t kBatchMaxLds = 150 * 1024;
+
+// Device-resident state of one lattice of a batch.
+struct BatchLattice {
+  int8_t* spins;        // int8 [N] in HBM (read at task start, written at task end)
+  const uint32_t* Jn;   // couplings, nibble words [dir][N/8], or nullptr (Ising)
+  uint32_t L;
+  uint32_t d;
+  uint32_t replica;
+  uint32_t t;           // absolute index of the next sweep (advanced by the kernel)
+  RoundKeys keys;
+};
+
+// Per-call parameters of one lattice.
+struct BatchCall {
+  uint32_t n;           // sweeps this call
+  uint32_t every;       // record cadence (0: none)
+  uint32_t never4;      // 4 * never_level of the acceptance table
+  uint32_t bound[8];    // acceptance bounds by unsatisfied-bond count
+  int64_t* E;           // n/every records (device) or nullptr
+  int64_t* M;
+};
+
+size_t batch_lds_bytes(uint32_t L, uint32_t d);
+// One persistent launch over ntasks tasks (lattices order[0..ntasks) with
+// their calls) of one class (d, model), nt threads per workgroup; counter is
+// a device word the launch zeroes and uses as the task queue.
+hipError_t launch_batch(uint32_t d, bool ea, uint32_t nt, BatchLattice* lats, const BatchCall* calls,
+                        const uint32_t* order, uint32_t ntasks, uint32_t* counter, size_t lds_bytes,
+                        uint32_t grid, hipStream_t stream);
+hipError_t launch_couplings_nibble(uint32_t* Jn, uint64_t N, uint32_t d, uint64_t cseed,
+                                   uint32_t realisation, hipStream_t stream);
+hipError_t launch_pack_nibbles(const int8_t* src, uint32_t* dst, uint64_t nbytes, hipStream_t stream);
+
+// int8 spins (0x01 / 0xFF) of 8 consecutive sites <-> one word of nibbles
+// (0x1 / 0xF, site j in nibble j).
+__device__ __forceinline__ uint32_t pack_nibbles(uint32_t lo, uint32_t hi) {
+  uint32_t a = lo & 0x0F0F0F0Fu, b = hi & 0x0F0F0F0Fu;
+  a = (a | (a >> 4)) & 0x00FF00FFu;
+  b = (b | (b >> 4)) & 0x00FF00FFu;
+  a = (a | (a >> 8)) & 0x0000FFFFu;
+  b = (b | (b >> 8)) & 0x0000FFFFu;
+  return a | (b << 16);
+}
+
+__device__ __forceinline__ uint32_t nibbles_to_bytes(uint32_t h) {  // 4 nibbles -> 4 bytes
+  uint32_t x = h & 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  const uint32_t neg = (x >> 3) & 0x01010101u;
+  return 0x01010101u + (neg << 8) - (neg << 1);  // 0x01 or 0xFF per byte
+}
+
+__device__ __forceinline__ void unpack_nibbles(uint32_t w, uint32_t& lo, uint32_t& hi) {
+  lo = nibbles_to_bytes(w);
+  hi = nibbles_to_bytes(w >> 16);
+}
+
+}  // namespace spin

@@ -35,6 +35,8 @@ struct Lat {
 
 RoundKeys make_round_keys(uint64_t seed);
 Accept make_accept(double beta, int d);
+// Record msg as the calling thread's spin_last_error(); returns code.
+int set_error(int code, const char* msg);
 
 // Kernel tile shapes (bytes along x, rows along y, planes along z, threads).
 struct Tile {

@@ -71,6 +71,11 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+int spin::set_error(int code, const char* msg) {
+  g_error = msg;
+  return code;
+}
+
 static int hip_fail(hipError_t e, const char* what) {
   return fail(SPIN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }

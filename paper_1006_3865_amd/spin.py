@@ -34,6 +34,15 @@ class spin_config(_c.Structure):
                 ("replica", _c.c_uint32), ("stream", _c.c_void_p)]
 
 
+class spin_desc(_c.Structure):
+    _fields_ = [("model", _c.c_int), ("L", _c.c_int), ("d", _c.c_int), ("couplings", _i8p),
+                ("coupling_seed", _c.c_uint64), ("realisation", _c.c_uint32), ("seed", _c.c_uint64),
+                ("replica", _c.c_uint32)]
+
+
+_ip = _c.POINTER(_c.c_int)
+_dp = _c.POINTER(_c.c_double)
+
 SIGNATURES = {
     "spin_create": (_P, [_c.c_int, _c.c_int, _c.c_int, _i8p, _c.c_uint64]),
     "spin_create_config": (_P, [_c.POINTER(spin_config)]),
@@ -56,6 +65,17 @@ SIGNATURES = {
     "spin_set_allocator": (None, [ALLOC_FN, RELEASE_FN, _c.c_void_p]),
     "spin_last_error": (_c.c_char_p, []),
     "spin_version": (_c.c_char_p, []),
+    "spin_batch_create": (_P, [_c.c_int, _c.POINTER(spin_desc), _c.c_void_p]),
+    "spin_batch_free": (None, [_P]),
+    "spin_batch_size": (_c.c_int, [_P]),
+    "spin_batch_sweep": (_c.c_int, [_P, _ip, _dp, _c.c_int, _i64p, _i64p]),
+    "spin_batch_sweep_device": (_c.c_int, [_P, _ip, _dp, _c.c_int, _c.c_void_p, _c.c_void_p]),
+    "spin_batch_measure": (_c.c_int, [_P, _i64p, _i64p]),
+    "spin_batch_get_spins": (_c.c_int, [_P, _c.c_int, _i8p, _c.c_size_t]),
+    "spin_batch_set_spins": (_c.c_int, [_P, _c.c_int, _i8p, _c.c_size_t]),
+    "spin_batch_sweeps_done": (_c.c_uint64, [_P, _c.c_int]),
+    "spin_batch_set_workgroups_per_cu": (_c.c_int, [_P, _c.c_int]),
+    "spin_batch_synchronize": (_c.c_int, [_P]),
 }
 
 _lib = None
@@ -299,3 +319,107 @@ class Lattice:
 
     def synchronize(self):
         spin_synchronize(self.h)
+
+
+# ------------------------------------------------------------------ batches
+
+def spin_batch_create(descs, stream=None):
+    """descs: list of dicts with model, L, d and optional couplings, coupling_seed, realisation, seed, replica."""
+    lib = load()
+    arr = (spin_desc * len(descs))()
+    keep = []
+    for i, d in enumerate(descs):
+        J = d.get("couplings")
+        Jp = None
+        if J is not None:
+            J = np.ascontiguousarray(J, dtype=np.int8)
+            keep.append(J)
+            Jp = _i8(J)
+        arr[i] = spin_desc(d["model"], d["L"], d["d"], Jp, d.get("coupling_seed", 0), d.get("realisation", 0),
+                           d.get("seed", 0), d.get("replica", 0))
+    h = lib.spin_batch_create(len(descs), arr, stream)
+    if not h:
+        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+    return h
+
+
+class Batch:
+    """Many lattices advanced together by the persistent batch kernels."""
+
+    def __init__(self, descs, stream=None):
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        self.h = spin_batch_create(descs, sp)
+        self.count = len(descs)
+        self.N = [d["L"] ** d["d"] for d in descs]
+
+    def close(self):
+        if self.h:
+            load().spin_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, n, beta):
+        n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.int32), (self.count,)), dtype=np.int32)
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (self.count,)),
+                                 dtype=np.float64)
+        return n, b
+
+    def record_counts(self, n, every):
+        n, _ = self._args(n, 0.0)
+        if every <= 0:
+            return np.zeros(self.count, dtype=np.int64)
+        return np.where(n > 0, n // every, 1).astype(np.int64)
+
+    def sweep(self, n, beta, every=0):
+        """Returns a list of (E, M) record arrays per lattice (empty when every == 0)."""
+        n, b = self._args(n, beta)
+        counts = self.record_counts(n, every)
+        tot = int(counts.sum())
+        E = np.zeros(max(tot, 1), dtype=np.int64)
+        M = np.zeros(max(tot, 1), dtype=np.int64)
+        _check(load().spin_batch_sweep(self.h, n.ctypes.data_as(_ip), b.ctypes.data_as(_dp), every,
+                                       E.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p)))
+        out, o = [], 0
+        for c in counts:
+            out.append((E[o:o + c].copy(), M[o:o + c].copy()))
+            o += c
+        return out
+
+    def sweep_device(self, n, beta, every, E, M):
+        """E, M: torch int64 CUDA tensors holding record_counts(n, every).sum() values."""
+        n, b = self._args(n, beta)
+        self._hold = (n, b)
+        _check(load().spin_batch_sweep_device(self.h, n.ctypes.data_as(_ip), b.ctypes.data_as(_dp), every,
+                                              E.data_ptr() if E is not None else None,
+                                              M.data_ptr() if M is not None else None))
+
+    def measure(self):
+        E = np.zeros(self.count, dtype=np.int64)
+        M = np.zeros(self.count, dtype=np.int64)
+        _check(load().spin_batch_measure(self.h, E.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p)))
+        return E, M
+
+    def spins(self, i):
+        out = np.empty(self.N[i], dtype=np.int8)
+        _check(load().spin_batch_get_spins(self.h, i, _i8(out), out.size))
+        return out
+
+    def set_spins(self, i, s):
+        a = np.ascontiguousarray(s, dtype=np.int8)
+        _check(load().spin_batch_set_spins(self.h, i, _i8(a), a.size))
+
+    def t(self, i):
+        return int(load().spin_batch_sweeps_done(self.h, i))
+
+    def set_workgroups_per_cu(self, w):
+        _check(load().spin_batch_set_workgroups_per_cu(self.h, w))
+
+    def synchronize(self):
+        _check(load().spin_batch_synchronize(self.h))
