@@ -57,7 +57,8 @@ struct spin_batch {
   BatchCall* d_calls;
   BatchCall* h_calls;                     // pinned
   uint32_t* d_order;
-  std::vector<uint32_t> h_order;
+  uint32_t* h_order;                      // pinned, count entries
+  hipEvent_t uploaded;                    // the last upload of h_calls / h_order has been read
   uint32_t* d_counters;                   // one per class
   int64_t* d_rec;
   size_t rec_cap;
@@ -81,6 +82,8 @@ static void batch_destroy(spin_batch* b) {
   (void)hipFree(b->d_lats);
   (void)hipFree(b->d_calls);
   if (b->h_calls) (void)hipHostFree(b->h_calls);
+  if (b->h_order) (void)hipHostFree(b->h_order);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
   (void)hipFree(b->d_order);
   (void)hipFree(b->d_counters);
   (void)hipFree(b->d_rec);
@@ -112,6 +115,8 @@ spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream) {
   b->d_calls = nullptr;
   b->h_calls = nullptr;
   b->d_order = nullptr;
+  b->h_order = nullptr;
+  b->uploaded = nullptr;
   b->d_counters = nullptr;
   b->d_rec = nullptr;
   b->rec_cap = 0;
@@ -142,7 +147,7 @@ spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream) {
     const uint64_t N = (s.d == 3) ? (uint64_t)s.L * s.L * s.L : (uint64_t)s.L * s.L;
     if (batch_lds_bytes((uint32_t)s.L, (uint32_t)s.d) > kBatchMaxLds) {
       bfail(SPIN_EINVAL, "lattice %d: L=%d d=%d does not fit one workgroup's LDS (L^d/2 bytes <= %zu)", i, s.L,
-            s.d, kBatchMaxLds - 160);
+            s.d, kBatchMaxLds);
       batch_destroy(b);
       return nullptr;
     }
@@ -173,9 +178,10 @@ spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream) {
     batch_destroy(b);
     return nullptr;
   }
-  if (hipHostMalloc((void**)&b->h_calls, sizeof(BatchCall) * count, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&b->h_calls, sizeof(BatchCall) * count, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_order, sizeof(uint32_t) * count, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
-    b->h_calls = nullptr;
     bfail(SPIN_ENOMEM, "pinned host allocation failed");
     batch_destroy(b);
     return nullptr;
@@ -292,6 +298,9 @@ static int batch_run(spin_batch* b, const int* n, int n0, const double* beta, in
   if (!b) return bfail(SPIN_EINVAL, "NULL batch");
   if (!beta) return bfail(SPIN_EINVAL, "NULL beta array");
   if (every < 0) return bfail(SPIN_EINVAL, "every must be >= 0");
+  // the previous call's uploads must have been read before the host buffers change
+  hipError_t e = hipEventSynchronize(b->uploaded);
+  if (e != hipSuccess) return hfail(e, "batch upload wait");
   size_t rec = 0;
   for (int i = 0; i < b->count; ++i) {
     const int ni = n ? n[i] : n0;
@@ -311,28 +320,28 @@ static int batch_run(spin_batch* b, const int* n, int n0, const double* beta, in
     if (!nr) c.every = 0;
     rec += nr;
   }
-  hipError_t e = hipMemcpyAsync(b->d_calls, b->h_calls, sizeof(BatchCall) * b->count, hipMemcpyHostToDevice,
-                                b->stream);
+  e = hipMemcpyAsync(b->d_calls, b->h_calls, sizeof(BatchCall) * b->count, hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return hfail(e, "batch call upload");
   // task order: per class, largest work first (longest-processing-time order)
-  b->h_order.clear();
+  uint32_t norder = 0;
   std::vector<std::pair<uint32_t, uint32_t>> ranges;
   for (const Class& c : b->classes) {
-    const uint32_t start = (uint32_t)b->h_order.size();
+    const uint32_t start = norder;
     std::vector<uint32_t> m;
     for (uint32_t i : c.members)
       if (b->h_calls[i].n > 0 || b->h_calls[i].every) m.push_back(i);
     std::stable_sort(m.begin(), m.end(), [&](uint32_t x, uint32_t y) {
       return b->N[x] * (uint64_t)b->h_calls[x].n > b->N[y] * (uint64_t)b->h_calls[y].n;
     });
-    b->h_order.insert(b->h_order.end(), m.begin(), m.end());
+    for (uint32_t i : m) b->h_order[norder++] = i;
     ranges.push_back({start, (uint32_t)m.size()});
   }
-  if (!b->h_order.empty()) {
-    e = hipMemcpyAsync(b->d_order, b->h_order.data(), sizeof(uint32_t) * b->h_order.size(), hipMemcpyHostToDevice,
-                       b->stream);
+  if (norder) {
+    e = hipMemcpyAsync(b->d_order, b->h_order, sizeof(uint32_t) * norder, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hfail(e, "batch order upload");
   }
+  e = hipEventRecord(b->uploaded, b->stream);
+  if (e != hipSuccess) return hfail(e, "batch upload event");
   for (size_t k = 0; k < b->classes.size(); ++k) {
     const Class& c = b->classes[k];
     const uint32_t ntasks = ranges[k].second;

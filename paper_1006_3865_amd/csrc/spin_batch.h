@@ -10,7 +10,7 @@
 namespace spin {
 
 // Largest dynamic LDS block of the batch kernel (spins packed 2 per byte).
-constexpr size_t kBatchMaxLds = 150 * 1024;
+constexpr size_t kBatchMaxLds = 150 * 1024;  // plus 208 bytes of static LDS
 
 // Device-resident state of one lattice of a batch.
 struct BatchLattice {

@@ -89,22 +89,29 @@ __device__ __forceinline__ uint32_t nib_unsat(uint32_t c, uint32_t lw, uint32_t 
   return S;
 }
 
-// Flip mask (0xE per flipped nibble) for the active nibbles p, p+2, p+4, p+6.
+// Flip mask (0xE per flipped nibble) for the active nibbles p, p+2, p+4, p+6:
+// S is shifted so the active nibbles sit at 0, 2, 4, 6 (constant offsets),
+// and the mask is shifted back.
 template <bool NEVER>
 __device__ __forceinline__ uint32_t nib_flips(uint32_t S, uint32_t p, const uint32_t r[4],
                                               const uint32_t* bound, uint32_t never4) {
+  const uint32_t Sp = S >> (4u * p);
   uint32_t f = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t sh = 4u * (2u * i + p);
-    const uint32_t u2 = __builtin_amdgcn_ubfe(S, sh, 4);  // 2u
+    const uint32_t u2 = (Sp >> (8 * i)) & 0xFu;  // 2u of active nibble i
     const uint32_t b = *(const uint32_t*)((const char*)bound + 2u * u2);
     bool acc = r[i] <= b;
     if (NEVER) acc = acc && (2u * u2 >= never4);
-    f |= acc ? (0xEu << sh) : 0u;
+    f |= acc ? (0xEu << (8 * i)) : 0u;
   }
-  return f;
+  return f << (4u * p);
 }
+
+// Global-address-space view of a device pointer (loads with a 32-bit offset
+// from a scalar base instead of 64-bit flat addresses).
+typedef const __attribute__((address_space(1))) uint32_t gu32;
+__device__ __forceinline__ gu32* as_global(const uint32_t* p) { return (gu32*)(p); }
 
 // E = -d N + 2 (unsatisfied bonds), M = N - 2 (negative spins) of the LDS
 // lattice into Cl.E[rec], Cl.M[rec].
@@ -164,9 +171,9 @@ __device__ void batch_task(const BatchLattice& B, const BatchCall& Cl, uint32_t*
   const uint32_t xg = tid % LG;
   const uint32_t r_first = tid / LG;
   const uint32_t dz = RI / L, dy = RI % L;          // row step in (y, z)
-  const uint32_t* Jx = EA ? B.Jn : nullptr;
-  const uint32_t* Jy = EA ? B.Jn + NW : nullptr;
-  const uint32_t* Jz = EA ? B.Jn + 2 * NW : nullptr;
+  gu32* Jx = as_global(B.Jn);
+  gu32* Jy = Jx + NW;
+  gu32* Jz = Jx + 2 * NW;
   const uint32_t wl = xg ? 0u - 1u : LG - 1u;       // offset to the word on the left
   const uint32_t wr = (xg + 1 < LG) ? 1u : 0u - (LG - 1u);
   uint32_t rec = 0;
@@ -237,18 +244,18 @@ __device__ void batch_task(const BatchLattice& B, const BatchCall& Cl, uint32_t*
 template <int D, bool EA, int NT>
 __global__ __launch_bounds__(NT) void k_batch(BatchLattice* lats, const BatchCall* calls,
                                               const uint32_t* order, uint32_t ntasks, uint32_t* next) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint32_t* bound = lds;                                  // 8 words
-  int64_t* red = reinterpret_cast<int64_t*>(lds + 8);     // 16 int64
-  uint32_t* sp = lds + 8 + 32;
+  __shared__ uint32_t bound[8];   // static LDS first: lookups use a constant base
+  __shared__ int64_t red[16];
   __shared__ uint32_t task;
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* sp = lds;
   for (;;) {
     if (threadIdx.x == 0) task = atomicAdd(next, 1u);
     __syncthreads();
-    const uint32_t k = task;
+    const uint32_t k = __builtin_amdgcn_readfirstlane(task);  // uniform: scalar loads below
     __syncthreads();
     if (k >= ntasks) break;
-    const uint32_t li = order[k];
+    const uint32_t li = __builtin_amdgcn_readfirstlane(order[k]);
     const BatchCall Cl = calls[li];
     const BatchLattice B = lats[li];
     batch_task<D, EA, NT>(B, Cl, sp, bound, red);
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchLattice* lats, const BatchCal
 
 size_t batch_lds_bytes(uint32_t L, uint32_t d) {
   const uint64_t N = (d == 3) ? (uint64_t)L * L * L : (uint64_t)L * L;
-  return (8 + 32) * 4 + N / 2;
+  return N / 2;
 }
 
 template <int NT>

@@ -89,3 +89,9 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
                               bool* measured, hipStream_t stream);
 
 }  // namespace spin
+
+struct spin_lattice;
+namespace spin {
+// E, M of a handle's current state into device int64s (asynchronous).
+int record_device(spin_lattice* h, int64_t* E, int64_t* M);
+}  // namespace spin

@@ -314,6 +314,17 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   return SPIN_OK;
 }
 
+// E, M of the current state into device int64 E, M (asynchronous).
+int spin::record_device(spin_lattice* h, int64_t* E, int64_t* M) {
+  if (!h || !E || !M) return fail(SPIN_EINVAL, "NULL argument");
+  const uint32_t parts = measure_parts(lat_of(h));
+  if (int rc = reserve_parts(h, 1, parts)) return rc;
+  hipError_t e = launch_measure(lat_of(h), Record{h->part}, h->stream);
+  if (e == hipSuccess) e = launch_finalize(h->part, parts, parts, 1, E, M, e_offset(h), (int64_t)h->N, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "record");
+  return SPIN_OK;
+}
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
