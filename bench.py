@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D EA workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--batched-sweeps", type=int, default=5000)
     return ap.parse_args()
 
 
@@ -95,6 +99,96 @@ def cpu_baseline(cfg, seconds_hint):
             "kind": "oracle",
             "sample": "%d sweeps (E/M recorded) of the L=%d d=%d lattice from the hot start at each of %d "
                       "beta(s); %.1f s on one host core" % (n_sweeps, L, d, used, dt)}
+
+
+def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
+    """Batched 3D +-J EA workload: 512 realisations (L in 16..64) x 16 betas = 8192 lattices, all
+    advanced `sweeps` sweeps by one pool call, (E, M) every `every` sweeps.  Plain: the same
+    lattices on lone handles one after another; its time is the sum over lattices of L^3 * sweeps
+    at the rate measured on two lattices of each size over `plain_sweeps` sweeps (steady state)."""
+    import numpy as np
+    descs = workloads.ea_batch()
+    betas = np.array([d["beta"] for d in descs])
+    N = np.array([d["L"] ** 3 for d in descs], dtype=np.float64)
+    stream = torch.cuda.Stream()
+    b = spin.Batch(descs, stream=stream)
+    nrec = int(b.record_counts(sweeps, every).sum())
+    E = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
+    M = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
+    b.sweep(2, betas, 0)          # warm-up: module load, LDS attributes
+    b.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.sweep_device(sweeps, betas, every, E, M)
+    ev1.record(stream)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    attempts = float(N.sum()) * sweeps
+    b.close()
+    rates = {}
+    for L in sorted({d["L"] for d in descs}):
+        sel = [d for d in descs if d["L"] == L][:2]
+        att = 0.0
+        ms = 0.0
+        for d in sel:
+            lat = spin.Lattice(1, L, 3, d["seed"], coupling_seed=d["coupling_seed"], realisation=d["realisation"],
+                               replica=d["replica"], stream=stream)
+            lat.sweep(5, d["beta"])
+            a, bb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.sweep(plain_sweeps, d["beta"])
+            bb.record(stream)
+            lat.synchronize()
+            ms += a.elapsed_time(bb)
+            att += plain_sweeps * L ** 3
+            kname = spin.KERNEL_NAMES[lat.kernel]
+            lat.close()
+        rates[L] = (att / (ms * 1e6), kname)
+    plain_s = sum(L ** 3 * sweeps / (rates[L][0] * 1e9) for L in (d["L"] for d in descs))
+    batched = attempts / (wall * 1e9)
+    plain = attempts / (plain_s * 1e9)
+    return {"workload": "ea3d_batch", "lattices": len(descs), "realisations": len(descs) // 16,
+            "sizes": sorted(rates), "sweeps": sweeps, "record_every": every, "attempts": attempts,
+            "batched_attempts_per_ns": round(batched, 2), "batched_gpu_ms": round(gpu_ms, 2),
+            "plain_attempts_per_ns": round(plain, 3), "ratio": round(batched / plain, 2),
+            "plain_rate_by_L": {str(L): {"attempts_per_ns": round(r, 3), "kernel": k} for L, (r, k) in rates.items()},
+            "plain_method": "lone handles, %d sweeps on 2 lattices per L, summed over the workload" % plain_sweeps}
+
+
+def bench_serving(torch, serve, workloads, jobs):
+    """Serving workload: Poisson job stream at 0.8 x the saturated capacity of the served path,
+    1 GiB pool budget, 512 slots; p50/p99 latency served vs plain FIFO (one job at a time on
+    lone handles, same trace, latencies by the FIFO recurrence over measured service times)."""
+    unit = workloads.serve_trace(jobs=jobs, rate_per_s=1.0)
+    work = sum(j["L"] ** j["d"] * j["sweeps"] for j in unit)
+    stream = torch.cuda.Stream()
+
+    def run(trace):
+        ex = serve.PoolExecutor(stream=stream)
+        srv = serve.Server(ex, budget_bytes=1 << 30, max_slots=512)
+        res = srv.serve(trace)
+        ex.close()
+        return res, srv.ticks
+
+    sat, _ = run([dict(j, arrival=0.0) for j in unit])
+    cap = work / max(r["finished"] for r in sat.values())          # attempts/s, saturated
+    lam = 0.8 * cap / (work / len(unit))                            # jobs/s
+    trace = [dict(j, arrival=j["arrival"] / lam) for j in unit]
+    served, ticks = run(trace)
+    plain = serve.plain_fifo(trace, serve.lone_service)
+    s_sum = serve.summarize(served, trace)
+    p_sum = serve.summarize(plain, trace)
+    same = all((served[k]["E"], served[k]["M"]) == (plain[k]["E"], plain[k]["M"]) for k in served)
+    return {"workload": "serve_trace", "jobs": jobs, "mean_attempts_per_job": work / len(unit),
+            "saturated_attempts_per_ns": round(cap / 1e9, 2), "arrival_rate_per_s": round(lam, 2),
+            "budget_bytes": 1 << 30, "max_slots": 512, "ticks": ticks,
+            "served": {k: round(v, 5) for k, v in s_sum.items()},
+            "plain_fifo": {k: round(v, 5) for k, v in p_sum.items()},
+            "p50_ratio": round(p_sum["p50_s"] / s_sum["p50_s"], 2),
+            "p99_ratio": round(p_sum["p99_s"] / s_sum["p99_s"], 2),
+            "results_identical": bool(same)}
 
 
 def main():
@@ -167,7 +261,8 @@ def main():
     alg_ops = ALG_OPS_PER_ATTEMPT[d]
     alu_tops = alg_ops * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e12
     hbm_gbs = BYTES_PER_ATTEMPT * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
-    kernel_tag = {("fused", 2): "k_stream2d", ("tiled", 3): "k_tiled3d"}.get((kname, d), kname)
+    kernel_tag = {("fused", 2): "k_stream2d", ("fused", 3): "k_stream3d", ("tiled", 3): "k_tiled3d"}.get(
+        (kname, d), kname)
     traffic = profiled_traffic(kernel_tag, L)
     roof = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
@@ -202,10 +297,18 @@ def main():
         "hbm_frac_sweep_only": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, 25.0)
     for lat, _ in lats:
         lat.close()
+    del Erec, Mrec
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps)
+        print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
+    if not args.no_serving:
+        from paper_1006_3865_amd import serve
+        out["serving"] = bench_serving(torch, serve, workloads, args.serve_jobs)
+        print("serving:", json.dumps(out["serving"]), file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, 25.0)
     print(json.dumps(out), flush=True)
 
 

@@ -166,19 +166,28 @@ const char* spin_version(void);
 
 /* ------------------------------------------------------------------ batches
  * Sec. 4, last paragraph (parallelism over many disorder realisations):
- * many independent lattices advanced together.  Every lattice of a batch
- * lives in one workgroup's LDS while it is swept (L % 8 == 0, L >= 8,
- * L^d/2 + 160 bytes <= 150 KiB: 2D L <= 552, 3D L <= 67); one persistent
- * launch per class of (d, model, size) takes the lattices from a queue,
- * largest work first.  Every lattice follows exactly the chain of a lone
- * lattice with the same seed, replica and couplings (same bits).
+ * a pool of independent lattices advanced together.  A member whose spins
+ * fit one workgroup's LDS (L % 8 == 0, L >= 8, L^d/2 bytes <= 150 KiB:
+ * 2D L <= 552, 3D L <= 64) is swept by one persistent launch per class of
+ * (d, model, size) that takes the members from a queue, largest work first;
+ * any other valid lattice (even L >= 4) is advanced by the single-lattice
+ * kernels on the batch's stream within the same call.  Every member follows
+ * exactly the chain of a lone lattice with the same seed, replica and
+ * couplings (same bits).
+ *
+ * Members live in numbered slots 0..spin_batch_size()-1.  spin_batch_add
+ * reuses the most recently freed slot, if any, else appends one;
+ * spin_batch_remove frees a slot.  Per-slot host arrays (n, beta, E, M of
+ * spin_batch_measure) have spin_batch_size() entries; a free slot must get
+ * n == 0 and its beta is ignored.
  */
 typedef struct {
   int model;                 /* spin_model */
   int L, d;
-  const int8_t* couplings;   /* host d*L^d +-1 ([dir][site]) copied at create, or NULL:
-                                EA generates from coupling_seed/realisation (shared
-                                by all lattices with the same four values), Ising: NULL */
+  const int8_t* couplings;   /* host d*L^d +-1 ([dir][site]) copied before return, or NULL:
+                                EA generates from coupling_seed/realisation (members of the
+                                LDS-sized kind with the same four values (seed, realisation,
+                                L, d) share one device copy), Ising: NULL */
   uint64_t coupling_seed;
   uint32_t realisation;
   uint64_t seed;
@@ -187,31 +196,53 @@ typedef struct {
 
 typedef struct spin_batch spin_batch;
 
-/* Create count lattices in their hot starts on hipStream_t stream (NULL =
- * null stream).  NULL on error (spin_last_error says which lattice). */
+/* Create a pool holding count >= 0 lattices (slots 0..count-1) in their hot
+ * starts on hipStream_t stream (NULL = null stream).  NULL on error
+ * (spin_last_error says which lattice). */
 spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream);
 void spin_batch_free(spin_batch* b);               /* NULL-safe; waits for queued work */
+
+/* Number of slots (members and free slots). */
 int  spin_batch_size(const spin_batch* b);
 
-/* Advance lattice i by n[i] >= 0 sweeps at beta[i] (host arrays of count).
- * If every >= 1, record (E, M) after every every-th sweep of each lattice;
- * lattice i's n[i]/every records (one record of the current state when
- * n[i] == 0) sit in E, M (HOST arrays) at offset sum_{j<i} of the earlier
- * lattices' counts.  Synchronises. */
+/* Add a lattice in its hot start; returns its slot (>= 0) or a negative
+ * spin_status.  Work is enqueued on the batch's stream; may synchronise. */
+int  spin_batch_add(spin_batch* b, const spin_desc* desc);
+
+/* Remove the lattice in slot i and release its memory to the pool (device
+ * memory returns to the system at spin_batch_free).  Synchronises. */
+int  spin_batch_remove(spin_batch* b, int i);
+
+/* 1 if slot i holds a lattice, else 0. */
+int  spin_batch_is_member(const spin_batch* b, int i);
+
+/* Device bytes that slot i's lattice may hold: spins (twice L^d for a
+ * lattice beyond the LDS-sized kind: the streaming kernels' second buffer)
+ * plus its couplings (d*L^d/2 packed for the LDS-sized kind, d*L^d
+ * otherwise), counted in full even when shared with other members; 0 for a
+ * free slot.  An upper bound for admission control. */
+uint64_t spin_batch_footprint(const spin_batch* b, int i);
+
+/* Advance slot i by n[i] >= 0 sweeps at beta[i] (host arrays of
+ * spin_batch_size() entries).  If every >= 1, record (E, M) after every
+ * every-th sweep of each member; slot i's n[i]/every records (one record of
+ * the current state when n[i] == 0) sit in E, M (HOST arrays) at offset
+ * sum_{j<i} of the earlier slots' counts (free slots count 0).  Synchronises. */
 int spin_batch_sweep(spin_batch* b, const int* n, const double* beta, int every, int64_t* E, int64_t* M);
 
 /* As spin_batch_sweep with DEVICE record arrays; asynchronous. */
 int spin_batch_sweep_device(spin_batch* b, const int* n, const double* beta, int every, int64_t* E,
                             int64_t* M);
 
-/* E, M of every lattice (host arrays of count).  Synchronises. */
+/* E, M of every slot (host arrays of spin_batch_size(); 0 for free slots).
+ * Synchronises. */
 int spin_batch_measure(spin_batch* b, int64_t* E, int64_t* M);
 
-/* Spins of lattice i to / from a host array of n == L^d values.  Synchronous. */
+/* Spins of slot i to / from a host array of n == L^d values.  Synchronous. */
 int spin_batch_get_spins(const spin_batch* b, int i, int8_t* out, size_t n);
 int spin_batch_set_spins(spin_batch* b, int i, const int8_t* in, size_t n);
 
-/* Absolute index of lattice i's next sweep. */
+/* Absolute index of slot i's next sweep (0 for a free slot). */
 uint64_t spin_batch_sweeps_done(const spin_batch* b, int i);
 
 /* Workgroups resident per compute unit for the batch launches (0 = as many

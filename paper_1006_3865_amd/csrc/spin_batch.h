@@ -33,7 +33,32 @@ struct BatchCall {
   int64_t* M;
 };
 
+// Device block of a lone lattice swept by the batch kernel as a one-task launch.
+struct BatchSingle {
+  BatchLattice lat;
+  BatchCall call;
+  uint32_t order;       // 0: the only task
+  uint32_t counter;     // task queue of the launch
+};
+
 size_t batch_lds_bytes(uint32_t L, uint32_t d);
+
+// Shapes the batch kernel holds in one workgroup's LDS.
+inline bool batch_fits(uint32_t L, uint32_t d) {
+  return L >= 8 && L % 8 == 0 && batch_lds_bytes(L, d) <= kBatchMaxLds;
+}
+
+// Workgroup size of the batch kernel for a lattice of nwords nibble words.
+inline uint32_t batch_threads_for(uint64_t nwords) {
+  if (nwords <= 2048) return 256;
+  if (nwords <= 8192) return 512;
+  return 1024;
+}
+
+// Write lat and call into blk (a device BatchSingle) and sweep the lattice as
+// one task (nt threads, LDS for the whole lattice), all on `stream`.
+hipError_t launch_batch_single(BatchSingle* blk, const BatchLattice& lat, const BatchCall& call, uint32_t nt,
+                               hipStream_t stream);
 // One persistent launch over ntasks tasks (lattices order[0..ntasks) with
 // their calls) of one class (d, model), nt threads per workgroup; counter is
 // a device word the launch zeroes and uses as the task queue.

@@ -308,4 +308,21 @@ hipError_t launch_batch(uint32_t d, bool ea, uint32_t nt, BatchLattice* lats, co
   return hipGetLastError();
 }
 
+__global__ void k_store_single(BatchSingle* blk, BatchLattice lat, BatchCall call) {
+  if (threadIdx.x == 0) {
+    blk->lat = lat;
+    blk->call = call;
+    blk->order = 0;
+  }
+}
+
+hipError_t launch_batch_single(BatchSingle* blk, const BatchLattice& lat, const BatchCall& call, uint32_t nt,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_store_single, dim3(1), dim3(64), 0, stream, blk, lat, call);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_batch(lat.d, lat.Jn != nullptr, nt, &blk->lat, &blk->call, &blk->order, 1, &blk->counter,
+                      batch_lds_bytes(lat.L, lat.d), 1, stream);
+}
+
 }  // namespace spin

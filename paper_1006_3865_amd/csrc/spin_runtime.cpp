@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "spin.h"
+#include "spin_batch.h"
 #include "spin_internal.h"
 
 namespace spin {
@@ -130,6 +131,8 @@ struct spin_lattice {
   int kernel;  // requested family
   Tile tile;   // requested shape (0 = default)
   Allocator mem;
+  BatchSingle* single;  // one-task block of the LDS-resident batch kernel (allocated on first use)
+  uint32_t* jn;         // EA couplings as nibble words for that kernel (packed on first use)
 };
 
 static const uint64_t kMaxSweepIndex = (uint64_t)1 << 32;
@@ -166,7 +169,21 @@ static void destroy(spin_lattice* h) {
   h->mem.put(h->J);
   h->mem.put(h->em);
   h->mem.put(h->part);
+  h->mem.put(h->single);
+  h->mem.put(h->jn);
   delete h;
+}
+
+// Workgroup size when the RESIDENT family runs on the nibble batch kernel
+// (L % 8 == 0 and the packed lattice fits LDS), else 0 (the per-site kernel).
+// A requested size of 256, 512 or 1024 is used; none picks by lattice size;
+// any other requested size selects the per-site kernel.
+static uint32_t single_threads(const spin_lattice* h) {
+  if (!batch_fits((uint32_t)h->L, (uint32_t)h->d)) return 0;
+  const int req = h->tile.threads;
+  if (req == 0) return batch_threads_for(h->N / 8);
+  if (req == 256 || req == 512 || req == 1024) return (uint32_t)req;
+  return 0;
 }
 
 static Tile default_tile(const spin_lattice* h, int kernel) {
@@ -202,8 +219,8 @@ static bool family_ok(const spin_lattice* h, int kernel, const Tile& tile) {
   switch (kernel) {
     case SPIN_KERNEL_GENERIC: return true;
     case SPIN_KERNEL_RESIDENT:
-      return h->N <= kResidentMaxSites && tile.threads >= 64 && tile.threads <= 1024 &&
-             tile.threads % 64 == 0;
+      if (tile.threads < 64 || tile.threads > 1024 || tile.threads % 64 != 0) return false;
+      return h->N <= kResidentMaxSites || (batch_fits((uint32_t)h->L, (uint32_t)h->d) && single_threads(h));
     case SPIN_KERNEL_TILED: return tiled_supported(l, tile);
     case SPIN_KERNEL_FUSED: return fused_supported(l, tile);
     default: return false;
@@ -251,6 +268,41 @@ static int check_beta(double beta) {
   return SPIN_OK;
 }
 
+// n sweeps of the whole lattice in one workgroup's LDS (the batch kernel with
+// one task); records (every > 0) go straight to dE, dM.
+static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM,
+                      uint32_t nt) {
+  if (!h->single) {
+    h->single = (BatchSingle*)h->mem.get(sizeof(BatchSingle));
+    if (!h->single) return fail(SPIN_ENOMEM, "allocation of the one-task block failed");
+  }
+  if (h->model == SPIN_EA_PMJ && !h->jn) {
+    const uint64_t nbytes = (uint64_t)h->d * h->N;
+    h->jn = (uint32_t*)h->mem.get(nbytes / 2);
+    if (!h->jn) return fail(SPIN_ENOMEM, "allocation of the packed couplings failed");
+    hipError_t e = launch_pack_nibbles(h->J, h->jn, nbytes, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "coupling packing launch");
+  }
+  BatchLattice bl;
+  bl.spins = h->buf[h->cur];
+  bl.Jn = h->jn;
+  bl.L = (uint32_t)h->L;
+  bl.d = (uint32_t)h->d;
+  bl.replica = h->replica;
+  bl.t = (uint32_t)h->t;
+  bl.keys = make_round_keys(h->seed);
+  BatchCall c;
+  c.n = (uint32_t)n;
+  c.every = every > 0 && n >= every ? (uint32_t)every : 0u;
+  c.never4 = 4u * acc.never_level;
+  for (int k = 0; k < 8; ++k) c.bound[k] = acc.bound[k];
+  c.E = c.every ? dE : nullptr;
+  c.M = c.every ? dM : nullptr;
+  hipError_t e = launch_batch_single(h->single, bl, c, nt, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
+  return SPIN_OK;
+}
+
 // Enqueue n sweeps; if every > 0 write records into device arrays dE, dM.
 static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
@@ -262,6 +314,11 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   Tile tile;
   const int kernel = resolve(h, &tile);
   hipError_t e = hipSuccess;
+  if (kernel == SPIN_KERNEL_RESIDENT && single_threads(h)) {
+    if (int rc = run_single(h, n, acc, every, dE, dM, single_threads(h))) return rc;
+    h->t += (uint64_t)n;
+    return SPIN_OK;
+  }
   if (kernel == SPIN_KERNEL_RESIDENT) {
     const Lat l = lat_of(h);
     e = launch_resident(l, (uint32_t)h->t, n, acc, every, dE, dM, tile.threads, h->stream);
@@ -373,6 +430,8 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   h->d = cfg->d;
   h->N = N;
   h->buf[0] = h->buf[1] = nullptr;
+  h->single = nullptr;
+  h->jn = nullptr;
   h->cur = 0;
   h->J = nullptr;
   h->em = nullptr;

@@ -68,6 +68,10 @@ SIGNATURES = {
     "spin_batch_create": (_P, [_c.c_int, _c.POINTER(spin_desc), _c.c_void_p]),
     "spin_batch_free": (None, [_P]),
     "spin_batch_size": (_c.c_int, [_P]),
+    "spin_batch_add": (_c.c_int, [_P, _c.POINTER(spin_desc)]),
+    "spin_batch_remove": (_c.c_int, [_P, _c.c_int]),
+    "spin_batch_is_member": (_c.c_int, [_P, _c.c_int]),
+    "spin_batch_footprint": (_c.c_uint64, [_P, _c.c_int]),
     "spin_batch_sweep": (_c.c_int, [_P, _ip, _dp, _c.c_int, _i64p, _i64p]),
     "spin_batch_sweep_device": (_c.c_int, [_P, _ip, _dp, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "spin_batch_measure": (_c.c_int, [_P, _i64p, _i64p]),
@@ -104,7 +108,8 @@ class SpinError(RuntimeError):
 
 
 def _check(rc):
-    if rc != SPIN_OK:
+    """Raise on a negative status; return rc (a slot index for spin_batch_add)."""
+    if rc < 0:
         raise SpinError(rc, load().spin_last_error().decode())
     return rc
 
@@ -323,20 +328,24 @@ class Lattice:
 
 # ------------------------------------------------------------------ batches
 
+def _desc(d, keep):
+    J = d.get("couplings")
+    Jp = None
+    if J is not None:
+        J = np.ascontiguousarray(J, dtype=np.int8)
+        keep.append(J)
+        Jp = _i8(J)
+    return spin_desc(d["model"], d["L"], d["d"], Jp, d.get("coupling_seed", 0), d.get("realisation", 0),
+                     d.get("seed", 0), d.get("replica", 0))
+
+
 def spin_batch_create(descs, stream=None):
     """descs: list of dicts with model, L, d and optional couplings, coupling_seed, realisation, seed, replica."""
     lib = load()
-    arr = (spin_desc * len(descs))()
+    arr = (spin_desc * max(len(descs), 1))()
     keep = []
     for i, d in enumerate(descs):
-        J = d.get("couplings")
-        Jp = None
-        if J is not None:
-            J = np.ascontiguousarray(J, dtype=np.int8)
-            keep.append(J)
-            Jp = _i8(J)
-        arr[i] = spin_desc(d["model"], d["L"], d["d"], Jp, d.get("coupling_seed", 0), d.get("realisation", 0),
-                           d.get("seed", 0), d.get("replica", 0))
+        arr[i] = _desc(d, keep)
     h = lib.spin_batch_create(len(descs), arr, stream)
     if not h:
         raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
@@ -344,15 +353,47 @@ def spin_batch_create(descs, stream=None):
 
 
 class Batch:
-    """Many lattices advanced together by the persistent batch kernels."""
+    """A pool of lattices advanced together (slots; see spin_batch_* in spin.h)."""
 
-    def __init__(self, descs, stream=None):
+    def __init__(self, descs=(), stream=None):
         sp = None
         if stream is not None:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
+        descs = list(descs)
         self.h = spin_batch_create(descs, sp)
-        self.count = len(descs)
         self.N = [d["L"] ** d["d"] for d in descs]
+        self._mask = np.ones(len(descs), dtype=bool)   # slot holds a lattice
+
+    @property
+    def count(self):
+        """Number of slots (members and free slots)."""
+        return int(load().spin_batch_size(self.h))
+
+    def add(self, desc):
+        """Add a lattice; returns its slot."""
+        keep = []
+        d = _desc(desc, keep)
+        slot = _check(load().spin_batch_add(self.h, _c.byref(d)))
+        while len(self.N) <= slot:
+            self.N.append(0)
+            self._mask = np.append(self._mask, False)
+        self.N[slot] = desc["L"] ** desc["d"]
+        self._mask[slot] = True
+        return slot
+
+    def remove(self, i):
+        _check(load().spin_batch_remove(self.h, i))
+        self.N[i] = 0
+        self._mask[i] = False
+
+    def is_member(self, i):
+        return bool(load().spin_batch_is_member(self.h, i))
+
+    def members(self):
+        return [int(i) for i in np.flatnonzero(self._mask)]
+
+    def footprint(self, i):
+        return int(load().spin_batch_footprint(self.h, i))
 
     def close(self):
         if self.h:
@@ -366,19 +407,22 @@ class Batch:
             pass
 
     def _args(self, n, beta):
-        n = np.ascontiguousarray(np.broadcast_to(np.asarray(n, dtype=np.int32), (self.count,)), dtype=np.int32)
-        b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (self.count,)),
-                                 dtype=np.float64)
+        S = len(self._mask)
+        n = np.array(np.broadcast_to(np.asarray(n, dtype=np.int32), (S,)), dtype=np.int32)
+        n[~self._mask] = 0
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (S,)), dtype=np.float64)
         return n, b
 
     def record_counts(self, n, every):
         n, _ = self._args(n, 0.0)
         if every <= 0:
-            return np.zeros(self.count, dtype=np.int64)
-        return np.where(n > 0, n // every, 1).astype(np.int64)
+            return np.zeros(len(self._mask), dtype=np.int64)
+        counts = np.where(n > 0, n // every, 1).astype(np.int64)
+        counts[~self._mask] = 0
+        return counts
 
     def sweep(self, n, beta, every=0):
-        """Returns a list of (E, M) record arrays per lattice (empty when every == 0)."""
+        """Returns a list of (E, M) record arrays per slot (empty when every == 0 or the slot is free)."""
         n, b = self._args(n, beta)
         counts = self.record_counts(n, every)
         tot = int(counts.sum())
@@ -401,10 +445,11 @@ class Batch:
                                               M.data_ptr() if M is not None else None))
 
     def measure(self):
-        E = np.zeros(self.count, dtype=np.int64)
-        M = np.zeros(self.count, dtype=np.int64)
+        S = max(self.count, 1)
+        E = np.zeros(S, dtype=np.int64)
+        M = np.zeros(S, dtype=np.int64)
         _check(load().spin_batch_measure(self.h, E.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p)))
-        return E, M
+        return E[:self.count], M[:self.count]
 
     def spins(self, i):
         out = np.empty(self.N[i], dtype=np.int8)

@@ -140,8 +140,138 @@ def test_batch_equals_lone_lattices():
     lone1.close()
 
 
-def test_batch_rejects_bad_shapes():
+def test_batch_rejects_bad_descs():
+    J0 = np.ones(2 * 16 * 16, dtype=np.int8)
+    J0[5] = 0
+    for bad in (dict(model=0, L=7, d=2, seed=1),                      # odd L
+                dict(model=0, L=2, d=2, seed=1),                      # L < 4
+                dict(model=0, L=8, d=4, seed=1),                      # d
+                dict(model=2, L=8, d=2, seed=1),                      # model
+                dict(model=0, L=16, d=2, seed=1, couplings=np.ones(512, dtype=np.int8)),
+                dict(model=1, L=16, d=2, seed=1, couplings=J0)):      # a coupling that is not +-1
+        with pytest.raises(spin.SpinError):
+            spin.Batch([dict(model=0, L=8, d=2, seed=1), bad])
+    b = spin.Batch([dict(model=0, L=8, d=2, seed=1)])
     with pytest.raises(spin.SpinError):
-        spin.Batch([dict(model=0, L=12, d=2, seed=1)])      # L % 8 != 0
+        b.remove(1)
     with pytest.raises(spin.SpinError):
-        spin.Batch([dict(model=0, L=128, d=3, seed=1)])     # does not fit LDS
+        b.add(dict(model=0, L=9, d=2, seed=1))
+    assert b.count == 1 and b.members() == [0]
+    b.remove(0)
+    with pytest.raises(spin.SpinError):
+        b.remove(0)
+    # a free slot must get n == 0
+    lib = spin.load()
+    n = np.array([1], dtype=np.int32)
+    beta = np.array([0.5])
+    rc = lib.spin_batch_sweep(b.h, n.ctypes.data_as(spin._ip), beta.ctypes.data_as(spin._dp), 0, None, None)
+    assert rc == spin.SPIN_EINVAL
+    b.close()
+
+
+class Pool:
+    """A batch and the oracle chain of every slot it holds."""
+
+    def __init__(self, oracle_mod):
+        self.o = oracle_mod
+        self.b = spin.Batch([])
+        self.chains = {}
+        self.descs = {}
+
+    def add(self, desc):
+        s = self.b.add(desc)
+        assert s not in self.chains
+        self.chains[s] = oracle_chain(self.o, desc)
+        self.descs[s] = desc
+        np.testing.assert_array_equal(self.b.spins(s), self.chains[s].spins)
+        return s
+
+    def remove(self, s):
+        self.b.remove(s)
+        del self.chains[s]
+        del self.descs[s]
+
+    def step(self, nsweeps, betas, every):
+        S = self.b.count
+        n = np.zeros(S, dtype=np.int32)
+        beta = np.zeros(S)
+        for s in self.chains:
+            n[s] = nsweeps[s]
+            beta[s] = betas[s]
+        note("pool step", dict((s, (int(n[s]), self.descs[s]["L"], self.descs[s]["d"])) for s in self.chains))
+        recs = self.b.sweep(n, beta, every)
+        for s, ch in self.chains.items():
+            if n[s] > 0:
+                Eo, Mo = ch.sweep(int(n[s]), float(beta[s]), every=every)
+            elif every:
+                e, m = ch.measure()
+                Eo, Mo = np.array([e]), np.array([m])
+            else:
+                Eo = Mo = np.zeros(0, dtype=np.int64)
+            if every:
+                np.testing.assert_array_equal(recs[s][0], Eo, err_msg="E of slot %d" % s)
+                np.testing.assert_array_equal(recs[s][1], Mo, err_msg="M of slot %d" % s)
+            got = self.b.spins(s)
+            if not np.array_equal(got, ch.spins):
+                raise AssertionError("slot %d (%s): spins differ at %d sites"
+                                     % (s, self.descs[s], int((got != ch.spins).sum())))
+            assert self.b.t(s) == ch.t
+        for s in range(S):
+            if s not in self.chains:
+                assert recs[s][0].size == 0
+        E, M = self.b.measure()
+        for s, ch in self.chains.items():
+            assert (E[s], M[s]) == ch.measure()
+
+
+def test_pool_add_remove_and_large_members(oracle_mod):
+    """Members too large for one workgroup (or with L % 8 != 0) go to the single-lattice kernels in the
+    same call; removed slots are reused; every member stays on its own chain."""
+    p = Pool(oracle_mod)
+    cs = workloads.seed(0x11)
+    a = p.add(dict(model=0, L=16, d=2, seed=workloads.seed(500), replica=0))
+    b_ = p.add(dict(model=1, L=16, d=3, seed=workloads.seed(501), replica=1, coupling_seed=cs, realisation=2))
+    c = p.add(dict(model=0, L=12, d=2, seed=workloads.seed(502), replica=2))          # L % 8 != 0
+    d = p.add(dict(model=0, L=256, d=2, seed=workloads.seed(503), replica=3))         # LDS-sized, 1024 threads
+    e = p.add(dict(model=1, L=72, d=3, seed=workloads.seed(504), replica=4, coupling_seed=cs, realisation=2))  # > LDS
+    f = p.add(dict(model=1, L=100, d=2, seed=workloads.seed(505), replica=5, coupling_seed=cs, realisation=7))
+    g = p.add(dict(model=0, L=1024, d=2, seed=workloads.seed(506), replica=6))        # beyond one workgroup
+    betas = {a: workloads.BETA_2D_CRIT, b_: 0.9, c: 0.3, d: 0.5, e: 1.1, f: 3.0, g: workloads.BETA_2D_CRIT}
+    p.step({a: 3, b_: 2, c: 4, d: 1, e: 2, f: 3, g: 2}, betas, 1)
+    p.remove(b_)
+    p.remove(e)
+    h = p.add(dict(model=1, L=24, d=3, seed=workloads.seed(507), replica=7, coupling_seed=cs, realisation=2))
+    assert h == e  # most recently freed slot first
+    betas[h] = 0.8
+    p.step({a: 2, c: 0, d: 2, f: 4, g: 2, h: 4}, betas, 2)
+    i = p.add(dict(model=1, L=16, d=3, seed=workloads.seed(508), replica=8, coupling_seed=cs, realisation=2))
+    assert i == b_
+    betas[i] = math.inf
+    p.step({a: 1, c: 2, d: 0, f: 1, g: 1, h: 2, i: 3}, betas, 0)
+    p.step({a: 1, c: 1, d: 1, f: 1, g: 1, h: 1, i: 1}, betas, 1)
+    assert p.b.footprint(g) == 2 * 1024 * 1024       # spins and the second buffer of the streaming kernels
+    assert p.b.footprint(a) == 256
+    assert p.b.footprint(p.b.count) == 0
+    p.b.close()
+
+
+def test_pool_member_equals_lone_run(oracle_mod):
+    """A lattice's bits do not depend on what else is in the pool or when it was admitted."""
+    desc = dict(model=1, L=32, d=3, seed=workloads.seed(600), replica=9, coupling_seed=workloads.seed(0x11),
+                realisation=4)
+    lone = spin.Batch([desc])
+    lone.sweep(7, 0.95)
+    want = lone.spins(0)
+    lone.close()
+    b = spin.Batch([dict(model=0, L=64, d=2, seed=workloads.seed(601), replica=r) for r in range(5)])
+    b.sweep(3, 0.4)
+    b.remove(2)
+    s = b.add(desc)
+    n = np.full(b.count, 2, dtype=np.int32)
+    n[s] = 4
+    b.sweep(n, 0.95)
+    n[:] = 1
+    n[s] = 3
+    b.sweep(n, 0.95)
+    np.testing.assert_array_equal(b.spins(s), want)
+    b.close()

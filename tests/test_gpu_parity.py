@@ -111,6 +111,7 @@ BETAS = [0.30, B_CRIT, 0.60, 0.0, math.inf, 3.0]
 CASES_2D = [
     (GEN, (0, 0, 0, 0), 32), (GEN, (0, 0, 0, 0), 34),
     (RES, (0, 0, 0, 64), 32), (RES, (0, 0, 0, 1024), 64), (RES, (0, 0, 0, 256), 18),
+    (RES, (0, 0, 0, 0), 8), (RES, (0, 0, 0, 256), 512), (RES, (0, 0, 0, 0), 552),
     (TIL, (16, 8, 0, 64), 32), (TIL, (64, 8, 0, 64), 128), (TIL, (128, 16, 0, 256), 256),
     (TIL, (256, 32, 0, 256), 512), (TIL, (512, 32, 0, 512), 1024),
     (FUS, (16, 8, 0, 64), 32), (FUS, (16, 8, 0, 64), 48), (FUS, (128, 16, 0, 256), 256),
@@ -130,6 +131,7 @@ def test_ising2d_all_kernels(oracle_mod, kernel, tile, L):
 CASES_3D = [
     (GEN, (0, 0, 0, 0), 16), (GEN, (0, 0, 0, 0), 10),
     (RES, (0, 0, 0, 256), 16), (RES, (0, 0, 0, 512), 32), (RES, (0, 0, 0, 128), 6),
+    (RES, (0, 0, 0, 0), 8), (RES, (0, 0, 0, 1024), 64),
     (TIL, (16, 4, 4, 64), 16), (TIL, (16, 4, 4, 64), 32), (TIL, (32, 8, 4, 128), 64),
     (TIL, (64, 8, 8, 256), 64), (TIL, (128, 8, 4, 256), 128),
 ]
@@ -145,6 +147,7 @@ def test_ising3d_all_kernels(oracle_mod, kernel, tile, L):
 @pytest.mark.parametrize("kernel,tile,L,d", [
     (GEN, (0, 0, 0, 0), 16, 2), (GEN, (0, 0, 0, 0), 10, 3), (GEN, (0, 0, 0, 0), 24, 3),
     (RES, (0, 0, 0, 256), 14, 2), (RES, (0, 0, 0, 512), 16, 3), (RES, (0, 0, 0, 1024), 24, 3),
+    (RES, (0, 0, 0, 0), 64, 3), (RES, (0, 0, 0, 512), 40, 2),
 ])
 def test_ea_all_kernels(oracle_mod, kernel, tile, L, d):
     sched = [(3, b, 1) for b in [0.5, 1.2, 0.0, math.inf, 3.0]]
