@@ -64,7 +64,9 @@ enum spin_kernel {
   SPIN_KERNEL_GENERIC = 1,  /* per-site, global memory, any even L */
   SPIN_KERNEL_RESIDENT = 2, /* whole lattice in one workgroup's LDS, all sweeps in one launch */
   SPIN_KERNEL_TILED = 3,    /* LDS tile + halo per colour phase, needs L % 8 == 0 */
-  SPIN_KERNEL_FUSED = 4     /* 2D Ising: both colours per launch, ping-pong buffers, needs L % 8 == 0 */
+  SPIN_KERNEL_FUSED = 4,    /* Ising, both colours per launch on the shapes it is built for, ping-pong buffers */
+  SPIN_KERNEL_STREAM = 5    /* both colours per launch streamed over planes, spins nibble-packed in LDS;
+                               any L % 8 == 0 with L >= 16, both models, ping-pong buffers */
 };
 
 /* Full set of creation parameters. */
@@ -138,6 +140,15 @@ int spin_set_stream(spin_lattice* h, void* stream);
  * 0 means the library default.  SPIN_EINVAL if the family cannot run this
  * lattice.  Results are bit-identical for every accepted choice. */
 int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads);
+
+/* Sec. 4 (tile sizes chosen by experiment): time every family and tile that
+ * can run this handle's shape for `sweeps` (1..1000) sweeps at beta on a
+ * scratch lattice of the same shape (the handle's spins, couplings and
+ * sweep counter are untouched), select the fastest for the handle and
+ * remember it for the process: handles of the same (model, L, d) in the
+ * AUTO family use it from then on.  Synchronises.  Returns the chosen
+ * spin_kernel value, or a negative status.  Bits never change. */
+int spin_autotune(spin_lattice* h, double beta, int sweeps);
 
 /* Kernel family that spin_sweep will use next (spin_kernel value). */
 int spin_get_kernel(const spin_lattice* h);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "spin_internal.h"
+#include "spin_nibble.h"
 
 namespace spin {
 
@@ -68,29 +69,5 @@ hipError_t launch_batch(uint32_t d, bool ea, uint32_t nt, BatchLattice* lats, co
 hipError_t launch_couplings_nibble(uint32_t* Jn, uint64_t N, uint32_t d, uint64_t cseed,
                                    uint32_t realisation, hipStream_t stream);
 hipError_t launch_pack_nibbles(const int8_t* src, uint32_t* dst, uint64_t nbytes, hipStream_t stream);
-
-// int8 spins (0x01 / 0xFF) of 8 consecutive sites <-> one word of nibbles
-// (0x1 / 0xF, site j in nibble j).
-__device__ __forceinline__ uint32_t pack_nibbles(uint32_t lo, uint32_t hi) {
-  uint32_t a = lo & 0x0F0F0F0Fu, b = hi & 0x0F0F0F0Fu;
-  a = (a | (a >> 4)) & 0x00FF00FFu;
-  b = (b | (b >> 4)) & 0x00FF00FFu;
-  a = (a | (a >> 8)) & 0x0000FFFFu;
-  b = (b | (b >> 8)) & 0x0000FFFFu;
-  return a | (b << 16);
-}
-
-__device__ __forceinline__ uint32_t nibbles_to_bytes(uint32_t h) {  // 4 nibbles -> 4 bytes
-  uint32_t x = h & 0xFFFFu;
-  x = (x | (x << 8)) & 0x00FF00FFu;
-  x = (x | (x << 4)) & 0x0F0F0F0Fu;
-  const uint32_t neg = (x >> 3) & 0x01010101u;
-  return 0x01010101u + (neg << 8) - (neg << 1);  // 0x01 or 0xFF per byte
-}
-
-__device__ __forceinline__ void unpack_nibbles(uint32_t w, uint32_t& lo, uint32_t& hi) {
-  lo = nibbles_to_bytes(w);
-  hi = nibbles_to_bytes(w >> 16);
-}
 
 }  // namespace spin

@@ -69,50 +69,6 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// Unsatisfied-bond count (2u per nibble) of word c with neighbour words.
-template <int D, bool EA>
-__device__ __forceinline__ uint32_t nib_unsat(uint32_t c, uint32_t lw, uint32_t rw, const uint32_t (&nb)[2 * D - 2],
-                                              const uint32_t (&jn)[2 * D]) {
-  constexpr uint32_t m = 0x22222222u;
-  const uint32_t Lx = __builtin_amdgcn_alignbit(c, lw, 28);  // site x-1 of each nibble
-  const uint32_t Rx = __builtin_amdgcn_alignbit(rw, c, 4);   // site x+1
-  uint32_t S;
-  if (EA) {
-    S = (xor3(c, Lx, jn[0]) & m) + (xor3(c, Rx, jn[1]) & m);
-#pragma unroll
-    for (int k = 0; k < 2 * D - 2; ++k) S += xor3(c, nb[k], jn[2 + k]) & m;
-  } else {
-    S = ((c ^ Lx) & m) + ((c ^ Rx) & m);
-#pragma unroll
-    for (int k = 0; k < 2 * D - 2; ++k) S += (c ^ nb[k]) & m;
-  }
-  return S;
-}
-
-// Flip mask (0xE per flipped nibble) for the active nibbles p, p+2, p+4, p+6:
-// S is shifted so the active nibbles sit at 0, 2, 4, 6 (constant offsets),
-// and the mask is shifted back.
-template <bool NEVER>
-__device__ __forceinline__ uint32_t nib_flips(uint32_t S, uint32_t p, const uint32_t r[4],
-                                              const uint32_t* bound, uint32_t never4) {
-  const uint32_t Sp = S >> (4u * p);
-  uint32_t f = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint32_t u2 = (Sp >> (8 * i)) & 0xFu;  // 2u of active nibble i
-    const uint32_t b = *(const uint32_t*)((const char*)bound + 2u * u2);
-    bool acc = r[i] <= b;
-    if (NEVER) acc = acc && (2u * u2 >= never4);
-    f |= acc ? (0xEu << (8 * i)) : 0u;
-  }
-  return f << (4u * p);
-}
-
-// Global-address-space view of a device pointer (loads with a 32-bit offset
-// from a scalar base instead of 64-bit flat addresses).
-typedef const __attribute__((address_space(1))) uint32_t gu32;
-__device__ __forceinline__ gu32* as_global(const uint32_t* p) { return (gu32*)(p); }
-
 // E = -d N + 2 (unsatisfied bonds), M = N - 2 (negative spins) of the LDS
 // lattice into Cl.E[rec], Cl.M[rec].
 template <int D, bool EA, int NT>

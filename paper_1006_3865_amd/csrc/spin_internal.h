@@ -83,6 +83,13 @@ hipError_t launch_tiled_phase(const Lat& lat, uint32_t t, uint32_t colour, const
 // One whole sweep of a 2D Ising lattice from `src` into `dst` (ping-pong).
 // With rec != nullptr the sweep also records E, M of its result if the
 // kernel can (returns true in *measured), else the caller measures.
+// General streaming sweep (both colours, any L % 8 == 0, L >= 16, both
+// models): tile.y = rows per workgroup (3D), tile.z = planes per strip,
+// tile.threads = 256 or 512.  Jn: nibble-packed couplings (EA) or nullptr.
+bool streamg_supported(const Lat& lat, const Tile& tile);
+size_t streamg_lds_bytes(const Lat& lat, const Tile& tile);
+hipError_t launch_streamg(const Lat& lat, const uint32_t* Jn, const int8_t* src, int8_t* dst, uint32_t t,
+                          const Accept& acc, const Tile& tile, hipStream_t stream);
 bool fused_supported(const Lat& lat, const Tile& tile);
 hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
                               const Accept& acc, const Tile& tile, const Record* rec,

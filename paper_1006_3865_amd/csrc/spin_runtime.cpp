@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "spin.h"
@@ -176,20 +179,44 @@ static void destroy(spin_lattice* h) {
 
 // Workgroup size when the RESIDENT family runs on the nibble batch kernel
 // (L % 8 == 0 and the packed lattice fits LDS), else 0 (the per-site kernel).
-// A requested size of 256, 512 or 1024 is used; none picks by lattice size;
-// any other requested size selects the per-site kernel.
-static uint32_t single_threads(const spin_lattice* h) {
+// A requested size of 256, 512 or 1024 is used; none (0) picks by lattice
+// size; any other requested size selects the per-site kernel.
+static uint32_t single_threads(const spin_lattice* h, const Tile& tile) {
   if (!batch_fits((uint32_t)h->L, (uint32_t)h->d)) return 0;
-  const int req = h->tile.threads;
+  const int req = tile.threads;
   if (req == 0) return batch_threads_for(h->N / 8);
   if (req == 256 || req == 512 || req == 1024) return (uint32_t)req;
   return 0;
 }
 
+// Choices of spin_autotune, per (model, L, d), used by the AUTO family.
+struct Tuned {
+  int kernel;
+  Tile tile;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, Tuned> g_tuned;
+
+static bool tuned_choice(const spin_lattice* h, Tuned* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(h->model, h->L, h->d));
+  if (it == g_tuned.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 static Tile default_tile(const spin_lattice* h, int kernel) {
   Tile t = h->tile;
-  if (t.x && t.y && t.threads && (h->d == 2 || t.z)) return t;
   const int L = h->L;
+  if (kernel == SPIN_KERNEL_STREAM) {  // each field: the request if given, else the default
+    Tile d = h->d == 3 ? Tile{L, (L % 16 == 0 && L >= 64) ? 16 : 8, L >= 16 ? 16 : L, 256}
+                       : Tile{L, 1, L >= 4096 ? 16 : 8, 256};
+    if (t.y && h->d == 3) d.y = t.y;
+    if (t.z) d.z = t.z;
+    if (t.threads) d.threads = t.threads;
+    return d;
+  }
+  if (t.x && t.y && t.threads && (h->d == 2 || t.z)) return t;
   if (kernel == SPIN_KERNEL_FUSED) {
     if (h->d == 3) return Tile{L, 8, 64, 640};
     if (L == 8192) return Tile{8192, 16, 0, 1024};
@@ -210,7 +237,7 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
     if (L % 32 == 0) return Tile{32, 8, 4, 128};
     return Tile{16, 4, 4, 64};
   }
-  if (kernel == SPIN_KERNEL_RESIDENT) return Tile{0, 0, 0, t.threads ? t.threads : 512};
+  if (kernel == SPIN_KERNEL_RESIDENT) return Tile{0, 0, 0, t.threads};
   return Tile{0, 0, 0, 256};
 }
 
@@ -219,10 +246,11 @@ static bool family_ok(const spin_lattice* h, int kernel, const Tile& tile) {
   switch (kernel) {
     case SPIN_KERNEL_GENERIC: return true;
     case SPIN_KERNEL_RESIDENT:
-      if (tile.threads < 64 || tile.threads > 1024 || tile.threads % 64 != 0) return false;
-      return h->N <= kResidentMaxSites || (batch_fits((uint32_t)h->L, (uint32_t)h->d) && single_threads(h));
+      if (tile.threads != 0 && (tile.threads < 64 || tile.threads > 1024 || tile.threads % 64 != 0)) return false;
+      return single_threads(h, tile) != 0 || h->N <= kResidentMaxSites;
     case SPIN_KERNEL_TILED: return tiled_supported(l, tile);
     case SPIN_KERNEL_FUSED: return fused_supported(l, tile);
+    case SPIN_KERNEL_STREAM: return streamg_supported(l, tile);
     default: return false;
   }
 }
@@ -233,11 +261,16 @@ static int resolve(const spin_lattice* h, Tile* tile) {
     *tile = default_tile(h, h->kernel);
     return h->kernel;
   }
+  Tuned tc;
+  if (tuned_choice(h, &tc) && family_ok(h, tc.kernel, tc.tile)) {
+    *tile = tc.tile;
+    return tc.kernel;
+  }
   if (h->N <= kResidentAutoSites) {
     *tile = default_tile(h, SPIN_KERNEL_RESIDENT);
     return SPIN_KERNEL_RESIDENT;
   }
-  const int order[2] = {SPIN_KERNEL_FUSED, SPIN_KERNEL_TILED};
+  const int order[3] = {SPIN_KERNEL_FUSED, SPIN_KERNEL_TILED, SPIN_KERNEL_STREAM};
   for (int k : order) {
     Tile t = default_tile(h, k);
     if (family_ok(h, k, t)) {
@@ -268,6 +301,17 @@ static int check_beta(double beta) {
   return SPIN_OK;
 }
 
+// Nibble-packed couplings (EA) for the kernels that read them, packed on first use.
+static int ensure_jn(spin_lattice* h) {
+  if (h->model != SPIN_EA_PMJ || h->jn) return SPIN_OK;
+  const uint64_t nbytes = (uint64_t)h->d * h->N;
+  h->jn = (uint32_t*)h->mem.get(nbytes / 2);
+  if (!h->jn) return fail(SPIN_ENOMEM, "allocation of the packed couplings failed");
+  hipError_t e = launch_pack_nibbles(h->J, h->jn, nbytes, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "coupling packing launch");
+  return SPIN_OK;
+}
+
 // n sweeps of the whole lattice in one workgroup's LDS (the batch kernel with
 // one task); records (every > 0) go straight to dE, dM.
 static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM,
@@ -276,13 +320,7 @@ static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int6
     h->single = (BatchSingle*)h->mem.get(sizeof(BatchSingle));
     if (!h->single) return fail(SPIN_ENOMEM, "allocation of the one-task block failed");
   }
-  if (h->model == SPIN_EA_PMJ && !h->jn) {
-    const uint64_t nbytes = (uint64_t)h->d * h->N;
-    h->jn = (uint32_t*)h->mem.get(nbytes / 2);
-    if (!h->jn) return fail(SPIN_ENOMEM, "allocation of the packed couplings failed");
-    hipError_t e = launch_pack_nibbles(h->J, h->jn, nbytes, h->stream);
-    if (e != hipSuccess) return hip_fail(e, "coupling packing launch");
-  }
+  if (int rc = ensure_jn(h)) return rc;
   BatchLattice bl;
   bl.spins = h->buf[h->cur];
   bl.Jn = h->jn;
@@ -314,8 +352,8 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   Tile tile;
   const int kernel = resolve(h, &tile);
   hipError_t e = hipSuccess;
-  if (kernel == SPIN_KERNEL_RESIDENT && single_threads(h)) {
-    if (int rc = run_single(h, n, acc, every, dE, dM, single_threads(h))) return rc;
+  if (kernel == SPIN_KERNEL_RESIDENT && single_threads(h, tile)) {
+    if (int rc = run_single(h, n, acc, every, dE, dM, single_threads(h, tile))) return rc;
     h->t += (uint64_t)n;
     return SPIN_OK;
   }
@@ -326,7 +364,9 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
     h->t += (uint64_t)n;
     return SPIN_OK;
   }
-  if (kernel == SPIN_KERNEL_FUSED && !h->buf[1]) {
+  if (kernel == SPIN_KERNEL_STREAM)
+    if (int rc = ensure_jn(h)) return rc;
+  if ((kernel == SPIN_KERNEL_FUSED || kernel == SPIN_KERNEL_STREAM) && !h->buf[1]) {
     h->buf[1] = (int8_t*)h->mem.get(h->N);
     if (!h->buf[1]) return fail(SPIN_ENOMEM, "allocation of the second spin buffer failed");
   }
@@ -347,6 +387,10 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
       e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile,
                              record_now ? &r : nullptr, &measured, h->stream);
       if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
+      h->cur = 1 - h->cur;
+    } else if (kernel == SPIN_KERNEL_STREAM) {
+      e = launch_streamg(l, h->jn, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "stream sweep launch");
       h->cur = 1 - h->cur;
     } else {
       for (uint32_t c = 0; c < 2; ++c) {
@@ -380,6 +424,36 @@ int spin::record_device(spin_lattice* h, int64_t* E, int64_t* M) {
   if (e == hipSuccess) e = launch_finalize(h->part, parts, parts, 1, E, M, e_offset(h), (int64_t)h->N, h->stream);
   if (e != hipSuccess) return hip_fail(e, "record");
   return SPIN_OK;
+}
+
+// Candidate (family, tile) pairs for a shape; family_ok filters them.
+static std::vector<Tuned> tune_candidates(const spin_lattice* h) {
+  std::vector<Tuned> c;
+  const int L = h->L;
+  for (int th : {256, 512, 1024}) c.push_back({SPIN_KERNEL_RESIDENT, Tile{0, 0, 0, th}});
+  c.push_back({SPIN_KERNEL_RESIDENT, Tile{0, 0, 0, 512 + 64}});  // the per-site resident kernel
+  if (h->d == 2) {
+    for (int th : {256, 512, 1024})
+      for (int H : {8, 16, 32}) c.push_back({SPIN_KERNEL_FUSED, Tile{L, H, 0, th}});
+    const int f2[7][3] = {{256, 32, 256}, {512, 32, 512}, {128, 16, 256}, {16, 8, 64},
+                          {512, 16, 256}, {512, 32, 256}, {512, 64, 256}};
+    for (auto& f : f2) c.push_back({SPIN_KERNEL_FUSED, Tile{f[0], f[1], 0, f[2]}});
+    const int t2[5][3] = {{256, 32, 256}, {128, 16, 256}, {512, 32, 512}, {64, 8, 64}, {16, 8, 64}};
+    for (auto& f : t2) c.push_back({SPIN_KERNEL_TILED, Tile{f[0], f[1], 0, f[2]}});
+    for (int th : {256, 512})
+      for (int H : {4, 8, 16, 32}) c.push_back({SPIN_KERNEL_STREAM, Tile{L, 1, H, th}});
+  } else {
+    const int f3[5][2] = {{8, 640}, {8, 320}, {16, 576}, {16, 384}, {32, 704}};
+    for (auto& f : f3)
+      for (int H : {8, 16, 32}) c.push_back({SPIN_KERNEL_FUSED, Tile{L, f[0], H, f[1]}});
+    const int t3[4][4] = {{64, 8, 8, 256}, {32, 8, 4, 128}, {128, 8, 4, 256}, {16, 4, 4, 64}};
+    for (auto& f : t3) c.push_back({SPIN_KERNEL_TILED, Tile{f[0], f[1], f[2], f[3]}});
+    for (int th : {256, 512})
+      for (int TY : {4, 8, 16, 32})
+        for (int H : {8, 16, 32}) c.push_back({SPIN_KERNEL_STREAM, Tile{L, TY, H, th}});
+  }
+  c.push_back({SPIN_KERNEL_GENERIC, Tile{0, 0, 0, 256}});
+  return c;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -597,7 +671,7 @@ int spin_set_stream(spin_lattice* h, void* stream) {
 
 int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
-  if (kernel < SPIN_KERNEL_AUTO || kernel > SPIN_KERNEL_FUSED) return fail(SPIN_EINVAL, "unknown kernel family %d", kernel);
+  if (kernel < SPIN_KERNEL_AUTO || kernel > SPIN_KERNEL_STREAM) return fail(SPIN_EINVAL, "unknown kernel family %d", kernel);
   const int old_kernel = h->kernel;
   const Tile old_tile = h->tile;
   h->kernel = kernel;
@@ -612,6 +686,64 @@ int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int til
     }
   }
   return SPIN_OK;
+}
+
+int spin_autotune(spin_lattice* h, double beta, int sweeps) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (int rc = check_beta(beta)) return rc;
+  if (sweeps < 1 || sweeps > 1000) return fail(SPIN_EINVAL, "sweeps must be in 1..1000");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  spin_config c;
+  std::memset(&c, 0, sizeof(c));
+  c.model = h->model;
+  c.L = h->L;
+  c.d = h->d;
+  c.coupling_seed = 1;
+  c.seed = h->seed;
+  c.replica = h->replica;
+  c.stream = h->stream;
+  spin_lattice* s = spin_create_config(&c);
+  if (!s) return SPIN_ENOMEM;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) {
+    destroy(s);
+    return hip_fail(hipGetLastError(), "autotune event");
+  }
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    destroy(s);
+    return hip_fail(hipGetLastError(), "autotune event");
+  }
+  float best_ms = 1e30f;
+  Tuned best{SPIN_KERNEL_GENERIC, Tile{0, 0, 0, 256}};
+  for (const Tuned& cand : tune_candidates(h)) {
+    s->kernel = cand.kernel;
+    s->tile = cand.tile;
+    if (!family_ok(s, cand.kernel, default_tile(s, cand.kernel))) continue;
+    if (run_sweeps(s, 1, beta, 0, nullptr, nullptr) != SPIN_OK) continue;
+    if (hipEventRecord(e0, s->stream) != hipSuccess) continue;
+    if (run_sweeps(s, sweeps, beta, 0, nullptr, nullptr) != SPIN_OK) continue;
+    float ms = 0;
+    if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      continue;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = Tuned{cand.kernel, default_tile(s, cand.kernel)};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  destroy(s);
+  g_error.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(h->model, h->L, h->d)] = best;
+  }
+  h->kernel = best.kernel;
+  h->tile = best.tile;
+  return best.kernel;
 }
 
 int spin_get_kernel(const spin_lattice* h) {

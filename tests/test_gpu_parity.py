@@ -20,6 +20,7 @@ B_CRIT = workloads.BETA_2D_CRIT
 B_3D = workloads.BETA_3D
 GEN, RES, TIL, FUS = (spin.SPIN_KERNEL_GENERIC, spin.SPIN_KERNEL_RESIDENT, spin.SPIN_KERNEL_TILED,
                       spin.SPIN_KERNEL_FUSED)
+STR = spin.SPIN_KERNEL_STREAM
 
 
 def note(*a):
@@ -118,6 +119,8 @@ CASES_2D = [
     (FUS, (256, 32, 0, 256), 512), (FUS, (512, 32, 0, 512), 1024), (FUS, (256, 32, 0, 256), 256),
     (FUS, (512, 16, 0, 256), 512), (FUS, (512, 32, 0, 256), 1024), (FUS, (512, 64, 0, 256), 1024),
     (FUS, (512, 64, 0, 256), 2048),
+    (STR, (0, 1, 8, 256), 16), (STR, (0, 1, 5, 512), 40), (STR, (0, 1, 3, 256), 72),
+    (STR, (0, 1, 16, 256), 1024), (STR, (0, 1, 7, 512), 2056),
 ]
 
 
@@ -132,6 +135,8 @@ CASES_3D = [
     (GEN, (0, 0, 0, 0), 16), (GEN, (0, 0, 0, 0), 10),
     (RES, (0, 0, 0, 256), 16), (RES, (0, 0, 0, 512), 32), (RES, (0, 0, 0, 128), 6),
     (RES, (0, 0, 0, 0), 8), (RES, (0, 0, 0, 1024), 64),
+    (STR, (0, 8, 16, 256), 16), (STR, (0, 4, 5, 256), 24), (STR, (0, 16, 16, 512), 64),
+    (STR, (0, 8, 7, 256), 72), (STR, (0, 32, 16, 256), 128), (STR, (0, 16, 3, 512), 48),
     (TIL, (16, 4, 4, 64), 16), (TIL, (16, 4, 4, 64), 32), (TIL, (32, 8, 4, 128), 64),
     (TIL, (64, 8, 8, 256), 64), (TIL, (128, 8, 4, 256), 128),
 ]
@@ -148,6 +153,8 @@ def test_ising3d_all_kernels(oracle_mod, kernel, tile, L):
     (GEN, (0, 0, 0, 0), 16, 2), (GEN, (0, 0, 0, 0), 10, 3), (GEN, (0, 0, 0, 0), 24, 3),
     (RES, (0, 0, 0, 256), 14, 2), (RES, (0, 0, 0, 512), 16, 3), (RES, (0, 0, 0, 1024), 24, 3),
     (RES, (0, 0, 0, 0), 64, 3), (RES, (0, 0, 0, 512), 40, 2),
+    (STR, (0, 1, 8, 256), 64, 2), (STR, (0, 1, 6, 512), 1000, 2), (STR, (0, 8, 16, 256), 48, 3),
+    (STR, (0, 16, 16, 512), 96, 3), (STR, (0, 8, 5, 256), 16, 3), (STR, (0, 0, 0, 0), 136, 3),
 ])
 def test_ea_all_kernels(oracle_mod, kernel, tile, L, d):
     sched = [(3, b, 1) for b in [0.5, 1.2, 0.0, math.inf, 3.0]]
@@ -160,6 +167,21 @@ def test_ea_host_couplings(oracle_mod):
     L, d = 12, 3
     J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d)
     compare_runs(oracle_mod, 1, L, d, 77, [(5, 0.8, 1)], J=J, tag="ea-host")
+    L = 40
+    J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d)
+    compare_runs(oracle_mod, 1, L, d, 78, [(4, 0.8, 2), (3, 1.9, 1)], J=J, kernel=STR, tile=(0, 8, 8, 256),
+                 tag="ea-host-stream")
+
+
+@pytest.mark.parametrize("model,L,d", [(1, 128, 3), (1, 72, 3), (0, 72, 3), (1, 1024, 2)])
+def test_auto_picks_stream(oracle_mod, model, L, d):
+    """Shapes no specialised kernel covers (any +-J lattice beyond LDS size, 3D L not a multiple of 16)."""
+    lat = make(model, L, d, workloads.seed(60 + L), 3, None, workloads.seed(0x11) if model else None, 0,
+               (0, 0, 0, 0))
+    assert lat.kernel == STR, spin.KERNEL_NAMES[lat.kernel]
+    lat.close()
+    compare_runs(oracle_mod, model, L, d, workloads.seed(60 + L), [(2, 0.7, 1)], replica=3,
+                 cseed=workloads.seed(0x11) if model else None, tag="auto-stream")
 
 
 def test_auto_choice_and_switching(oracle_mod):
@@ -264,4 +286,32 @@ def test_ising3d_L512_first_sweep(oracle_mod):
         np.testing.assert_array_equal(E, Eo)
         np.testing.assert_array_equal(M, Mo)
         np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
+
+
+@pytest.mark.parametrize("model,L,d", [(0, 256, 3), (1, 96, 3), (0, 2048, 2), (1, 48, 3)])
+def test_autotune_keeps_chain_and_parity(oracle_mod, model, L, d):
+    """spin_autotune leaves the handle's chain untouched, and the family it picks (also taken by new
+    AUTO handles of the shape) gives the oracle's bits."""
+    s = workloads.seed(70 + L)
+    cs = workloads.seed(0x11) if model else None
+    lat = make(model, L, d, s, 2, None, cs)
+    lat.sweep(2, 0.6)
+    before, t = lat.spins(), lat.t
+    k = lat.autotune(0.6, 2)
+    note("autotune", model, L, d, "->", spin.KERNEL_NAMES[k])
+    assert k == lat.kernel and k in spin.KERNEL_NAMES and k != spin.SPIN_KERNEL_AUTO
+    np.testing.assert_array_equal(lat.spins(), before)
+    assert lat.t == t
+    other = make(model, L, d, s, 2, None, cs)
+    assert other.kernel == k
+    other.close()
+    Jo = oracle_mod.couplings(L, d, cs, 0) if model else None
+    ch = oracle_mod.Chain(L, d, s, 2, J=Jo)
+    ch.sweep(2, 0.6)
+    E, M = lat.sweep_record(3, 0.6, 1)
+    Eo, Mo = ch.sweep(3, 0.6, every=1)
+    np.testing.assert_array_equal(E, Eo)
+    np.testing.assert_array_equal(M, Mo)
+    np.testing.assert_array_equal(lat.spins(), ch.spins)
     lat.close()
