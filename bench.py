@@ -56,9 +56,21 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sources_sha():
+# Source files that define each profiled kernel (its counters are valid while they are unchanged).
+KERNEL_SOURCES = {
+    "k_stream2d": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h"),
+    "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h"),
+    "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
+    "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
+}
+
+
+def kernel_sources_sha(kernel_tag):
+    files = KERNEL_SOURCES.get(kernel_tag)
+    if files is None:
+        return None
     h = hashlib.sha256()
-    for f in ("spin_kernels.hip", "spin_device.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1006_3865_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -68,7 +80,9 @@ def profiled_traffic(kernel_tag, L):
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
-    sha = kernel_sources_sha()
+    sha = kernel_sources_sha(kernel_tag)
+    if sha is None:
+        return None
     for f in sorted(os.listdir(pdir)):
         if not f.endswith(".md"):
             continue

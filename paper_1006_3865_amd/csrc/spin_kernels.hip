@@ -7,14 +7,17 @@
 //   tiled     one colour phase, an LDS tile plus a one-site halo, updated in
 //             place, 8-site groups processed four sites per register (2D/3D
 //             Ising, L % 8 == 0);
-//   fused     2D Ising, a whole sweep per launch: tile plus a two-site halo,
-//             colour 0 on the tile and its one-site ring, barrier, colour 1
-//             on the tile, written to the other buffer of a ping-pong pair.
+//   fused     Ising, a whole sweep per launch, written to the other buffer of
+//             a ping-pong pair: 2D tiles plus a two-site halo (colour 0 on
+//             the tile and its one-site ring, barrier, colour 1 on the tile)
+//             here; the row- and plane-streaming kernels of the large 2D and
+//             3D lattices in spin_stream2d.hip and spin_stream3d.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "spin_device.h"
 #include "spin_internal.h"
+#include "spin_phase.h"
 
 namespace spin {
 
@@ -83,14 +86,6 @@ hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t stream) {
 
 // ================================================================ geometry
 
-// (v - back) mod L for 0 <= v < L + 2L and back <= L: the coordinate `back`
-// sites before v, wrapped periodically.
-__device__ __forceinline__ uint32_t wrap_row(uint32_t v, uint32_t back, uint32_t L) {
-  uint32_t w = v + L - back;  // in [0, 3L)
-  if (w >= L) w -= L;
-  if (w >= L) w -= L;
-  return w;
-}
 
 // Coordinates and wrapped neighbours of site s (generic paths).
 struct Site {
@@ -390,28 +385,6 @@ hipError_t launch_resident(const Lat& lat, uint32_t t0, int n, const Accept& acc
 
 // =============================================================== tiled
 
-// Kernel arguments of the register-parallel phase kernels.
-struct PhaseArgs {
-  RoundKeys keys;
-  uint32_t bound[8];
-  uint32_t never4;  // 4 * never_level
-  uint32_t L;
-  uint32_t t;
-  uint32_t colour;
-  uint32_t replica;
-};
-
-static PhaseArgs phase_args(const Lat& lat, uint32_t t, uint32_t colour, const Accept& acc) {
-  PhaseArgs a;
-  a.keys = lat.keys;
-  for (int i = 0; i < 8; ++i) a.bound[i] = acc.bound[i];
-  a.never4 = 4u * acc.never_level;
-  a.L = lat.L;
-  a.t = t;
-  a.colour = colour;
-  a.replica = lat.replica;
-  return a;
-}
 
 // 2D colour phase.  LDS row (TW+32 bytes): byte q <-> x = x0 - 16 + q, so the
 // tile occupies bytes [16, 16+TW), its halo dwords [12,16) and [16+TW, 20+TW).
@@ -770,428 +743,14 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
   }
 }
 
-// 2D Ising, one whole sweep, streaming over full-width rows.  L = 8 * NT * G:
-// thread l owns the groups g = l + NT*j (j < G) of every row (x = 8g).  A
-// workgroup owns the strip of H rows [y0, y0+H) (H even) and keeps a ring of 8
-// rows in LDS (row k of the strip, k = y - (y0-2), lives in slot k & 7; a
-// row's bytes sit at [16, 16+L) with x = L-16..L-1 copied to [0,16) and
-// x = 0..15 to [16+L, 32+L)).  Step i (i = 0..H+2), with a = y0-1+i:
-//   load row a+2 into registers (stored to LDS at the end of the step);
-//   colour 0 on row a (i <= H+1): reads rows a-1..a+1, writes row a in LDS;
-//   colour 1 on row a-2 (i >= 3): reads rows a-3..a-1, writes dst;
-//   barrier.
-// Row a's colour-1 bytes are still the old ones when colour 0 reads them
-// (colour 1 reaches row a two steps later), and colour 1 on row a-2 reads
-// colour-0 bytes finished one or more steps earlier.  The step loop is
-// unrolled over the ring period so that ring slots and row parities (y0 is
-// even) are compile-time constants.
-template <int NT, int G>
-struct StreamCtx {
-  static constexpr uint32_t L = 8u * NT * G;
-  static constexpr uint32_t GPR = L / 8;
-  static constexpr uint32_t RBS = L + 32;
-  const int8_t* __restrict__ src;
-  int8_t* __restrict__ dst;
-  int8_t* ring;
-  const uint32_t* bound;
-  const RoundKeys* keys;
-  PhiloxUniform U0, U1;
-  uint32_t never4, y0, H, t;
 
-  __device__ __forceinline__ void get_row(uint32_t y, uint2 (&v)[G]) const {
-    const int8_t* rowp = src + (uint64_t)y * L;
-#pragma unroll
-    for (int j = 0; j < G; ++j) v[j] = *reinterpret_cast<const uint2*>(rowp + 8 * (t + NT * j));
-  }
-  __device__ __forceinline__ void put_row(uint32_t slot, const uint2 (&v)[G]) const {
-    int8_t* row = ring + slot * RBS;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const uint32_t g = t + NT * j;
-      *reinterpret_cast<uint2*>(row + 16 + 8 * g) = v[j];
-      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row + 8 * (g - (GPR - 2))) = v[j];
-      if (g < 2) *reinterpret_cast<uint2*>(row + 16 + L + 8 * g) = v[j];
-    }
-  }
-};
-
-template <int NT, int G, bool NEVER, bool MEAS, uint32_t S>
-__device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t i, int& unsat,
-                                            int& neg) {
-  using C = StreamCtx<NT, G>;
-  constexpr uint32_t L = C::L, GPR = C::GPR, RBS = C::RBS;
-  const uint32_t H = c.H, y0 = c.y0, t = c.t;
-  if (i >= H + 3) return;
-  uint2 nxt[G];
-  const bool do_load = (i <= H);
-  if (do_load) c.get_row(wrap_row(y0 + i + 3, 2u, L), nxt);
-  if (i <= H + 1) {
-    // colour 0 on row a = y0 - 1 + i (strip row k = i + 1); parity of a is (i+1) & 1
-    const uint32_t y = wrap_row(y0 + i + 1, 2u, L);
-    int8_t* row = c.ring + ((S + 1) & 7) * RBS + 16;
-    const int8_t* up = c.ring + (S & 7) * RBS + 16;
-    const int8_t* dn = c.ring + ((S + 2) & 7) * RBS + 16;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const uint32_t g = t + NT * j;
-      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
-      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
-      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
-      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
-      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
-      uint32_t rnd[4];
-      philox_lane(y * GPR + g, c.U0, *c.keys, rnd);
-      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
-      uint32_t S0, S1;
-      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
-      uint32_t c0 = cc.x, c1 = cc.y;
-      apply_group_p<(S + 1) & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
-      *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
-      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
-      if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
-    }
-  }
-  if (i >= 3) {
-    // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1
-    const uint32_t y = y0 + i - 3u;
-    int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
-    const int8_t* up = c.ring + ((S + 6) & 7) * RBS + 16;
-    const int8_t* dn = c.ring + (S & 7) * RBS + 16;
-    int8_t* out = c.dst + (uint64_t)y * L;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const uint32_t g = t + NT * j;
-      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
-      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
-      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
-      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
-      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
-      uint32_t rnd[4];
-      philox_lane(y * GPR + g, c.U1, *c.keys, rnd);
-      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
-      uint32_t S0, S1;
-      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
-      uint32_t c0 = cc.x, c1 = cc.y;
-      apply_group_p<S & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
-      *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(c0, c1);
-      if (MEAS) {
-        // E and M of the swept lattice, counted on final values:
-        //  - row b's negative spins;
-        //  - bonds (b-1, b): row b-1 in LDS is final when b > y0 (written by the
-        //    previous step); for b == y0 it is the ring row y0-1 whose colour-0
-        //    bytes only are final, so only bonds whose row-b end is colour 1
-        //    are counted (the strip above counts the others);
-        //  - for the last row, bonds to the ring row y0+H, same rule;
-        //  - horizontal bonds of row b-1 (final in LDS);
-        // and row b's final bytes go to LDS for the next step.
-        constexpr uint32_t kMsb = 0x80808080u;
-        constexpr uint32_t kCol1 = (S & 1) ? 0x80008000u : 0x00800080u;  // colour-1 bytes of row b
-        *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
-        if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
-        if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
-        neg += __popc(c0 & kMsb) + __popc(c1 & kMsb);
-        const uint32_t vm = (i == 3) ? kCol1 : kMsb;
-        unsat += __popc((c0 ^ u2.x) & vm) + __popc((c1 ^ u2.y) & vm);
-        if (i == H + 2) unsat += __popc((c0 ^ d2.x) & kCol1) + __popc((c1 ^ d2.y) & kCol1);
-        if (i >= 4) {
-          const uint32_t nx = *reinterpret_cast<const uint32_t*>(up + 8 * g + 8);
-          unsat += __popc((u2.x ^ __builtin_amdgcn_alignbyte(u2.y, u2.x, 1)) & kMsb) +
-                   __popc((u2.y ^ __builtin_amdgcn_alignbyte(nx, u2.y, 1)) & kMsb);
-        }
-      }
-    }
-  }
-  if (do_load) c.put_row((S + 3) & 7, nxt);
-  __syncthreads();
-}
-
-template <int NT, int G, bool NEVER, bool MEAS>
-__global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
-                                                 int8_t* __restrict__ dst, PhaseArgs a,
-                                                 uint32_t H, Record rec) {
-  using C = StreamCtx<NT, G>;
-  // one LDS block: the bound table at byte 0 (a lookup address is just 4u),
-  // then the 8-row ring
-  __shared__ __align__(16) int8_t lds[32 + 8 * C::RBS];
-  C c;
-  c.src = src;
-  c.dst = dst;
-  c.ring = lds + 32;
-  c.bound = reinterpret_cast<const uint32_t*>(lds);
-  c.keys = &a.keys;
-  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
-  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
-  c.never4 = a.never4;
-  c.y0 = blockIdx.x * H;
-  c.H = H;
-  c.t = threadIdx.x;
-  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
-  // prologue: rows k = 0, 1, 2 (y0-2, y0-1, y0)
-  for (uint32_t k = 0; k < 3; ++k) {
-    uint2 v[G];
-    c.get_row(wrap_row(c.y0 + k, 2u, C::L), v);
-    c.put_row(k, v);
-  }
-  __syncthreads();
-  const uint32_t steps = H + 3;
-  int unsat = 0, neg = 0;
-  for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
-    stream_step<NT, G, NEVER, MEAS, 0>(c, i0 + 0, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 1>(c, i0 + 1, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 2>(c, i0 + 2, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 3>(c, i0 + 3, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 4>(c, i0 + 4, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 5>(c, i0 + 5, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 6>(c, i0 + 6, unsat, neg);
-    stream_step<NT, G, NEVER, MEAS, 7>(c, i0 + 7, unsat, neg);
-  }
-  if (MEAS) {
-    // horizontal bonds of the strip's last row (final in LDS, strip row k = H + 1)
-    const int8_t* last = c.ring + ((H + 1) & 7) * C::RBS + 16;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const uint32_t g = c.t + NT * j;
-      const uint2 v = *reinterpret_cast<const uint2*>(last + 8 * g);
-      const uint32_t nx = *reinterpret_cast<const uint32_t*>(last + 8 * g + 8);
-      unsat += __popc((v.x ^ __builtin_amdgcn_alignbyte(v.y, v.x, 1)) & 0x80808080u) +
-               __popc((v.y ^ __builtin_amdgcn_alignbyte(nx, v.y, 1)) & 0x80808080u);
-    }
-    __shared__ int64_t red[NT / 64];
-    record_block<NT>(unsat, neg, rec, red);
-  }
-}
-
-// 3D Ising, one whole sweep, streaming over planes.  Rows are full x rows,
-// L = 512 * G (lane l of a wave owns groups g = l + 64 j, j < G).  A
-// workgroup of W waves owns the TY rows [y0, y0+TY) of the planes
-// [z0, z0+H) and keeps a ring of 6 plane slices in LDS; a slice holds the
-// rows y0-2 .. y0+TY+1 (row r <-> y = y0-2+r), each row with 16 wrap bytes
-// on both sides.  Plane k of the strip (z = z0-2+k) lives in slot k % 6.
-// Step i (i = 0..H+2), a = z0-1+i:
-//   load plane a+2 (registers; stored to LDS at the end of the step);
-//   colour 0 on plane a, rows y0-1 .. y0+TY (the tile rows and a one-row
-//   ring that colour 1 needs): reads planes a-1..a+1, writes plane a;
-//   colour 1 on plane a-2, rows y0 .. y0+TY-1: reads planes a-3..a-1,
-//   writes dst;
-//   barrier.
-// The 2TY+2 row-units of a step are dealt to the waves round-robin.  The
-// step loop is unrolled over the ring period (slots compile-time; with z0
-// even the plane parities are too).
-template <int TY, int W, int G>
-struct Stream3Ctx {
-  static constexpr uint32_t L = 512u * G;
-  static constexpr uint32_t GPR = L / 8;
-  static constexpr uint32_t RB = L + 32;
-  static constexpr uint32_t RP = TY + 4;
-  static constexpr uint32_t PB = RP * RB;
-  static constexpr int NT = 64 * W;
-  static constexpr int RPW = (RP + W - 1) / W;  // plane rows loaded per wave
-  const int8_t* __restrict__ src;
-  int8_t* __restrict__ dst;
-  int8_t* ring;
-  const uint32_t* bound;
-  const RoundKeys* keys;
-  PhiloxUniform U0, U1;
-  uint32_t never4, y0, z0, H, lane, wave;
-
-  __device__ __forceinline__ void get_plane(uint32_t z, uint2 (&v)[RPW][G]) const {
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      const uint32_t rr = wave + W * q;
-      if (rr < RP) {
-        const uint32_t y = wrap_row(y0 + rr, 2u, L);
-        const int8_t* rowp = src + ((uint64_t)z * L + y) * L;
-#pragma unroll
-        for (int j = 0; j < G; ++j) v[q][j] = *reinterpret_cast<const uint2*>(rowp + 8 * (lane + 64 * j));
-      }
-    }
-  }
-  __device__ __forceinline__ void put_plane(uint32_t slot, const uint2 (&v)[RPW][G]) const {
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      const uint32_t rr = wave + W * q;
-      if (rr < RP) {
-        int8_t* row = ring + slot * PB + rr * RB;
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-          const uint32_t g = lane + 64 * j;
-          *reinterpret_cast<uint2*>(row + 16 + 8 * g) = v[q][j];
-          if (g >= GPR - 2) *reinterpret_cast<uint2*>(row + 8 * (g - (GPR - 2))) = v[q][j];
-          if (g < 2) *reinterpret_cast<uint2*>(row + 16 + L + 8 * g) = v[q][j];
-        }
-      }
-    }
-  }
-};
-
-// One 8-site group of row r (LDS slot PC, z-neighbour slots PM, PP) in colour C.
-template <int TY, int W, int G, bool NEVER, uint32_t C, uint32_t PM, uint32_t PC, uint32_t PP>
-__device__ __forceinline__ void stream3_group(const Stream3Ctx<TY, W, G>& c, uint32_t r, uint32_t y,
-                                              uint32_t z, uint32_t g, uint32_t& o_lo,
-                                              uint32_t& o_hi) {
-  using X = Stream3Ctx<TY, W, G>;
-  constexpr uint32_t L = X::L, RB = X::RB, PB = X::PB;
-  const int8_t* row = c.ring + PC * PB + r * RB + 16;
-  const int8_t* zm = c.ring + PM * PB + r * RB + 16;
-  const int8_t* zp = c.ring + PP * PB + r * RB + 16;
-  const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
-  const uint2 ym = *reinterpret_cast<const uint2*>(row - RB + 8 * g);
-  const uint2 yp = *reinterpret_cast<const uint2*>(row + RB + 8 * g);
-  const uint2 a2 = *reinterpret_cast<const uint2*>(zm + 8 * g);
-  const uint2 b2 = *reinterpret_cast<const uint2*>(zp + 8 * g);
-  const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
-  const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
-  uint32_t rnd[4];
-  const uint32_t cbase = (uint32_t)((((uint64_t)z * L + y) * L) >> 3);
-  philox_lane(cbase + g, C ? c.U1 : c.U0, *c.keys, rnd);
-  const uint32_t o0[4] = {ym.x, yp.x, a2.x, b2.x}, o1[4] = {ym.y, yp.y, a2.y, b2.y};
-  uint32_t S0, S1;
-  unsat_ising<4>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
-  uint32_t c0 = cc.x, c1 = cc.y;
-  apply_group<NEVER>(c0, c1, S0, S1, (C + y + z) & 1u, rnd, c.bound, c.never4);
-  o_lo = c0;
-  o_hi = c1;
-}
-
-// Step i of the plane pipeline.  Wave w updates colour-0 rows 1 + w + W q
-// (q < N0, rows 1..TY+2 of plane a) and colour-1 rows 2 + w + W q (q < N1,
-// rows 2..TY+1 of plane a-2); rows past the end are computed on a valid row
-// and not stored, so the compute is straight-line and the units interleave.
-template <int TY, int W, int G, bool NEVER, uint32_t S>
-__device__ __forceinline__ void stream3_step(const Stream3Ctx<TY, W, G>& c, uint32_t i) {
-  using X = Stream3Ctx<TY, W, G>;
-  constexpr uint32_t L = X::L, GPR = X::GPR, RB = X::RB, PB = X::PB;
-  constexpr int N0 = (TY + 2 + W - 1) / W, N1 = (TY + W - 1) / W;
-  const uint32_t H = c.H;
-  if (i >= H + 3) return;
-  uint2 nxt[X::RPW][G];
-  const bool do_load = (i <= H);
-  if (do_load) c.get_plane(wrap_row(c.z0 + i + 3, 2u, L), nxt);
-  const bool col0 = (i <= H + 1), col1 = (i >= 3);
-  const uint32_t za = wrap_row(c.z0 + i + 1, 2u, L);  // plane a = z0 - 1 + i
-  const uint32_t zb = c.z0 + i - 3u;                   // plane a - 2
-  uint32_t r0[N0], r1[N1], y0v[N0], y1v[N1];
-#pragma unroll
-  for (int q = 0; q < N0; ++q) {
-    const uint32_t rr = 1u + c.wave + W * q;
-    r0[q] = rr <= TY + 2u ? rr : TY + 2u;
-    y0v[q] = wrap_row(c.y0 + r0[q], 2u, L);
-  }
-#pragma unroll
-  for (int q = 0; q < N1; ++q) {
-    const uint32_t rr = 2u + c.wave + W * q;
-    r1[q] = rr <= TY + 1u ? rr : TY + 1u;
-    y1v[q] = c.y0 + r1[q] - 2u;
-  }
-  uint32_t v0[N0][G][2], v1[N1][G][2];
-#pragma unroll
-  for (int j = 0; j < G; ++j) {
-    const uint32_t g = c.lane + 64 * j;
-#pragma unroll
-    for (int q = 0; q < N0; ++q)
-      stream3_group<TY, W, G, NEVER, 0, S % 6, (S + 1) % 6, (S + 2) % 6>(c, r0[q], y0v[q], za, g, v0[q][j][0], v0[q][j][1]);
-#pragma unroll
-    for (int q = 0; q < N1; ++q)
-      stream3_group<TY, W, G, NEVER, 1, (S + 4) % 6, (S + 5) % 6, S % 6>(c, r1[q], y1v[q], zb, g, v1[q][j][0], v1[q][j][1]);
-  }
-  if (col0) {
-#pragma unroll
-    for (int q = 0; q < N0; ++q) {
-      if (1u + c.wave + W * q > TY + 2u) break;
-      int8_t* row = c.ring + ((S + 1) % 6) * PB + r0[q] * RB + 16;
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        const uint32_t g = c.lane + 64 * j;
-        const uint2 v = make_uint2(v0[q][j][0], v0[q][j][1]);
-        *reinterpret_cast<uint2*>(row + 8 * g) = v;
-        if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = v;
-        if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = v;
-      }
-    }
-  }
-  if (col1) {
-#pragma unroll
-    for (int q = 0; q < N1; ++q) {
-      if (2u + c.wave + W * q > TY + 1u) break;
-      int8_t* out = c.dst + ((uint64_t)zb * L + y1v[q]) * L;
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        const uint32_t g = c.lane + 64 * j;
-        *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(v1[q][j][0], v1[q][j][1]);
-      }
-    }
-  }
-  if (do_load) c.put_plane((S + 3) % 6, nxt);
-  __syncthreads();
-}
-
-template <int TY, int W, int G, bool NEVER>
-__global__ __launch_bounds__(64 * W) void k_stream3d(const int8_t* __restrict__ src,
-                                                     int8_t* __restrict__ dst, PhaseArgs a,
-                                                     uint32_t H) {
-  using X = Stream3Ctx<TY, W, G>;
-  __shared__ __align__(16) int8_t lds[32 + 6 * X::PB];
-  X c;
-  c.src = src;
-  c.dst = dst;
-  c.ring = lds + 32;
-  c.bound = reinterpret_cast<const uint32_t*>(lds);
-  c.keys = &a.keys;
-  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
-  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
-  c.never4 = a.never4;
-  c.y0 = blockIdx.x * TY;
-  c.z0 = blockIdx.y * H;
-  c.H = H;
-  c.lane = threadIdx.x & 63;
-  c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
-  for (uint32_t k = 0; k < 3; ++k) {
-    uint2 v[X::RPW][G];
-    c.get_plane(wrap_row(c.z0 + k, 2u, X::L), v);
-    c.put_plane(k, v);
-  }
-  __syncthreads();
-  const uint32_t steps = H + 3;
-  for (uint32_t i0 = 0; i0 < steps; i0 += 6) {
-    stream3_step<TY, W, G, NEVER, 0>(c, i0 + 0);
-    stream3_step<TY, W, G, NEVER, 1>(c, i0 + 1);
-    stream3_step<TY, W, G, NEVER, 2>(c, i0 + 2);
-    stream3_step<TY, W, G, NEVER, 3>(c, i0 + 3);
-    stream3_step<TY, W, G, NEVER, 4>(c, i0 + 4);
-    stream3_step<TY, W, G, NEVER, 5>(c, i0 + 5);
-  }
-}
-
-// Streaming variants: tile.x == L (full rows), tile.y = strip height H,
-// tile.threads = NT with L = 8 * NT * G.
-static bool stream_shape(uint32_t L, int threads, int* G) {
-  if (threads != 256 && threads != 512 && threads != 1024) return false;
-  if (L % (8u * (uint32_t)threads) != 0) return false;
-  const uint32_t g = L / (8u * (uint32_t)threads);
-  if (g != 1 && g != 2) return false;
-  if (threads == 256 && g != 2) return false;  // instantiated: (1024,1) (1024,2) (512,1) (512,2) (256,2)
-  *G = (int)g;
-  return true;
-}
-
-// 3D streaming shapes: tile.x == L == 512*G, tile.y = TY, tile.z = H, threads = 64*W.
-static bool stream3_shape(const Lat& lat, const Tile& tile) {
-  if (lat.J != nullptr || lat.d != 3) return false;
-  if ((uint32_t)tile.x != lat.L || (lat.L != 512 && lat.L != 1024)) return false;
-  const bool ok_shape = (tile.y == 8 && (tile.threads == 640 || tile.threads == 320)) ||
-                        (tile.y == 16 && (tile.threads == 576 || tile.threads == 384)) ||
-                        (tile.y == 32 && tile.threads == 704 && lat.L == 512);
-  return ok_shape && lat.L % (uint32_t)tile.y == 0 && tile.z >= 4 && tile.z % 2 == 0 &&
-         lat.L % (uint32_t)tile.z == 0;
-}
 
 bool fused_supported(const Lat& lat, const Tile& tile) {
-  if (lat.d == 3) return stream3_shape(lat, tile);
+  if (lat.d == 3) return stream3d_shape(lat, tile);
   if (lat.J != nullptr || lat.d != 2) return false;
   if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
     int G;
-    return stream_shape(lat.L, tile.threads, &G) && tile.y >= 4 && tile.y % 2 == 0 &&
+    return stream2d_shape(lat.L, tile.threads, &G) && tile.y >= 4 && tile.y % 2 == 0 &&
            lat.L % (uint32_t)tile.y == 0 && (uint32_t)tile.y <= lat.L;
   }
   if (lat.L % 16 != 0 || lat.L < 32) return false;
@@ -1225,16 +784,6 @@ static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const 
   return hipGetLastError();
 }
 
-template <int TY, int W, int G>
-static hipError_t gostream3(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
-                            bool never, uint32_t H, hipStream_t stream) {
-  dim3 grid(lat.L / TY, lat.L / H);
-  if (never)
-    hipLaunchKernelGGL((k_stream3d<TY, W, G, true>), grid, dim3(64 * W), 0, stream, src, dst, a, H);
-  else
-    hipLaunchKernelGGL((k_stream3d<TY, W, G, false>), grid, dim3(64 * W), 0, stream, src, dst, a, H);
-  return hipGetLastError();
-}
 
 uint32_t fused_record_parts(const Lat& lat, const Tile& tile) {
   if (!fused_supported(lat, tile)) return 0;
@@ -1242,24 +791,6 @@ uint32_t fused_record_parts(const Lat& lat, const Tile& tile) {
   return 0;
 }
 
-template <int NT, int G>
-static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
-                           bool never, uint32_t H, const Record* rec, hipStream_t stream) {
-  dim3 grid(lat.L / H);
-  const Record r = rec ? *rec : Record{nullptr};
-  if (rec) {
-    if (never)
-      hipLaunchKernelGGL((k_stream2d<NT, G, true, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
-    else
-      hipLaunchKernelGGL((k_stream2d<NT, G, false, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
-  } else {
-    if (never)
-      hipLaunchKernelGGL((k_stream2d<NT, G, true, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
-    else
-      hipLaunchKernelGGL((k_stream2d<NT, G, false, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, uint32_t t,
                               const Accept& acc, const Tile& tile, const Record* rec,
@@ -1268,30 +799,12 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
   if (!fused_supported(lat, tile)) return hipErrorInvalidValue;
   const PhaseArgs a = phase_args(lat, t, 0u, acc);
   const bool never = acc.never_level > 0;
-  if (lat.d == 3) {
-    const uint32_t H = (uint32_t)tile.z;
-    if (lat.L == 512) {
-      if (tile.y == 8 && tile.threads == 640) return gostream3<8, 10, 1>(lat, src, dst, a, never, H, stream);
-      if (tile.y == 8) return gostream3<8, 5, 1>(lat, src, dst, a, never, H, stream);
-      if (tile.y == 16 && tile.threads == 576) return gostream3<16, 9, 1>(lat, src, dst, a, never, H, stream);
-      if (tile.y == 16) return gostream3<16, 6, 1>(lat, src, dst, a, never, H, stream);
-      return gostream3<32, 11, 1>(lat, src, dst, a, never, H, stream);
-    }
-    if (tile.y == 8 && tile.threads == 640) return gostream3<8, 10, 2>(lat, src, dst, a, never, H, stream);
-    if (tile.y == 8) return gostream3<8, 5, 2>(lat, src, dst, a, never, H, stream);
-    if (tile.y == 16 && tile.threads == 576) return gostream3<16, 9, 2>(lat, src, dst, a, never, H, stream);
-    return gostream3<16, 6, 2>(lat, src, dst, a, never, H, stream);
-  }
+  if (lat.d == 3) return launch_stream3d(lat, src, dst, a, never, tile, stream);
   if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
     int G = 0;
-    stream_shape(lat.L, tile.threads, &G);
-    const uint32_t H = (uint32_t)tile.y;
+    stream2d_shape(lat.L, tile.threads, &G);
     if (measured) *measured = (rec != nullptr);
-    if (tile.threads == 1024 && G == 1) return gostream<1024, 1>(lat, src, dst, a, never, H, rec, stream);
-    if (tile.threads == 1024 && G == 2) return gostream<1024, 2>(lat, src, dst, a, never, H, rec, stream);
-    if (tile.threads == 512 && G == 1) return gostream<512, 1>(lat, src, dst, a, never, H, rec, stream);
-    if (tile.threads == 512 && G == 2) return gostream<512, 2>(lat, src, dst, a, never, H, rec, stream);
-    return gostream<256, 2>(lat, src, dst, a, never, H, rec, stream);
+    return launch_stream2d(lat, src, dst, a, never, (uint32_t)tile.y, rec, tile.threads, G, stream);
   }
   if (tile.x == 512 && tile.threads == 256) {
     if (tile.y == 16) return gofused_w<16>(lat, src, dst, a, never, stream);

@@ -1,0 +1,243 @@
+// spin_stream2d.hip -- 2D Ising, one whole sweep per launch, streamed over
+// full-width rows (the kernel of the L = 4096 .. 16384 lattices).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spin_device.h"
+#include "spin_phase.h"
+
+namespace spin {
+
+// 2D Ising, one whole sweep, streaming over full-width rows.  L = 8 * NT * G:
+// thread l owns the groups g = l + NT*j (j < G) of every row (x = 8g).  A
+// workgroup owns the strip of H rows [y0, y0+H) (H even) and keeps a ring of 8
+// rows in LDS (row k of the strip, k = y - (y0-2), lives in slot k & 7; a
+// row's bytes sit at [16, 16+L) with x = L-16..L-1 copied to [0,16) and
+// x = 0..15 to [16+L, 32+L)).  Step i (i = 0..H+2), with a = y0-1+i:
+//   load row a+2 into registers (stored to LDS at the end of the step);
+//   colour 0 on row a (i <= H+1): reads rows a-1..a+1, writes row a in LDS;
+//   colour 1 on row a-2 (i >= 3): reads rows a-3..a-1, writes dst;
+//   barrier.
+// Row a's colour-1 bytes are still the old ones when colour 0 reads them
+// (colour 1 reaches row a two steps later), and colour 1 on row a-2 reads
+// colour-0 bytes finished one or more steps earlier.  The step loop is
+// unrolled over the ring period so that ring slots and row parities (y0 is
+// even) are compile-time constants.
+template <int NT, int G>
+struct StreamCtx {
+  static constexpr uint32_t L = 8u * NT * G;
+  static constexpr uint32_t GPR = L / 8;
+  static constexpr uint32_t RBS = L + 32;
+  const int8_t* __restrict__ src;
+  int8_t* __restrict__ dst;
+  int8_t* ring;
+  const uint32_t* bound;
+  const RoundKeys* keys;
+  PhiloxUniform U0, U1;
+  uint32_t never4, y0, H, t;
+
+  __device__ __forceinline__ void get_row(uint32_t y, uint2 (&v)[G]) const {
+    const int8_t* rowp = src + (uint64_t)y * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) v[j] = *reinterpret_cast<const uint2*>(rowp + 8 * (t + NT * j));
+  }
+  __device__ __forceinline__ void put_row(uint32_t slot, const uint2 (&v)[G]) const {
+    int8_t* row = ring + slot * RBS;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      *reinterpret_cast<uint2*>(row + 16 + 8 * g) = v[j];
+      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row + 8 * (g - (GPR - 2))) = v[j];
+      if (g < 2) *reinterpret_cast<uint2*>(row + 16 + L + 8 * g) = v[j];
+    }
+  }
+};
+
+template <int NT, int G, bool NEVER, bool MEAS, uint32_t S>
+__device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t i, int& unsat,
+                                            int& neg) {
+  using C = StreamCtx<NT, G>;
+  constexpr uint32_t L = C::L, GPR = C::GPR, RBS = C::RBS;
+  const uint32_t H = c.H, y0 = c.y0, t = c.t;
+  if (i >= H + 3) return;
+  uint2 nxt[G];
+  const bool do_load = (i <= H);
+  if (do_load) c.get_row(wrap_row(y0 + i + 3, 2u, L), nxt);
+  if (i <= H + 1) {
+    // colour 0 on row a = y0 - 1 + i (strip row k = i + 1); parity of a is (i+1) & 1
+    const uint32_t y = wrap_row(y0 + i + 1, 2u, L);
+    int8_t* row = c.ring + ((S + 1) & 7) * RBS + 16;
+    const int8_t* up = c.ring + (S & 7) * RBS + 16;
+    const int8_t* dn = c.ring + ((S + 2) & 7) * RBS + 16;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
+      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
+      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
+      uint32_t rnd[4];
+      philox_lane(y * GPR + g, c.U0, *c.keys, rnd);
+      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = cc.x, c1 = cc.y;
+      apply_group_p<(S + 1) & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
+      *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
+      if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
+      if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
+    }
+  }
+  if (i >= 3) {
+    // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1
+    const uint32_t y = y0 + i - 3u;
+    int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
+    const int8_t* up = c.ring + ((S + 6) & 7) * RBS + 16;
+    const int8_t* dn = c.ring + (S & 7) * RBS + 16;
+    int8_t* out = c.dst + (uint64_t)y * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = t + NT * j;
+      const uint2 cc = *reinterpret_cast<const uint2*>(row + 8 * g);
+      const uint2 u2 = *reinterpret_cast<const uint2*>(up + 8 * g);
+      const uint2 d2 = *reinterpret_cast<const uint2*>(dn + 8 * g);
+      const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
+      const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
+      uint32_t rnd[4];
+      philox_lane(y * GPR + g, c.U1, *c.keys, rnd);
+      const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
+      uint32_t S0, S1;
+      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      uint32_t c0 = cc.x, c1 = cc.y;
+      apply_group_p<S & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
+      *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(c0, c1);
+      if (MEAS) {
+        // E and M of the swept lattice, counted on final values:
+        //  - row b's negative spins;
+        //  - bonds (b-1, b): row b-1 in LDS is final when b > y0 (written by the
+        //    previous step); for b == y0 it is the ring row y0-1 whose colour-0
+        //    bytes only are final, so only bonds whose row-b end is colour 1
+        //    are counted (the strip above counts the others);
+        //  - for the last row, bonds to the ring row y0+H, same rule;
+        //  - horizontal bonds of row b-1 (final in LDS);
+        // and row b's final bytes go to LDS for the next step.
+        constexpr uint32_t kMsb = 0x80808080u;
+        constexpr uint32_t kCol1 = (S & 1) ? 0x80008000u : 0x00800080u;  // colour-1 bytes of row b
+        *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
+        if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
+        if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
+        neg += __popc(c0 & kMsb) + __popc(c1 & kMsb);
+        const uint32_t vm = (i == 3) ? kCol1 : kMsb;
+        unsat += __popc((c0 ^ u2.x) & vm) + __popc((c1 ^ u2.y) & vm);
+        if (i == H + 2) unsat += __popc((c0 ^ d2.x) & kCol1) + __popc((c1 ^ d2.y) & kCol1);
+        if (i >= 4) {
+          const uint32_t nx = *reinterpret_cast<const uint32_t*>(up + 8 * g + 8);
+          unsat += __popc((u2.x ^ __builtin_amdgcn_alignbyte(u2.y, u2.x, 1)) & kMsb) +
+                   __popc((u2.y ^ __builtin_amdgcn_alignbyte(nx, u2.y, 1)) & kMsb);
+        }
+      }
+    }
+  }
+  if (do_load) c.put_row((S + 3) & 7, nxt);
+  __syncthreads();
+}
+
+template <int NT, int G, bool NEVER, bool MEAS>
+__global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
+                                                 int8_t* __restrict__ dst, PhaseArgs a,
+                                                 uint32_t H, Record rec) {
+  using C = StreamCtx<NT, G>;
+  // one LDS block: the bound table at byte 0 (a lookup address is just 4u),
+  // then the 8-row ring
+  __shared__ __align__(16) int8_t lds[32 + 8 * C::RBS];
+  C c;
+  c.src = src;
+  c.dst = dst;
+  c.ring = lds + 32;
+  c.bound = reinterpret_cast<const uint32_t*>(lds);
+  c.keys = &a.keys;
+  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
+  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
+  c.never4 = a.never4;
+  c.y0 = blockIdx.x * H;
+  c.H = H;
+  c.t = threadIdx.x;
+  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
+  // prologue: rows k = 0, 1, 2 (y0-2, y0-1, y0)
+  for (uint32_t k = 0; k < 3; ++k) {
+    uint2 v[G];
+    c.get_row(wrap_row(c.y0 + k, 2u, C::L), v);
+    c.put_row(k, v);
+  }
+  __syncthreads();
+  const uint32_t steps = H + 3;
+  int unsat = 0, neg = 0;
+  for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
+    stream_step<NT, G, NEVER, MEAS, 0>(c, i0 + 0, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 1>(c, i0 + 1, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 2>(c, i0 + 2, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 3>(c, i0 + 3, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 4>(c, i0 + 4, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 5>(c, i0 + 5, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 6>(c, i0 + 6, unsat, neg);
+    stream_step<NT, G, NEVER, MEAS, 7>(c, i0 + 7, unsat, neg);
+  }
+  if (MEAS) {
+    // horizontal bonds of the strip's last row (final in LDS, strip row k = H + 1)
+    const int8_t* last = c.ring + ((H + 1) & 7) * C::RBS + 16;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint32_t g = c.t + NT * j;
+      const uint2 v = *reinterpret_cast<const uint2*>(last + 8 * g);
+      const uint32_t nx = *reinterpret_cast<const uint32_t*>(last + 8 * g + 8);
+      unsat += __popc((v.x ^ __builtin_amdgcn_alignbyte(v.y, v.x, 1)) & 0x80808080u) +
+               __popc((v.y ^ __builtin_amdgcn_alignbyte(nx, v.y, 1)) & 0x80808080u);
+    }
+    __shared__ int64_t red[NT / 64];
+    record_block<NT>(unsat, neg, rec, red);
+  }
+}
+
+// Streaming variants: tile.x == L (full rows), tile.y = strip height H,
+// tile.threads = NT with L = 8 * NT * G.
+bool stream2d_shape(uint32_t L, int threads, int* G) {
+  if (threads != 256 && threads != 512 && threads != 1024) return false;
+  if (L % (8u * (uint32_t)threads) != 0) return false;
+  const uint32_t g = L / (8u * (uint32_t)threads);
+  if (g != 1 && g != 2) return false;
+  if (threads == 256 && g != 2) return false;  // instantiated: (1024,1) (1024,2) (512,1) (512,2) (256,2)
+  *G = (int)g;
+  return true;
+}
+
+template <int NT, int G>
+static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a,
+                           bool never, uint32_t H, const Record* rec, hipStream_t stream) {
+  dim3 grid(lat.L / H);
+  const Record r = rec ? *rec : Record{nullptr};
+  if (rec) {
+    if (never)
+      hipLaunchKernelGGL((k_stream2d<NT, G, true, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2d<NT, G, false, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  } else {
+    if (never)
+      hipLaunchKernelGGL((k_stream2d<NT, G, true, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2d<NT, G, false, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stream2d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
+                           uint32_t H, const Record* rec, int threads, int G, hipStream_t stream) {
+  if (threads == 1024 && G == 1) return gostream<1024, 1>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 1024 && G == 2) return gostream<1024, 2>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 512 && G == 1) return gostream<512, 1>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 512 && G == 2) return gostream<512, 2>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 256 && G == 2) return gostream<256, 2>(lat, src, dst, a, never, H, rec, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace spin
