@@ -182,7 +182,10 @@ const char* spin_version(void);
  * 2D L <= 552, 3D L <= 64) is swept by one persistent launch per class of
  * (d, model, size) that takes the members from a queue, largest work first;
  * any other valid lattice (even L >= 4) is advanced by the single-lattice
- * kernels on the batch's stream within the same call.  Every member follows
+ * kernels within the same call, on internal streams that start after the
+ * work already queued on the batch's stream and that the batch's stream
+ * waits for before its later work, so they run alongside the persistent
+ * launch and each other.  Every member follows
  * exactly the chain of a lone lattice with the same seed, replica and
  * couplings (same bits).
  *

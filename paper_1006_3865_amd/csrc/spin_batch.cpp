@@ -130,6 +130,7 @@ struct Member {
   bool jn_shared = false;        // jn belongs to the shared map under `key`
   CouplingKey key;
   spin_lattice* big = nullptr;   // not resident: a single-lattice handle
+  int aux = 0;                   // not resident: index of its stream
 };
 
 struct Shared {
@@ -166,6 +167,14 @@ struct spin_batch {
   int64_t* d_rec = nullptr;
   size_t rec_cap = 0;
   hipStream_t stream = nullptr;
+  // Larger members run on these streams (members round-robin), forked from
+  // `stream` at the start of a call and joined back at its end, so that they
+  // overlap each other and the persistent launch.
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t joined[kAux] = {};
+  int next_aux = 0;
   int num_cu = 256;
   int wgs_override = 0;               // 0: by occupancy
 };
@@ -203,6 +212,14 @@ static void batch_destroy(spin_batch* b) {
   if (b->h_calls) (void)hipHostFree(b->h_calls);
   if (b->h_order) (void)hipHostFree(b->h_order);
   if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (int k = 0; k < spin_batch::kAux; ++k) {
+    if (b->joined[k]) (void)hipEventDestroy(b->joined[k]);
+    if (b->aux[k]) {
+      (void)hipStreamSynchronize(b->aux[k]);
+      (void)hipStreamDestroy(b->aux[k]);
+    }
+  }
   delete b;
 }
 
@@ -291,7 +308,9 @@ static int init_member(spin_batch* b, int slot, const spin_desc& s, bool upload)
     c.realisation = s.realisation;
     c.seed = s.seed;
     c.replica = s.replica;
-    c.stream = b->stream;
+    mb.aux = b->next_aux;
+    b->next_aux = (b->next_aux + 1) % spin_batch::kAux;
+    c.stream = b->aux[mb.aux];
     mb.big = spin_create_config(&c);
     if (!mb.big) return SPIN_EINVAL;  // message set by spin_create_config
     mb.active = true;
@@ -385,6 +404,18 @@ static int add_member(spin_batch* b, const spin_desc& s, bool upload) {
   return slot;
 }
 
+// Make later work on the pool's stream wait for what the calls enqueued on
+// the auxiliary streams marked in `used`.
+static int join_aux(spin_batch* b, const bool* used) {
+  for (int k = 0; k < spin_batch::kAux; ++k) {
+    if (!used[k]) continue;
+    hipError_t e = hipEventRecord(b->joined[k], b->aux[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->joined[k], 0);
+    if (e != hipSuccess) return hfail(e, "batch join");
+  }
+  return SPIN_OK;
+}
+
 static bool slot_ok(const spin_batch* b, int i) { return b && i >= 0 && i < (int)b->m.size() && b->m[i].active; }
 
 // Advance slot i by n[i] sweeps at beta[i]; slot i's records go to device
@@ -443,6 +474,34 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     cl.members.push_back((uint32_t)i);
     cl.lds = std::max(cl.lds, batch_lds_bytes((uint32_t)mb.L, (uint32_t)mb.d));
   }
+  // members too large for one workgroup: the single-lattice kernels on their own streams, forked
+  // before the persistent launches so that both run at once
+  bool used[spin_batch::kAux] = {};
+  if (!bigs.empty()) {
+    e = hipEventRecord(b->fork, b->stream);
+    if (e != hipSuccess) return hfail(e, "batch fork");
+  }
+  for (const auto& bg : bigs) {
+    const int i = bg.first;
+    const int k = b->m[i].aux;
+    if (!used[k]) {
+      e = hipStreamWaitEvent(b->aux[k], b->fork, 0);
+      if (e != hipSuccess) return hfail(e, "batch fork wait");
+      used[k] = true;
+    }
+    spin_lattice* h = b->m[i].big;
+    int rc;
+    if (n[i] > 0 && rec_count(n[i], every))
+      rc = spin_sweep_record_device(h, n[i], beta[i], every, dE + bg.second, dM + bg.second);
+    else if (n[i] > 0)
+      rc = spin_sweep(h, n[i], beta[i]);
+    else
+      rc = record_device(h, dE + bg.second, dM + bg.second);
+    if (rc != SPIN_OK) {
+      join_aux(b, used);
+      return rc;
+    }
+  }
   // task order: per class, largest work first (longest-processing-time order)
   uint32_t norder = 0;
   std::vector<std::pair<uint32_t, uint32_t>> ranges;
@@ -459,7 +518,10 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->d_order, b->h_order, sizeof(uint32_t) * norder, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, b->stream);
-    if (e != hipSuccess) return hfail(e, "batch upload");
+    if (e != hipSuccess) {
+      join_aux(b, used);
+      return hfail(e, "batch upload");
+    }
   }
   for (size_t k = 0; k < classes.size(); ++k) {
     const Class& cl = classes[k];
@@ -470,23 +532,15 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     const uint32_t grid = std::min<uint32_t>(ntasks, per_cu * (uint32_t)b->num_cu);
     e = launch_batch(cl.d, cl.ea, cl.nt, b->d_lats, b->d_calls, b->d_order + ranges[k].first, ntasks,
                      b->d_counters + k, cl.lds, grid, b->stream);
-    if (e != hipSuccess) return hfail(e, "batch launch");
+    if (e != hipSuccess) {
+      join_aux(b, used);
+      return hfail(e, "batch launch");
+    }
   }
+  // join: later work on the pool's stream waits for the larger members
+  if (int rc = join_aux(b, used)) return rc;
   for (int i = 0; i < S; ++i)
     if (b->m[i].active && b->m[i].resident) b->m[i].t += (uint64_t)n[i];
-  // members too large for one workgroup: the single-lattice kernels, same stream
-  for (const auto& bg : bigs) {
-    const int i = bg.first;
-    spin_lattice* h = b->m[i].big;
-    int rc;
-    if (n[i] > 0 && rec_count(n[i], every))
-      rc = spin_sweep_record_device(h, n[i], beta[i], every, dE + bg.second, dM + bg.second);
-    else if (n[i] > 0)
-      rc = spin_sweep(h, n[i], beta[i]);
-    else
-      rc = record_device(h, dE + bg.second, dM + bg.second);
-    if (rc != SPIN_OK) return rc;
-  }
   return SPIN_OK;
 }
 
@@ -509,8 +563,12 @@ spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||
-      !dmalloc(&b->d_counters, sizeof(uint32_t) * 64)) {
+  bool ok = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < spin_batch::kAux; ++k)
+    ok = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->joined[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok || !dmalloc(&b->d_counters, sizeof(uint32_t) * 64)) {
     (void)hipGetLastError();
     bfail(SPIN_ENOMEM, "batch allocation failed");
     batch_destroy(b);
@@ -532,6 +590,7 @@ spin_batch* spin_batch_create(int count, const spin_desc* descs, void* stream) {
   hipError_t e = hipSuccess;
   if (count)
     e = hipMemcpyAsync(b->d_lats, b->h_lats, sizeof(BatchLattice) * count, hipMemcpyHostToDevice, b->stream);
+  for (int k = 0; k < spin_batch::kAux && e == hipSuccess; ++k) e = hipStreamSynchronize(b->aux[k]);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     hfail(e, "batch setup");
@@ -659,7 +718,9 @@ int spin_batch_set_workgroups_per_cu(spin_batch* b, int wgs) {
 
 int spin_batch_synchronize(spin_batch* b) {
   if (!b) return bfail(SPIN_EINVAL, "NULL batch");
-  hipError_t e = hipStreamSynchronize(b->stream);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < spin_batch::kAux && e == hipSuccess; ++k) e = hipStreamSynchronize(b->aux[k]);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hfail(e, "batch synchronize");
   return SPIN_OK;
 }

@@ -209,8 +209,7 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
   Tile t = h->tile;
   const int L = h->L;
   if (kernel == SPIN_KERNEL_STREAM) {  // each field: the request if given, else the default
-    Tile d = h->d == 3 ? Tile{L, (L % 16 == 0 && L >= 64) ? 16 : 8, L >= 16 ? 16 : L, 256}
-                       : Tile{L, 1, L >= 4096 ? 16 : 8, 256};
+    Tile d = h->d == 3 ? Tile{L, 8, L >= 8 ? 8 : L, 512} : Tile{L, 1, 8, 512};
     if (t.y && h->d == 3) d.y = t.y;
     if (t.z) d.z = t.z;
     if (t.threads) d.threads = t.threads;

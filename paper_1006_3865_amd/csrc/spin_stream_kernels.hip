@@ -52,24 +52,25 @@ __device__ __forceinline__ uint32_t wrap_sub2(uint32_t v, uint32_t L) {  // (v -
   return w;
 }
 
-// Load plane z (global, int8) into ring slot `slot` as nibble words, with pads.
+// Words of a plane slice each thread loads (slice words u = thread + NT*q).
+constexpr int kFetch = 8;
+
+// Load the slice of plane z (global, int8) into registers: word u of the
+// slice is row u / GPR, column u % GPR.
 template <int D, int NT>
-__device__ __forceinline__ void sg_load(const int8_t* __restrict__ src, uint32_t* slot, uint32_t z, uint32_t y0,
-                                        const StreamArgs& a, uint32_t RP, uint32_t RW) {
+__device__ __forceinline__ void sg_fetch(const int8_t* __restrict__ src, uint32_t z, uint32_t y0, const StreamArgs& a,
+                                         uint32_t tot, uint2 (&v)[kFetch]) {
   const uint32_t GPR = a.GPR, L = a.L;
-  const uint32_t tot = RP * GPR;
   const uint32_t dr = NT / GPR, dg = NT - dr * GPR;
   uint32_t r = threadIdx.x / GPR, g = threadIdx.x - r * GPR;
   const uint2* s2 = reinterpret_cast<const uint2*>(src);
-  for (uint32_t u = threadIdx.x; u < tot; u += NT) {
-    const uint32_t y = (D == 3) ? wrap_sub2(y0 + r, L) : 0u;
-    const uint32_t w = (D == 3) ? (z * L + y) * GPR + g : z * GPR + g;
-    const uint2 b = s2[w];
-    const uint32_t v = pack_nibbles(b.x, b.y);
-    uint32_t* row = slot + r * RW;
-    row[1 + g] = v;
-    if (g == 0) row[GPR + 1] = v;
-    if (g == GPR - 1) row[0] = v;
+#pragma unroll
+  for (int q = 0; q < kFetch; ++q) {
+    if (threadIdx.x + NT * q < tot) {
+      const uint32_t y = (D == 3) ? wrap_sub2(y0 + r, L) : 0u;
+      const uint32_t w = (D == 3) ? (z * L + y) * GPR + g : z * GPR + g;
+      v[q] = s2[w];
+    }
     g += dg;
     r += dr;
     if (g >= GPR) {
@@ -79,14 +80,62 @@ __device__ __forceinline__ void sg_load(const int8_t* __restrict__ src, uint32_t
   }
 }
 
+// Store fetched words into ring slot `slot` as nibble words, with the pads.
+template <int NT>
+__device__ __forceinline__ void sg_store(uint32_t* slot, const StreamArgs& a, uint32_t tot, uint32_t RW,
+                                         const uint2 (&v)[kFetch]) {
+  const uint32_t GPR = a.GPR;
+  const uint32_t dr = NT / GPR, dg = NT - dr * GPR;
+  uint32_t r = threadIdx.x / GPR, g = threadIdx.x - r * GPR;
+#pragma unroll
+  for (int q = 0; q < kFetch; ++q) {
+    if (threadIdx.x + NT * q < tot) {
+      const uint32_t x = pack_nibbles(v[q].x, v[q].y);
+      uint32_t* row = slot + r * RW;
+      row[1 + g] = x;
+      if (g == 0) row[GPR + 1] = x;
+      if (g == GPR - 1) row[0] = x;
+    }
+    g += dg;
+    r += dr;
+    if (g >= GPR) {
+      g -= GPR;
+      r += 1;
+    }
+  }
+}
+
+// Couplings of the 2d bonds of word w (raw words: x at w and its left
+// neighbour word, y at w and the row below, z at w and the plane below).
+template <int D>
+__device__ __forceinline__ void sg_jload(gu32* Jn, uint32_t NW, uint32_t w, uint32_t g, uint32_t y, uint32_t z,
+                                         const StreamArgs& a, uint32_t (&j)[2 * D]) {
+  const uint32_t GPR = a.GPR, L = a.L;
+  const uint32_t wl = g ? w - 1u : w + GPR - 1u;
+  j[0] = Jn[wl];
+  j[1] = Jn[w];
+  if (D == 3) {
+    const uint32_t wym = y ? w - GPR : w + (L - 1u) * GPR;
+    const uint32_t wzm = z ? w - L * GPR : w + (L - 1u) * L * GPR;
+    j[2] = Jn[NW + wym];
+    j[3] = Jn[NW + w];
+    j[4] = Jn[2 * NW + wzm];
+    j[5] = Jn[2 * NW + w];
+  } else {
+    const uint32_t wym = z ? w - GPR : w + (L - 1u) * GPR;
+    j[2] = Jn[NW + wym];
+    j[3] = Jn[NW + w];
+  }
+}
+
 // Update the colour-C nibbles of word g of slice row r (slots pm, pc, pp hold
-// planes z-1, z, z+1); returns the new word.
+// planes z-1, z, z+1; w is the word's global index, jr its raw couplings);
+// returns the new word.
 template <int D, bool EA, bool NEVER, uint32_t C>
 __device__ __forceinline__ uint32_t sg_unit(const uint32_t* pm, const uint32_t* pc, const uint32_t* pp, uint32_t r,
-                                            uint32_t g, uint32_t y, uint32_t z, const StreamArgs& a,
-                                            const PhiloxUniform& U, const uint32_t* bound, gu32* Jn, uint32_t NW,
-                                            uint32_t RW) {
-  const uint32_t GPR = a.GPR, L = a.L;
+                                            uint32_t g, uint32_t y, uint32_t z, uint32_t w, const StreamArgs& a,
+                                            const PhiloxUniform& U, const uint32_t* bound, uint32_t RW,
+                                            const uint32_t (&jr)[2 * D]) {
   const uint32_t o = r * RW + 1 + g;
   const uint32_t c = pc[o];
   const uint32_t lw = pc[o - 1], rw = pc[o + 1];
@@ -100,24 +149,15 @@ __device__ __forceinline__ uint32_t sg_unit(const uint32_t* pm, const uint32_t* 
     nb[0] = pm[o];
     nb[1] = pp[o];
   }
-  const uint32_t w = (D == 3) ? (z * L + y) * GPR + g : z * GPR + g;
   uint32_t jn[2 * D];
   if (EA) {
-    const uint32_t wl = g ? w - 1u : w + GPR - 1u;
-    const uint32_t jx = Jn[w];
-    jn[0] = __builtin_amdgcn_alignbit(jx, Jn[wl], 28);
-    jn[1] = jx;
+    jn[0] = __builtin_amdgcn_alignbit(jr[1], jr[0], 28);  // bond (x-1, x) of each site
+    jn[1] = jr[1];
+    jn[2] = jr[2];
+    jn[3] = jr[3];
     if (D == 3) {
-      const uint32_t wym = y ? w - GPR : w + (L - 1u) * GPR;
-      const uint32_t wzm = z ? w - L * GPR : w + (L - 1u) * L * GPR;
-      jn[2] = Jn[NW + wym];
-      jn[3] = Jn[NW + w];
-      jn[4] = Jn[2 * NW + wzm];
-      jn[5] = Jn[2 * NW + w];
-    } else {
-      const uint32_t wym = z ? w - GPR : w + (L - 1u) * GPR;
-      jn[2] = Jn[NW + wym];
-      jn[3] = Jn[NW + w];
+      jn[4] = jr[4];
+      jn[5] = jr[5];
     }
   }
   const uint32_t S = nib_unsat<D, EA>(c, lw, rw, nb, jn);
@@ -125,6 +165,57 @@ __device__ __forceinline__ uint32_t sg_unit(const uint32_t* pm, const uint32_t* 
   philox_lane(w, U, a.keys, rnd);
   const uint32_t p = (C + y + z) & 1u;
   return c ^ nib_flips<NEVER>(S, p, rnd, bound, a.never4);
+}
+
+// The colour-C units of one step: slice rows RB0 + (u / GPR), words u % GPR,
+// u = thread + NT*q < n.  Colour 0 writes back into slot pc (with pads),
+// colour 1 writes the finished words to dst.  The couplings of the next unit
+// are loaded while the current one is computed.
+template <int D, bool EA, bool NEVER, int NT, uint32_t C>
+__device__ __forceinline__ void sg_units(const uint32_t* pm, uint32_t* pc, const uint32_t* pp, uint32_t n, uint32_t y0,
+                                         uint32_t z, const StreamArgs& a, const PhiloxUniform& U,
+                                         const uint32_t* bound, uint32_t RW, gu32* Jn, uint32_t NW,
+                                         int8_t* __restrict__ dst) {
+  const uint32_t GPR = a.GPR, L = a.L;
+  constexpr uint32_t RB0 = (D == 3) ? (C == 0 ? 1u : 2u) : 0u;  // first slice row
+  const uint32_t dr = NT / GPR, dg = NT - dr * GPR;
+  uint32_t r = threadIdx.x / GPR, g = threadIdx.x - r * GPR;
+  // slice row rr -> y: colour 0 rows may wrap (y0 - 1, y0 + TY), colour 1 rows are owned
+  auto ycoord = [&](uint32_t rr) -> uint32_t {
+    if (D != 3) return 0u;
+    return C == 0 ? wrap_sub2(y0 + rr, L) : y0 + rr - 2u;
+  };
+  auto word = [&](uint32_t y, uint32_t gg) -> uint32_t { return (D == 3) ? (z * L + y) * GPR + gg : z * GPR + gg; };
+  uint32_t jc[2 * D] = {}, jx[2 * D] = {};
+  if (EA && threadIdx.x < n) sg_jload<D>(Jn, NW, word(ycoord(r + RB0), g), g, ycoord(r + RB0), z, a, jc);
+  for (uint32_t u = threadIdx.x; u < n; u += NT) {
+    const uint32_t rr = r + RB0;
+    const uint32_t y = ycoord(rr);
+    const uint32_t w = word(y, g);
+    uint32_t rn = r + dr, gn = g + dg;
+    if (gn >= GPR) {
+      gn -= GPR;
+      rn += 1;
+    }
+    if (EA && u + NT < n) sg_jload<D>(Jn, NW, word(ycoord(rn + RB0), gn), gn, ycoord(rn + RB0), z, a, jx);
+    const uint32_t v = sg_unit<D, EA, NEVER, C>(pm, pc, pp, rr, g, y, z, w, a, U, bound, RW, jc);
+    if (C == 0) {
+      uint32_t* row = pc + rr * RW;
+      row[1 + g] = v;
+      if (g == 0) row[GPR + 1] = v;
+      if (g == GPR - 1) row[0] = v;
+    } else {
+      uint2 b;
+      unpack_nibbles(v, b.x, b.y);
+      reinterpret_cast<uint2*>(dst)[w] = b;
+    }
+    if (EA) {
+#pragma unroll
+      for (int k = 0; k < 2 * D; ++k) jc[k] = jx[k];
+    }
+    r = rn;
+    g = gn;
+  }
 }
 
 template <int D, bool EA, bool NEVER, int NT>
@@ -146,13 +237,16 @@ __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, 
   if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
   const PhiloxUniform U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
   const PhiloxUniform U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
-  for (uint32_t k = 0; k < 3; ++k) sg_load<D, NT>(src, ring + k * SB, wrap_sub2(z0 + k, L), y0, a, RP, RW);
+  const uint32_t tot = RP * GPR;  // words of a plane slice
+  uint2 nxt[kFetch];
+  for (uint32_t k = 0; k < 3; ++k) {
+    sg_fetch<D, NT>(src, wrap_sub2(z0 + k, L), y0, a, tot, nxt);
+    sg_store<NT>(ring + k * SB, a, tot, RW, nxt);
+  }
   __syncthreads();
   // units: colour 0 on slice rows 1..TY+2 (3D) / row 0 (2D); colour 1 on rows 2..TY+1 / row 0
   const uint32_t U0n = (D == 3) ? (TY + 2) * GPR : GPR;
   const uint32_t U1n = (D == 3) ? TY * GPR : GPR;
-  const uint32_t dr = NT / GPR, dg = NT - dr * GPR;
-  const uint32_t r_first = threadIdx.x / GPR, g_first = threadIdx.x - r_first * GPR;
   uint32_t sa = 1;  // slot of plane a = z0 - 1 + i
   for (uint32_t i = 0; i < H + 3; ++i) {
     const uint32_t s_m3 = sa >= 3 ? sa - 3 : sa + 3;   // a-3
@@ -160,52 +254,15 @@ __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, 
     const uint32_t s_m1 = sa >= 1 ? sa - 1 : 5;        // a-1
     const uint32_t s_p1 = sa <= 4 ? sa + 1 : 0;        // a+1
     const uint32_t s_p2 = sa <= 3 ? sa + 2 : sa - 4;   // a+2
-    if (i <= H) sg_load<D, NT>(src, ring + s_p2 * SB, wrap_sub2(z0 + i + 3, L), y0, a, RP, RW);
-    if (i <= H + 1) {
-      const uint32_t za = wrap_sub2(z0 + i + 1, L);
-      const uint32_t* pm = ring + s_m1 * SB;
-      uint32_t* pc = ring + sa * SB;
-      const uint32_t* pp = ring + s_p1 * SB;
-      uint32_t r = r_first, g = g_first;
-      for (uint32_t u = threadIdx.x; u < U0n; u += NT) {
-        const uint32_t rr = (D == 3) ? r + 1 : 0u;
-        const uint32_t y = (D == 3) ? wrap_sub2(y0 + rr, L) : 0u;
-        const uint32_t v = sg_unit<D, EA, NEVER, 0>(pm, pc, pp, rr, g, y, za, a, U0, bound, Jn, NW, RW);
-        uint32_t* row = pc + rr * RW;
-        row[1 + g] = v;
-        if (g == 0) row[GPR + 1] = v;
-        if (g == GPR - 1) row[0] = v;
-        g += dg;
-        r += dr;
-        if (g >= GPR) {
-          g -= GPR;
-          r += 1;
-        }
-      }
-    }
-    if (i >= 3) {
-      const uint32_t zb = z0 + i - 3u;
-      const uint32_t* pm = ring + s_m3 * SB;
-      const uint32_t* pc = ring + s_m2 * SB;
-      const uint32_t* pp = ring + s_m1 * SB;
-      uint2* d2 = reinterpret_cast<uint2*>(dst);
-      uint32_t r = r_first, g = g_first;
-      for (uint32_t u = threadIdx.x; u < U1n; u += NT) {
-        const uint32_t rr = (D == 3) ? r + 2 : 0u;
-        const uint32_t y = (D == 3) ? y0 + r : 0u;
-        const uint32_t v = sg_unit<D, EA, NEVER, 1>(pm, pc, pp, rr, g, y, zb, a, U1, bound, Jn, NW, RW);
-        const uint32_t w = (D == 3) ? (zb * L + y) * GPR + g : zb * GPR + g;
-        uint2 b;
-        unpack_nibbles(v, b.x, b.y);
-        d2[w] = b;
-        g += dg;
-        r += dr;
-        if (g >= GPR) {
-          g -= GPR;
-          r += 1;
-        }
-      }
-    }
+    // plane a+2: loads issued now, stored after the compute of this step
+    if (i <= H) sg_fetch<D, NT>(src, wrap_sub2(z0 + i + 3, L), y0, a, tot, nxt);
+    if (i <= H + 1)
+      sg_units<D, EA, NEVER, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0,
+                                    wrap_sub2(z0 + i + 1, L), a, U0, bound, RW, Jn, NW, dst);
+    if (i >= 3)
+      sg_units<D, EA, NEVER, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u, a,
+                                    U1, bound, RW, Jn, NW, dst);
+    if (i <= H) sg_store<NT>(ring + s_p2 * SB, a, tot, RW, nxt);
     __syncthreads();
     sa = sa == 5 ? 0 : sa + 1;
   }
@@ -221,6 +278,8 @@ bool streamg_supported(const Lat& lat, const Tile& tile) {
     if (tile.y != 4 && tile.y != 8 && tile.y != 16 && tile.y != 32) return false;
     if (lat.L % (uint32_t)tile.y != 0) return false;
   }
+  const uint32_t RP = lat.d == 3 ? (uint32_t)tile.y + 4 : 1u;
+  if (RP * (lat.L / 8) > (uint32_t)kFetch * (uint32_t)tile.threads) return false;  // slice words per thread
   return streamg_lds_bytes(lat, tile) <= 150 * 1024;
 }
 

@@ -100,23 +100,30 @@ class Server:
     """Admission, tick scheduling and retirement; the executor does the sweeping."""
 
     def __init__(self, executor, budget_bytes=1 << 30, max_slots=512, tick_s=0.02,
-                 rate_wg=2.0e9, rate_big=8.0e11, clock=time.perf_counter, keep_spins=False):
+                 rate_wg=2.0e9, rate_big=8.0e11, sweep_floor_s=15e-6, streams=4, clock=time.perf_counter,
+                 keep_spins=False):
         self.ex = executor
         self.budget = budget_bytes
         self.max_slots = max_slots
         self.tick_s = tick_s
-        self.rate_wg = rate_wg        # attempts/s of one workgroup on an LDS-resident lattice
-        self.rate_big = rate_big      # attempts/s of the whole chip on a larger lattice
+        self.rate_wg = rate_wg              # attempts/s of one workgroup on an LDS-resident lattice
+        self.rate_big = rate_big            # attempts/s of the whole chip on a larger lattice
+        self.sweep_floor_s = sweep_floor_s  # shortest sweep of a larger lattice (launch and pipeline latency)
+        self.streams = streams              # larger lattices the pool runs at once
         self.clock = clock
         self.keep_spins = keep_spins
         self.ticks = 0
 
     def quantum(self, job, nbig):
+        """Sweeps for this tick: what the job's own rate estimate does in tick_s, sharing the
+        pool's streams with the other larger jobs; at least 1, at most what is left."""
         N = job["L"] ** job["d"]
         if lds_resident(job["L"], job["d"]):
             q = self.tick_s * self.rate_wg / N
         else:
-            q = self.tick_s * self.rate_big / (N * max(nbig, 1))
+            rate = min(self.rate_big, N / self.sweep_floor_s)
+            share = max(1.0, nbig / float(self.streams))
+            q = self.tick_s * rate / (N * share)
         return int(min(job["left"], max(1, math.floor(q))))
 
     def serve(self, trace):

@@ -137,12 +137,15 @@ def test_job_over_budget_is_rejected():
 
 
 def test_quantum_bounds():
-    srv = serve.Server(None, tick_s=0.01, rate_wg=1e9, rate_big=1e12)
+    srv = serve.Server(None, tick_s=0.01, rate_wg=1e9, rate_big=1e12, sweep_floor_s=1e-5, streams=4)
     small = dict(L=16, d=3, left=10 ** 6)
     assert srv.quantum(small, 0) == int(0.01 * 1e9 / 16 ** 3)
     assert srv.quantum(dict(L=16, d=3, left=5), 0) == 5
-    big = dict(L=4096, d=2, left=10 ** 6)
-    assert srv.quantum(big, 2) == int(0.01 * 1e12 / (4096 ** 2 * 2))
+    big = dict(L=4096, d=2, left=10 ** 6)                   # chip-rate bound, 8 jobs share 4 streams
+    assert srv.quantum(big, 8) == int(0.01 * 1e12 / (4096 ** 2 * 2))
+    assert srv.quantum(big, 3) == int(0.01 * 1e12 / 4096 ** 2)
+    mid = dict(L=72, d=3, left=10 ** 6)                     # latency-floor bound: tick / floor sweeps
+    assert abs(srv.quantum(mid, 1) - 1000) <= 1
     huge = dict(L=1 << 15, d=2, left=7)
     assert srv.quantum(huge, 100) == 1  # at least one sweep per tick
 
