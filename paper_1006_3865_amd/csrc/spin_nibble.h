@@ -82,6 +82,14 @@ __device__ __forceinline__ uint32_t nib_flips(uint32_t S, uint32_t p, const uint
 // Global-address-space view of a device pointer (loads with a 32-bit offset
 // from a scalar base instead of 64-bit flat addresses).
 typedef const __attribute__((address_space(1))) uint32_t gu32;
+typedef const __attribute__((address_space(1))) char gc8;
 __device__ __forceinline__ gu32* as_global(const uint32_t* p) { return (gu32*)(p); }
+
+// Word i of a global array whose base is the same for the whole wavefront
+// and whose byte offsets fit 32 bits: a scalar base plus a 32-bit vector
+// offset (no 64-bit address arithmetic per lane).
+__device__ __forceinline__ uint32_t ldg_word(gu32* base, uint32_t i) {
+  return *reinterpret_cast<gu32*>(reinterpret_cast<gc8*>(base) + (uint64_t)(i << 2));
+}
 
 }  // namespace spin

@@ -112,19 +112,19 @@ __device__ __forceinline__ void sg_jload(gu32* Jn, uint32_t NW, uint32_t w, uint
                                          const StreamArgs& a, uint32_t (&j)[2 * D]) {
   const uint32_t GPR = a.GPR, L = a.L;
   const uint32_t wl = g ? w - 1u : w + GPR - 1u;
-  j[0] = Jn[wl];
-  j[1] = Jn[w];
+  j[0] = ldg_word(Jn, wl);
+  j[1] = ldg_word(Jn, w);
   if (D == 3) {
     const uint32_t wym = y ? w - GPR : w + (L - 1u) * GPR;
     const uint32_t wzm = z ? w - L * GPR : w + (L - 1u) * L * GPR;
-    j[2] = Jn[NW + wym];
-    j[3] = Jn[NW + w];
-    j[4] = Jn[2 * NW + wzm];
-    j[5] = Jn[2 * NW + w];
+    j[2] = ldg_word(Jn, NW + wym);
+    j[3] = ldg_word(Jn, NW + w);
+    j[4] = ldg_word(Jn, 2 * NW + wzm);
+    j[5] = ldg_word(Jn, 2 * NW + w);
   } else {
     const uint32_t wym = z ? w - GPR : w + (L - 1u) * GPR;
-    j[2] = Jn[NW + wym];
-    j[3] = Jn[NW + w];
+    j[2] = ldg_word(Jn, NW + wym);
+    j[3] = ldg_word(Jn, NW + w);
   }
 }
 
@@ -268,10 +268,12 @@ __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, 
   }
 }
 
-// Supported: L % 8 == 0, L >= 16; 3D: TY in {4, 8, 16, 32} dividing L;
+// Supported: L % 8 == 0, L >= 16; +-J: packed couplings (d*L^d/2 bytes) under 4 GiB;
+// 3D: TY in {4, 8, 16, 32} dividing L;
 // H >= 1 (the last strip may be shorter); threads 256 or 512.
 bool streamg_supported(const Lat& lat, const Tile& tile) {
   if (lat.L % 8 != 0 || lat.L < 16) return false;
+  if (lat.J != nullptr && (uint64_t)lat.d * lat.N / 2 >= ((uint64_t)1 << 32)) return false;  // 32-bit offsets (ldg_word)
   if (tile.threads != 256 && tile.threads != 512) return false;
   if (tile.z < 1 || (uint32_t)tile.z > lat.L) return false;
   if (lat.d == 3) {
