@@ -18,5 +18,6 @@ from .oracle import (  # noqa: F401
     couplings,
     measure,
     sweeps,
+    coarse_sweeps,
     Chain,
 )

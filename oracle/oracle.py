@@ -60,6 +60,10 @@ class OracleLib:
                                       ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       i64p, i64p, ctypes.c_int, u64p]
         lib.oracle_sweeps.restype = ctypes.c_int
+        lib.oracle_coarse_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, ctypes.c_uint64, ctypes.c_uint32,
+                                             ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, i64p, i64p]
+        lib.oracle_coarse_sweeps.restype = ctypes.c_int
         self.lib = lib
 
     def philox4x32_10(self, ctr, key):
@@ -121,6 +125,20 @@ class OracleLib:
             raise ValueError("oracle_sweeps rejected its arguments")
         return E[:nrec].copy(), M[:nrec].copy()
 
+    def coarse_sweeps(self, L, d, J, spins, seed, replica, t0, n, beta, T, k, every=0):
+        """The paper's coarse-tile schedule (tile edge T, k hits per tile load): n sweeps in place."""
+        assert spins.dtype == np.int8 and spins.flags.c_contiguous
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1), dtype=np.int64)
+        M = np.zeros(max(nrec, 1), dtype=np.int64)
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        Jp = None if Jarr is None else _ptr(Jarr, ctypes.c_int8)
+        rc = self.lib.oracle_coarse_sweeps(L, d, Jp, _ptr(spins, ctypes.c_int8), seed, replica, t0, n, float(beta),
+                                           T, k, every, _ptr(E, ctypes.c_int64), _ptr(M, ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle_coarse_sweeps rejected its arguments")
+        return E[:nrec].copy(), M[:nrec].copy()
+
 
 _default = None
 
@@ -158,6 +176,10 @@ def sweeps(L, d, J, spins, seed, replica, t0, n, beta, every=0, order=0, stats=N
     return default().sweeps(L, d, J, spins, seed, replica, t0, n, beta, every, order, stats)
 
 
+def coarse_sweeps(L, d, J, spins, seed, replica, t0, n, beta, T, k, every=0):
+    return default().coarse_sweeps(L, d, J, spins, seed, replica, t0, n, beta, T, k, every)
+
+
 class Chain:
     """Convenience state holder: one lattice advanced by an oracle build."""
 
@@ -171,6 +193,12 @@ class Chain:
     def sweep(self, n, beta, every=0, order=0, stats=None):
         E, M = self.lib.sweeps(self.L, self.d, self.J, self.spins, self.seed, self.replica, self.t, n, beta,
                                every, order, stats)
+        self.t += n
+        return E, M
+
+    def coarse_sweep(self, n, beta, T, k, every=0):
+        E, M = self.lib.coarse_sweeps(self.L, self.d, self.J, self.spins, self.seed, self.replica, self.t, n, beta,
+                                      T, k, every)
         self.t += n
         return E, M
 

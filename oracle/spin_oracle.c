@@ -46,8 +46,20 @@
  *  the current spins; the order inside a colour does not matter because no
  *  two sites of one colour are neighbours (Sec. 3, the sentence on the
  *  independence of sub-lattice sites).  The paper's coarse-tile ordering
- *  and its k-fold multi-hit repetition change the chain and are not part
- *  of it.
+ *  and its k-fold multi-hit repetition change the chain; they are a
+ *  separate mode, oracle_coarse_sweeps below.
+ *
+ *  The paper's own schedule (Sec. 3, steps 1-7, with the generalized
+ *  multi-hit of the paragraph after them), as an explicit mode with its own
+ *  chain: the lattice is cut into tiles of edge T, B = L/T per edge (B
+ *  even); a tile is even or odd by the parity of the sum of its tile
+ *  coordinates.  Sweep t: for tile parity q = 0, then q = 1, in every tile
+ *  of parity q, k times: update the tile's colour-0 sites, then its
+ *  colour-1 sites (colour = (x+y+z) mod 2 as above), each from the current
+ *  spins.  Tiles of one parity are never neighbours, so they are
+ *  independent.  Hit h (0..k-1) of site s of colour c in sweep t draws
+ *  word (s>>1)&3 of Philox counter (s>>3, t*k + h, replica, c).  With
+ *  T = 1 and k = 1 this is the canonical chain.
  */
 #include <math.h>
 #include <stddef.h>
@@ -284,5 +296,59 @@ int oracle_sweeps(int L, int d, const int8_t* J, int8_t* spins, uint64_t seed,
     }
   }
   free(list);
+  return 0;
+}
+
+/*
+ * The coarse-tile schedule with k-fold multi-hit (see the header): n sweeps
+ * from absolute sweep index t0, each updating every site k times.  Records
+ * as in oracle_sweeps.  Requires T >= 1 dividing L with L/T even, k >= 1 and
+ * (t0 + n) * k <= 2^32.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_coarse_sweeps(int L, int d, const int8_t* J, int8_t* spins,
+                         uint64_t seed, uint32_t replica, uint64_t t0, int n,
+                         double beta, int T, int k, int every, int64_t* E,
+                         int64_t* M) {
+  if (!valid_shape(L, d) || n < 0 || T < 1 || k < 1) return -1;
+  if (L % T != 0 || (L / T) % 2 != 0) return -1;
+  if (isnan(beta) || beta < 0) return -1;
+  if ((t0 + (uint64_t)n) * (uint64_t)k > ((uint64_t)1 << 32)) return -1;
+  int z = 2 * d;
+  uint64_t Tab[7];
+  oracle_table(beta, d, Tab);
+  int64_t N = site_count(L, d);
+  int B = L / T;
+  int nbz = (d == 3) ? B : 1, tz = (d == 3) ? T : 1;
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    uint64_t t = t0 + (uint64_t)i;
+    for (int q = 0; q < 2; ++q)
+      for (int bz = 0; bz < nbz; ++bz)
+        for (int by = 0; by < B; ++by)
+          for (int bx = 0; bx < B; ++bx) {
+            if ((bx + by + bz) % 2 != q) continue;
+            for (int h = 0; h < k; ++h) {
+              uint32_t hit = (uint32_t)(t * (uint64_t)k + (uint64_t)h);
+              for (int c = 0; c < 2; ++c)
+                for (int zz = 0; zz < tz; ++zz)
+                  for (int yy = 0; yy < T; ++yy)
+                    for (int xx = 0; xx < T; ++xx) {
+                      int64_t x[3] = {(int64_t)bx * T + xx, (int64_t)by * T + yy,
+                                      (int64_t)bz * tz + zz};
+                      int64_t s = index_of(x, L, d);
+                      if (colour_of(s, L, d) != c) continue;
+                      int kk = spins[s] * local_field(s, L, d, J, spins, N);
+                      uint32_t r = draw(seed, (uint32_t)(s >> 3), hit, replica,
+                                        (uint32_t)c, (unsigned)((s >> 1) & 3));
+                      if ((uint64_t)r < Tab[(kk + z) / 2])
+                        spins[s] = (int8_t)(-spins[s]);
+                    }
+            }
+          }
+    if (every > 0 && (i + 1) % every == 0) {
+      oracle_measure(L, d, J, spins, &E[rec], &M[rec]);
+      ++rec;
+    }
+  }
   return 0;
 }

@@ -65,3 +65,36 @@ def sweep(spins, L, d, J, beta, t, draw, zero_temperature=False):
                 cur[s] = -cur[s]
     spins[:] = cur
     return spins
+
+
+def coarse_sweep(spins, L, d, J, beta, t, T, k, draw):
+    """One sweep of the paper's coarse-tile schedule (Sec. 3, steps 1-7, and k-fold multi-hit), in place:
+    tiles of edge T; every tile whose tile coordinates sum to an even number, then every odd one; in each
+    tile k times its colour-0 sites, then its colour-1 sites.  draw(s, hit, c) -> 32-bit word, with
+    hit = t * k + h for the h-th repetition."""
+    B = L // T
+    cur = np.array(spins, dtype=np.int8)
+    sites_of_tile = {}
+    for s in range(L ** d):
+        x, y = s % L, (s // L) % L
+        z = s // (L * L) if d == 3 else 0
+        tile = (x // T, y // T, z // T if d == 3 else 0)
+        sites_of_tile.setdefault(tile, []).append(s)
+    for q in (0, 1):
+        for tile, sites in sorted(sites_of_tile.items()):
+            if sum(tile) % 2 != q:
+                continue
+            for h in range(k):
+                for c in (0, 1):
+                    for s in sites:
+                        if colour(s, L, d) != c:
+                            continue
+                        e0 = energy(cur, L, d, J)
+                        cur[s] = -cur[s]
+                        dE = energy(cur, L, d, J) - e0
+                        cur[s] = -cur[s]
+                        if draw(s, t * k + h, c) < threshold(beta, dE):
+                            cur[s] = -cur[s]
+    assert B % 2 == 0
+    spins[:] = cur
+    return spins

@@ -21,7 +21,9 @@ MUTANTS = {
     "dE_is_k_not_2k": ("double dE = (double)(2 * k);", "double dE = (double)k;"),
     "colour_order_swapped": ("for (int c = 0; c < 2; ++c) {", "for (int c = 1; c >= 0; --c) {"),
     "update_counter_word_s_over_4": ("draw(seed, (uint32_t)(s >> 3), t, replica", "draw(seed, (uint32_t)(s >> 2), t, replica"),
-    "update_word_index": ("(unsigned)((s >> 1) & 3));", "(unsigned)(s & 3));"),
+    "update_word_index": ("t, replica, (uint32_t)c,\n                          (unsigned)((s >> 1) & 3));",
+                          "t, replica, (uint32_t)c,\n                          (unsigned)(s & 3));"),
+    "coarse_update_word_index": ("(uint32_t)c, (unsigned)((s >> 1) & 3));", "(uint32_t)c, (unsigned)(s & 3));"),
     "philox_swapped_high_words": ("uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;"),
     "philox_key_not_bumped": ("if (round < 9) { k0 += W0; k1 += W1; }", "if (round < 9) { k0 += W0; }"),
     "energy_sign": ("e -= (int64_t)coupling(J, dir, s, N) * spins[s] * spins[t];",
@@ -32,6 +34,14 @@ MUTANTS = {
     "y_coordinate_wraps_wrong": ("x[1] = (s / L) % L;", "x[1] = (s / L) % (L - 1);"),
     "table_index_off_by_one": ("int accept = (uint64_t)r < T[cls];", "int accept = (uint64_t)r < T[cls > 0 ? cls - 1 : 0];"),
     "table_ceil": ("v = (uint64_t)floor(ldexp(p, 32));", "v = (uint64_t)ceil(ldexp(p, 32));"),
+    # the coarse-tile multi-hit schedule
+    "coarse_odd_tiles_first": ("if ((bx + by + bz) % 2 != q) continue;", "if ((bx + by + bz) % 2 == q) continue;"),
+    "coarse_hit_counter_ignores_k": ("uint32_t hit = (uint32_t)(t * (uint64_t)k + (uint64_t)h);",
+                                     "uint32_t hit = (uint32_t)(t + (uint64_t)h);"),
+    "coarse_fine_colours_swapped": ("              for (int c = 0; c < 2; ++c)\n                for (int zz",
+                                    "              for (int c = 1; c >= 0; --c)\n                for (int zz"),
+    "coarse_single_hit": ("for (int h = 0; h < k; ++h) {", "for (int h = 0; h < 1; ++h) {"),
+    "coarse_last_tiles_skipped": ("int B = L / T;", "int B = L / T - 1;"),
 }
 
 
@@ -76,6 +86,26 @@ def _quick_pins(lib, rocrand_philox):
         ref = s0.copy()
         for t in range(t0, t0 + n):
             bf.sweep(ref, L, d, J, beta, t, lambda s, tt, c: int(w[(s >> 3, tt, c)][(s >> 1) & 3]))
+        np.testing.assert_array_equal(got, ref)
+    # coarse-tile multi-hit sweeps against their brute-force restatement
+    for (L, d, ea, T, k, beta) in ((8, 2, False, 2, 2, 0.44), (4, 3, True, 2, 2, 0.5)):
+        seed, rep, t0, n = 0x1006386500000009, 1, 3, 1
+        J = rng.choice(np.array([-1, 1], dtype=np.int8), size=d * L ** d) if ea else None
+        s0 = rng.choice(np.array([-1, 1], dtype=np.int8), size=L ** d)
+        got = s0.copy()
+        lib.coarse_sweeps(L, d, J, got, seed, rep, t0, n, beta, T, k)
+        N = L ** d
+        ctrs, keys = [], []
+        for t in range(t0, t0 + n):
+            for h in range(k):
+                for c in (0, 1):
+                    for g in range((N + 7) // 8):
+                        ctrs.append((g, t * k + h, rep, c))
+                        keys.append((g, t * k + h, c))
+        w = dict(zip(keys, rocrand_philox(ctrs, (seed & 0xFFFFFFFF, seed >> 32))))
+        ref = s0.copy()
+        for t in range(t0, t0 + n):
+            bf.coarse_sweep(ref, L, d, J, beta, t, T, k, lambda s, hit, c: int(w[(s >> 3, hit, c)][(s >> 1) & 3]))
         np.testing.assert_array_equal(got, ref)
 
 
