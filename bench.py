@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D EA workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-tile multi-hit schedule")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     return ap.parse_args()
 
@@ -169,6 +170,30 @@ def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
             "plain_attempts_per_ns": round(plain, 3), "ratio": round(batched / plain, 2),
             "plain_rate_by_L": {str(L): {"attempts_per_ns": round(r, 3), "kernel": k} for L, (r, k) in rates.items()},
             "plain_method": "lone handles, %d sweeps on 2 lattices per L, summed over the workload" % plain_sweeps}
+
+
+def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64), hits=(1, 2, 4, 8)):
+    """The paper's own schedule (coarse tiles, k-fold multi-hit): 2D Ising at beta 0.4406868, attempts/ns
+    (k * L^2 attempts per sweep) for each tile edge and hit count, HIP events on the lattice's stream."""
+    stream = torch.cuda.Stream()
+    out = {}
+    for L in sizes:
+        lat = spin.Lattice(0, L, 2, workloads.seed(2), stream=stream)
+        for T in tiles:
+            for k in hits:
+                lat.set_schedule(spin.SPIN_SCHEDULE_COARSE, T, k)
+                n = max(2, int(4e9 / (k * L * L)))
+                n = min(n, 400)
+                lat.sweep(1, workloads.BETA_2D_CRIT)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                lat.sweep(n, workloads.BETA_2D_CRIT)
+                b.record(stream)
+                lat.synchronize()
+                out["L%d_T%d_k%d" % (L, T, k)] = round(n * k * L * L / (a.elapsed_time(b) * 1e6), 2)
+        lat.close()
+    return {"workload": "ising2d coarse-tile multi-hit", "beta": workloads.BETA_2D_CRIT,
+            "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
 
 
 def bench_serving(torch, serve, workloads, jobs):
@@ -317,6 +342,9 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps)
         print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
+    if not args.no_coarse:
+        out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
+        print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
     if not args.no_serving:
         from paper_1006_3865_amd import serve
         out["serving"] = bench_serving(torch, serve, workloads, args.serve_jobs)

@@ -69,6 +69,12 @@ enum spin_kernel {
                                any L % 8 == 0 with L >= 16, both models, ping-pong buffers */
 };
 
+/* Order of the updates within a sweep (spin_set_schedule). */
+enum spin_schedule {
+  SPIN_SCHEDULE_CHECKERBOARD = 0, /* the chain above (default) */
+  SPIN_SCHEDULE_COARSE = 1        /* the paper's coarse-tile order with multi-hit: its own chain */
+};
+
 /* Full set of creation parameters. */
 typedef struct {
   int model;                 /* spin_model */
@@ -140,6 +146,20 @@ int spin_set_stream(spin_lattice* h, void* stream);
  * 0 means the library default.  SPIN_EINVAL if the family cannot run this
  * lattice.  Results are bit-identical for every accepted choice. */
 int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads);
+
+/* Sec. 3, steps 1-7, with the generalized multi-hit of the paragraph after
+ * them: the paper's own update order, a chain of its own that depends on
+ * tile and hits.  With SPIN_SCHEDULE_COARSE the lattice is cut into tiles
+ * of edge `tile` (2D: 8, 16, 32 or 64; 3D: 8 or 16; L/tile even); a sweep
+ * updates every tile whose tile coordinates sum to an even number, then
+ * every odd one; inside a tile its colour-0 sites, then its colour-1
+ * sites, `hits` times (>= 1), each from the current spins.  A sweep is
+ * hits * L^d attempts; hit h of sweep t of site s with colour c draws word
+ * (s>>1)&3 of Philox counter (s>>3, t*hits + h, replica, c), so
+ * (sweep index + sweeps) * hits must stay <= 2^32.  The kernel family
+ * setting does not apply.  SPIN_SCHEDULE_CHECKERBOARD (tile and hits
+ * ignored) restores the canonical chain.  SPIN_EINVAL for other values. */
+int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits);
 
 /* Sec. 4 (tile sizes chosen by experiment): time every family and tile that
  * can run this handle's shape for `sweeps` (1..1000) sweeps at beta on a

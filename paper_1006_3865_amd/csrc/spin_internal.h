@@ -83,6 +83,13 @@ hipError_t launch_tiled_phase(const Lat& lat, uint32_t t, uint32_t colour, const
 // One whole sweep of a 2D Ising lattice from `src` into `dst` (ping-pong).
 // With rec != nullptr the sweep also records E, M of its result if the
 // kernel can (returns true in *measured), else the caller measures.
+// The coarse-tile schedule with multi-hit: tile edge T (2D: 8, 16, 32, 64;
+// 3D: 8, 16; L/T even), k hits, tiles of parity q; in place.  Jn: packed
+// couplings (EA) or nullptr.
+bool coarse_supported(const Lat& lat, int T);
+hipError_t launch_coarse_phase(const Lat& lat, const uint32_t* Jn, uint32_t t, uint32_t k, uint32_t q,
+                               const Accept& acc, int T, hipStream_t stream);
+
 // General streaming sweep (both colours, any L % 8 == 0, L >= 16, both
 // models): tile.y = rows per workgroup (3D), tile.z = planes per strip,
 // tile.threads = 256 or 512.  Jn: nibble-packed couplings (EA) or nullptr.

@@ -134,6 +134,9 @@ struct spin_lattice {
   int kernel;  // requested family
   Tile tile;   // requested shape (0 = default)
   Allocator mem;
+  int schedule;         // spin_schedule
+  int coarse_tile;      // SPIN_SCHEDULE_COARSE: tile edge T
+  int hits;             // SPIN_SCHEDULE_COARSE: k
   BatchSingle* single;  // one-task block of the LDS-resident batch kernel (allocated on first use)
   uint32_t* jn;         // EA couplings as nibble words for that kernel (packed on first use)
 };
@@ -340,6 +343,38 @@ static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int6
   return SPIN_OK;
 }
 
+// n sweeps of the coarse-tile schedule (two launches each, one per tile
+// parity), records by the measurement kernel.
+static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM) {
+  if ((h->t + (uint64_t)n) * (uint64_t)h->hits > kMaxSweepIndex)
+    return fail(SPIN_EINVAL, "sweep index times hits would exceed 2^32");
+  if (int rc = ensure_jn(h)) return rc;
+  const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
+  const uint32_t parts = measure_parts(lat_of(h));
+  if (nrec > 0)
+    if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  hipError_t e = hipSuccess;
+  uint32_t rec = 0;
+  for (int i = 0; i < n; ++i) {
+    const Lat l = lat_of(h);
+    const uint32_t t = (uint32_t)(h->t + (uint64_t)i);
+    for (uint32_t q = 0; q < 2 && e == hipSuccess; ++q)
+      e = launch_coarse_phase(l, h->jn, t, (uint32_t)h->hits, q, acc, h->coarse_tile, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "coarse phase launch");
+    if (every > 0 && (i + 1) % every == 0) {
+      e = launch_measure(l, Record{h->part + (size_t)rec * parts * 2}, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "measure launch");
+      ++rec;
+    }
+  }
+  if (nrec > 0) {
+    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "record finalize launch");
+  }
+  h->t += (uint64_t)n;
+  return SPIN_OK;
+}
+
 // Enqueue n sweeps; if every > 0 write records into device arrays dE, dM.
 static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
@@ -348,6 +383,7 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   if (h->t + (uint64_t)n > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index would exceed 2^32");
   if (n == 0) return SPIN_OK;
   const Accept acc = make_accept(beta, h->d);
+  if (h->schedule == SPIN_SCHEDULE_COARSE) return run_coarse(h, n, acc, every, dE, dM);
   Tile tile;
   const int kernel = resolve(h, &tile);
   hipError_t e = hipSuccess;
@@ -505,6 +541,9 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   h->buf[0] = h->buf[1] = nullptr;
   h->single = nullptr;
   h->jn = nullptr;
+  h->schedule = SPIN_SCHEDULE_CHECKERBOARD;
+  h->coarse_tile = 0;
+  h->hits = 1;
   h->cur = 0;
   h->J = nullptr;
   h->em = nullptr;
@@ -743,6 +782,26 @@ int spin_autotune(spin_lattice* h, double beta, int sweeps) {
   h->kernel = best.kernel;
   h->tile = best.tile;
   return best.kernel;
+}
+
+int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (schedule == SPIN_SCHEDULE_CHECKERBOARD) {
+    h->schedule = schedule;
+    h->coarse_tile = 0;
+    h->hits = 1;
+    return SPIN_OK;
+  }
+  if (schedule != SPIN_SCHEDULE_COARSE) return fail(SPIN_EINVAL, "unknown schedule %d", schedule);
+  if (hits < 1) return fail(SPIN_EINVAL, "hits must be >= 1 (got %d)", hits);
+  if (!coarse_supported(lat_of(h), tile))
+    return fail(SPIN_EINVAL, "coarse tile %d cannot run L=%d d=%d (2D: 8, 16, 32, 64; 3D: 8, 16; L/T even)", tile,
+                h->L, h->d);
+  if ((h->t + 1) * (uint64_t)hits > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index times hits past 2^32");
+  h->schedule = schedule;
+  h->coarse_tile = tile;
+  h->hits = hits;
+  return SPIN_OK;
 }
 
 int spin_get_kernel(const spin_lattice* h) {

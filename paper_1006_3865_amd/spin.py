@@ -17,6 +17,7 @@ SPIN_ISING, SPIN_EA_PMJ = 0, 1
 SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EDEVICE, SPIN_ESTATE = 0, -1, -2, -3, -4
 SPIN_KERNEL_AUTO, SPIN_KERNEL_GENERIC, SPIN_KERNEL_RESIDENT, SPIN_KERNEL_TILED, SPIN_KERNEL_FUSED = 0, 1, 2, 3, 4
 SPIN_KERNEL_STREAM = 5
+SPIN_SCHEDULE_CHECKERBOARD, SPIN_SCHEDULE_COARSE = 0, 1
 KERNEL_NAMES = {0: "auto", 1: "generic", 2: "resident", 3: "tiled", 4: "fused", 5: "stream"}
 
 # Every symbol include/spin.h declares, with (restype, argtypes).
@@ -61,6 +62,7 @@ SIGNATURES = {
     "spin_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "spin_get_kernel": (_c.c_int, [_P]),
     "spin_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
+    "spin_set_schedule": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int]),
     "spin_synchronize": (_c.c_int, [_P]),
     "spin_device_spins": (_c.c_void_p, [_P]),
     "spin_threshold_table": (_c.c_int, [_c.c_double, _c.c_int, _u64p]),
@@ -316,6 +318,10 @@ class Lattice:
 
     def set_kernel(self, kernel, tile_x=0, tile_y=0, tile_z=0, threads=0):
         spin_set_kernel(self.h, kernel, tile_x, tile_y, tile_z, threads)
+
+    def set_schedule(self, schedule, tile=0, hits=1):
+        """SPIN_SCHEDULE_COARSE with tile edge and hits: the paper's coarse-tile multi-hit order."""
+        _check(load().spin_set_schedule(self.h, int(schedule), int(tile), int(hits)))
 
     def autotune(self, beta=0.44, sweeps=4):
         """Time every kernel family and tile for this shape, keep the fastest (see spin_autotune)."""

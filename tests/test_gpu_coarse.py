@@ -1,0 +1,97 @@
+"""GPU parity of the coarse-tile multi-hit schedule (the paper's own update order) against the oracle.
+
+Every supported tile edge in 2D and 3D, Ising and +-J, several hit counts and
+inverse temperatures (including 0, inf and 3, which has T = 0 entries),
+records after every sweep, and switching between the schedules in the middle
+of a chain.  Tolerance 0: spins, E and M are integers.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1006_3865_amd import spin, workloads
+
+pytestmark = pytest.mark.gpu
+COARSE, CHECKER = spin.SPIN_SCHEDULE_COARSE, spin.SPIN_SCHEDULE_CHECKERBOARD
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    spin.load()
+    return torch
+
+
+def run(oracle_mod, model, L, d, T, k, sched, replica=1):
+    note("coarse", model, L, d, "T", T, "k", k)
+    seed = workloads.seed(0x40 + L + T + k)
+    cs = workloads.seed(0x11) if model else None
+    lat = spin.Lattice(model, L, d, seed, coupling_seed=cs, replica=replica)
+    lat.set_schedule(COARSE, T, k)
+    J = oracle_mod.couplings(L, d, cs, 0) if model else None
+    ch = oracle_mod.Chain(L, d, seed, replica, J=J)
+    for (n, beta, every) in sched:
+        E, M = lat.sweep_record(n, beta, every)
+        Eo, Mo = ch.coarse_sweep(n, beta, T, k, every=every)
+        np.testing.assert_array_equal(E, Eo)
+        np.testing.assert_array_equal(M, Mo)
+        got = lat.spins()
+        if not np.array_equal(got, ch.spins):
+            raise AssertionError("spins differ at %d sites (t=%d)" % (int((got != ch.spins).sum()), ch.t))
+        assert lat.t == ch.t
+    lat.close()
+
+
+BETAS = [0.3, workloads.BETA_2D_CRIT, 0.9, 0.0, math.inf, 3.0]
+
+
+@pytest.mark.parametrize("model,L,T,k", [
+    (0, 16, 8, 1), (0, 32, 8, 3), (0, 32, 16, 2), (0, 64, 16, 1), (0, 64, 32, 4), (0, 128, 64, 2),
+    (0, 256, 16, 5), (1, 32, 8, 2), (1, 64, 32, 3), (1, 128, 64, 1),
+])
+def test_coarse_2d(oracle_mod, model, L, T, k):
+    run(oracle_mod, model, L, 2, T, k, [(2, b, 1) for b in BETAS])
+
+
+@pytest.mark.parametrize("model,L,T,k", [
+    (0, 16, 8, 1), (0, 32, 8, 2), (0, 32, 16, 3), (0, 64, 16, 1), (1, 16, 8, 2), (1, 32, 16, 2), (1, 48, 8, 1),
+])
+def test_coarse_3d(oracle_mod, model, L, T, k):
+    run(oracle_mod, model, L, 3, T, k, [(1, b, 1) for b in [workloads.BETA_3D, 0.0, math.inf, 3.0, 0.7]])
+
+
+def test_switching_schedules_mid_chain(oracle_mod):
+    L, d, seed = 64, 2, workloads.seed(0x4F)
+    lat = spin.Lattice(0, L, d, seed)
+    ch = oracle_mod.Chain(L, d, seed)
+    for (mode, T, k, n) in [(COARSE, 16, 3, 2), (CHECKER, 0, 1, 3), (COARSE, 32, 2, 2), (CHECKER, 0, 1, 1)]:
+        lat.set_schedule(mode, T, k)
+        lat.sweep(n, 0.5)
+        if mode == COARSE:
+            ch.coarse_sweep(n, 0.5, T, k)
+        else:
+            ch.sweep(n, 0.5)
+        np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
+
+
+def test_bad_schedules_rejected():
+    lat = spin.Lattice(0, 48, 2, 1)
+    for (mode, T, k) in [(COARSE, 16, 1), (COARSE, 8, 0), (COARSE, 12, 1), (COARSE, 24, 1), (7, 8, 1)]:
+        with pytest.raises(spin.SpinError):
+            lat.set_schedule(mode, T, k)          # 48/16 = 3 is odd; k < 1; 12 and 24 unsupported; unknown mode
+    lat.set_schedule(COARSE, 8, 2)                # 48/8 = 6 tiles per edge
+    lat.close()
+    lat3 = spin.Lattice(0, 64, 3, 1)
+    with pytest.raises(spin.SpinError):
+        lat3.set_schedule(COARSE, 32, 1)          # 3D tiles are 8 or 16
+    lat3.close()
