@@ -19,5 +19,7 @@ from .oracle import (  # noqa: F401
     measure,
     sweeps,
     coarse_sweeps,
+    msc_sweeps,
+    MscChain,
     Chain,
 )

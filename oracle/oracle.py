@@ -64,6 +64,9 @@ class OracleLib:
                                              ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, i64p, i64p]
         lib.oracle_coarse_sweeps.restype = ctypes.c_int
+        lib.oracle_msc_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int, i64p, i64p]
+        lib.oracle_msc_sweeps.restype = ctypes.c_int
         self.lib = lib
 
     def philox4x32_10(self, ctr, key):
@@ -139,6 +142,21 @@ class OracleLib:
             raise ValueError("oracle_coarse_sweeps rejected its arguments")
         return E[:nrec].copy(), M[:nrec].copy()
 
+    def msc_sweeps(self, L, d, J, spins, seed, p0, t0, n, beta, every=0):
+        """Multi-spin-coded +-J glass: spins int8[32, N], J int8[32, d, N]; n sweeps in place.
+        Returns E, M int64[n//every, 32]."""
+        assert spins.dtype == np.int8 and spins.flags.c_contiguous and spins.size == 32 * L ** d
+        Jarr = np.ascontiguousarray(J, dtype=np.int8)
+        assert Jarr.size == 32 * d * L ** d
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1) * 32, dtype=np.int64)
+        M = np.zeros(max(nrec, 1) * 32, dtype=np.int64)
+        rc = self.lib.oracle_msc_sweeps(L, d, _ptr(Jarr, ctypes.c_int8), _ptr(spins, ctypes.c_int8), seed, p0, t0, n,
+                                        float(beta), every, _ptr(E, ctypes.c_int64), _ptr(M, ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle_msc_sweeps rejected its arguments")
+        return E[:nrec * 32].reshape(nrec, 32).copy(), M[:nrec * 32].reshape(nrec, 32).copy()
+
 
 _default = None
 
@@ -178,6 +196,30 @@ def sweeps(L, d, J, spins, seed, replica, t0, n, beta, every=0, order=0, stats=N
 
 def coarse_sweeps(L, d, J, spins, seed, replica, t0, n, beta, T, k, every=0):
     return default().coarse_sweeps(L, d, J, spins, seed, replica, t0, n, beta, T, k, every)
+
+
+def msc_sweeps(L, d, J, spins, seed, p0, t0, n, beta, every=0):
+    return default().msc_sweeps(L, d, J, spins, seed, p0, t0, n, beta, every)
+
+
+class MscChain:
+    """32 multi-spin-coded +-J systems: realisations r0 + b, hot starts of replicas p0 + b."""
+
+    def __init__(self, L, d, cseed, r0, seed, p0, lib=None):
+        self.lib = lib or default()
+        self.L, self.d, self.seed, self.p0 = L, d, seed, p0
+        self.J = np.stack([self.lib.couplings(L, d, cseed, r0 + b) for b in range(32)])
+        self.spins = np.stack([self.lib.init_spins(L, d, seed, p0 + b) for b in range(32)])
+        self.t = 0
+
+    def sweep(self, n, beta, every=0):
+        E, M = self.lib.msc_sweeps(self.L, self.d, self.J, self.spins, self.seed, self.p0, self.t, n, beta, every)
+        self.t += n
+        return E, M
+
+    def measure(self):
+        out = [self.lib.measure(self.L, self.d, self.J[b], self.spins[b]) for b in range(32)]
+        return np.array([e for e, _ in out]), np.array([m for _, m in out])
 
 
 class Chain:

@@ -60,6 +60,17 @@
  *  independent.  Hit h (0..k-1) of site s of colour c in sweep t draws
  *  word (s>>1)&3 of Philox counter (s>>3, t*k + h, replica, c).  With
  *  T = 1 and k = 1 this is the canonical chain.
+ *
+ *  Multi-spin coding of the +-J glass (Sec. 4, last paragraph: many
+ *  disorder realisations at once, combined with asynchronous multi-spin
+ *  coding), a mode with its own chain: 32 systems b = 0..31 of edge L
+ *  share the lattice; system b has the couplings of realisation r0 + b and
+ *  the hot start of replica p0 + b, both by the rules above.  In sweep t,
+ *  colour c, site s draws ONE word, (s>>1)&3 of Philox counter
+ *  (s>>3, t, p0, 4 + c), shared by the 32 systems; each system b flips its
+ *  spin iff r < T[(k_b + z)/2] with its own k_b.  Each system alone is a
+ *  Metropolis chain of its realisation; the systems are coupled only
+ *  through the shared draws.
  */
 #include <math.h>
 #include <stddef.h>
@@ -347,6 +358,47 @@ int oracle_coarse_sweeps(int L, int d, const int8_t* J, int8_t* spins,
           }
     if (every > 0 && (i + 1) % every == 0) {
       oracle_measure(L, d, J, spins, &E[rec], &M[rec]);
+      ++rec;
+    }
+  }
+  return 0;
+}
+
+/*
+ * Multi-spin-coded +-J glass (see the header): spins[b*N + s] and
+ * J[(b*d + dir)*N + s] hold the 32 systems' spins and couplings.  n sweeps
+ * from absolute index t0; if every > 0, the 32 energies and magnetisations
+ * after each every-th sweep go to E[rec*32 + b], M[rec*32 + b].
+ */
+int oracle_msc_sweeps(int L, int d, const int8_t* J, int8_t* spins,
+                      uint64_t seed, uint32_t p0, uint64_t t0, int n,
+                      double beta, int every, int64_t* E, int64_t* M) {
+  if (!valid_shape(L, d) || n < 0 || !J) return -1;
+  if (isnan(beta) || beta < 0) return -1;
+  if (t0 + (uint64_t)n > ((uint64_t)1 << 32)) return -1;
+  int z = 2 * d;
+  uint64_t Tab[7];
+  oracle_table(beta, d, Tab);
+  int64_t N = site_count(L, d);
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    uint32_t t = (uint32_t)(t0 + (uint64_t)i);
+    for (int c = 0; c < 2; ++c)
+      for (int64_t s = 0; s < N; ++s) {
+        if (colour_of(s, L, d) != c) continue;
+        uint32_t r = draw(seed, (uint32_t)(s >> 3), t, p0, 4u + (uint32_t)c,
+                          (unsigned)((s >> 1) & 3));
+        for (int b = 0; b < 32; ++b) {
+          int8_t* sb = spins + (int64_t)b * N;
+          const int8_t* Jb = J + (int64_t)b * d * N;
+          int kk = sb[s] * local_field(s, L, d, Jb, sb, N);
+          if ((uint64_t)r < Tab[(kk + z) / 2]) sb[s] = (int8_t)(-sb[s]);
+        }
+      }
+    if (every > 0 && (i + 1) % every == 0) {
+      for (int b = 0; b < 32; ++b)
+        oracle_measure(L, d, J + (int64_t)b * d * N, spins + (int64_t)b * N,
+                       &E[rec * 32 + b], &M[rec * 32 + b]);
       ++rec;
     }
   }

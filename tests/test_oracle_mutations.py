@@ -42,6 +42,10 @@ MUTANTS = {
                                     "              for (int c = 1; c >= 0; --c)\n                for (int zz"),
     "coarse_single_hit": ("for (int h = 0; h < k; ++h) {", "for (int h = 0; h < 1; ++h) {"),
     "coarse_last_tiles_skipped": ("int B = L / T;", "int B = L / T - 1;"),
+    # the multi-spin-coded glass
+    "msc_counter_space": ("t, p0, 4u + (uint32_t)c,", "t, p0, (uint32_t)c,"),
+    "msc_all_systems_share_couplings": ("const int8_t* Jb = J + (int64_t)b * d * N;", "const int8_t* Jb = J;"),
+    "msc_draw_from_wrong_replica": ("(uint32_t)(s >> 3), t, p0, 4u", "(uint32_t)(s >> 3), t, p0 + 1u, 4u"),
 }
 
 
@@ -108,6 +112,19 @@ def _quick_pins(lib, rocrand_philox):
             bf.coarse_sweep(ref, L, d, J, beta, t, T, k, lambda s, hit, c: int(w[(s >> 3, hit, c)][(s >> 1) & 3]))
         np.testing.assert_array_equal(got, ref)
 
+    # multi-spin-coded systems against single-system brute force with the shared draws
+    L, d, beta, r0, p0, t0, n = 6, 2, 0.3, 3, 40, 1, 2
+    J = np.stack([lib.couplings(L, d, 0x51, r0 + b) for b in range(32)])
+    spins = np.stack([lib.init_spins(L, d, 0x52, p0 + b) for b in range(32)])
+    start = spins.copy()
+    lib.msc_sweeps(L, d, J, spins, 0x52, p0, t0, n, beta)
+    keys = [(g, t, c) for t in range(t0, t0 + n) for c in (0, 1) for g in range(5)]
+    w = dict(zip(keys, rocrand_philox([(g, t, p0, 4 + c) for (g, t, c) in keys], (0x52, 0))))
+    for b in (0, 7, 31):
+        ref = start[b].copy()
+        for t in range(t0, t0 + n):
+            bf.sweep(ref, L, d, J[b], beta, t, lambda s, tt, c: int(w[(s >> 3, tt, c)][(s >> 1) & 3]))
+        np.testing.assert_array_equal(spins[b], ref)
 
 def test_unmodified_oracle_passes_quick_pins(oracle_mod, rocrand_philox):
     _quick_pins(oracle_mod.default(), rocrand_philox)
