@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-tile multi-hit schedule")
+    ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     return ap.parse_args()
 
@@ -194,6 +195,29 @@ def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64),
         lat.close()
     return {"workload": "ising2d coarse-tile multi-hit", "beta": workloads.BETA_2D_CRIT,
             "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
+
+
+def bench_msc(torch, spin, workloads, shapes=((256, 3), (128, 3), (4096, 2))):
+    """Multi-spin-coded +-J glass: 32 realisations per word, attempts/ns (32 * L^d per sweep) at the
+    middle of the batch's temperature ladder, HIP events on the handle's stream."""
+    stream = torch.cuda.Stream()
+    beta = workloads.ea_betas()[7]
+    out = {}
+    for (L, d) in shapes:
+        m = spin.Msc(L, d, workloads.seed(0x11), 0, workloads.seed(0x10), 0, stream=stream)
+        N = L ** d
+        n = max(4, min(400, int(2e11 / (32 * N))))
+        m.sweep(2, beta)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        m.sweep(n, beta)
+        b.record(stream)
+        m.synchronize()
+        ms = a.elapsed_time(b)
+        out["d%d_L%d" % (d, L)] = {"attempts_per_ns": round(32 * N * n / (ms * 1e6), 1),
+                                   "ps_per_attempt": round(ms * 1e9 / (32 * N * n), 4), "sweeps": n}
+        m.close()
+    return {"workload": "ea multi-spin-coded (32 realisations per word)", "beta": beta, "rates": out}
 
 
 def bench_serving(torch, serve, workloads, jobs):
@@ -345,6 +369,9 @@ def main():
     if not args.no_coarse:
         out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
+    if not args.no_msc:
+        out["multispin"] = bench_msc(torch, spin, workloads)
+        print("multispin:", json.dumps(out["multispin"]), file=sys.stderr, flush=True)
     if not args.no_serving:
         from paper_1006_3865_amd import serve
         out["serving"] = bench_serving(torch, serve, workloads, args.serve_jobs)

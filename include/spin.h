@@ -286,6 +286,44 @@ int spin_batch_set_workgroups_per_cu(spin_batch* b, int wgs);
 /* Wait for the batch's queued work. */
 int spin_batch_synchronize(spin_batch* b);
 
+/* ---------------------------------------------------- multi-spin coding
+ * Sec. 4, last paragraph (many disorder realisations at once, combined with
+ * multi-spin coding): 32 +-J systems of edge L (L % 8 == 0, d = 2 or 3) in
+ * the bits of one 32-bit word per site.  System b has the couplings of
+ * realisation realisation0 + b and the hot start of replica replica0 + b,
+ * by the rules at the top of this file (with the coupling seed and seed
+ * given), so each system is the lattice spin_create_config would make.
+ * A chain of its own: in sweep t, colour c, site s draws one word,
+ * (s>>1)&3 of Philox(seed, counter (s>>3, t, replica0, 4 + c)), shared by
+ * the 32 systems; system b flips s iff that word < T[(k_b+2d)/2] with its
+ * own k_b (Eq. 2).  A sweep is 32 * L^d attempts. */
+typedef struct spin_msc spin_msc;
+
+/* NULL on error (spin_last_error). */
+spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisation0, uint64_t seed,
+                          uint32_t replica0, void* stream);
+void spin_msc_free(spin_msc* h);                   /* NULL-safe; waits for queued work */
+
+/* n >= 0 sweeps at beta (as spin_sweep); asynchronous. */
+int spin_msc_sweep(spin_msc* h, int n, double beta);
+
+/* As spin_msc_sweep, recording after every every-th sweep the 32 energies
+ * and magnetisations: E[r*32 + b], M[r*32 + b] for record r (n/every
+ * records; HOST arrays).  Synchronises. */
+int spin_msc_sweep_record(spin_msc* h, int n, double beta, int every, int64_t* E, int64_t* M);
+
+/* Current E[b], M[b] of the 32 systems (host arrays of 32).  Synchronises. */
+int spin_msc_measure(spin_msc* h, int64_t* E, int64_t* M);
+
+/* Spins of system b (0..31) into a host array of n == L^d int8.  Synchronous. */
+int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n);
+
+/* Absolute index of the next sweep. */
+uint64_t spin_msc_sweeps_done(const spin_msc* h);
+
+/* Wait for the handle's queued work. */
+int spin_msc_synchronize(spin_msc* h);
+
 #ifdef __cplusplus
 }
 #endif

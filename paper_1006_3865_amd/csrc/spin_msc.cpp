@@ -1,0 +1,212 @@
+// spin_msc.cpp -- C ABI of the multi-spin-coded +-J glass (include/spin.h,
+// spin_msc_*): 32 systems in the bits of one word per site.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "spin.h"
+#include "spin_internal.h"
+#include "spin_msc.h"
+
+using namespace spin;
+
+static int mfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return set_error(code, buf);
+}
+
+struct spin_msc {
+  int L, d;
+  uint64_t N;
+  uint64_t seed;
+  uint32_t p0;
+  uint64_t t;
+  uint32_t* S;       // [N]
+  uint32_t* J;       // [d][N]
+  int64_t* part;     // measurement partial counts
+  int64_t* rec;      // records staging (2 * 32 * rec_cap)
+  size_t rec_cap;
+  hipStream_t stream;
+};
+
+static void msc_destroy(spin_msc* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(h->S);
+  (void)hipFree(h->J);
+  (void)hipFree(h->part);
+  (void)hipFree(h->rec);
+  delete h;
+}
+
+template <class T>
+static bool dalloc(T** p, size_t bytes) {
+  if (hipMalloc((void**)p, bytes ? bytes : 16) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
+
+static MscArgs msc_args(const spin_msc* h, double beta) {
+  const Accept acc = make_accept(beta, h->d);
+  MscArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.keys = make_round_keys(h->seed);
+  for (int u = 0; u < 3; ++u) a.thr[u] = (u < h->d) ? acc.T[2 * h->d - u] : ((uint64_t)1 << 32);
+  a.N = h->N;
+  a.L = (uint32_t)h->L;
+  a.p0 = h->p0;
+  return a;
+}
+
+// n sweeps; records (every > 0) of the 32 systems into device arrays dE, dM.
+static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
+  if (!h) return mfail(SPIN_EINVAL, "NULL handle");
+  if (n < 0) return mfail(SPIN_EINVAL, "n must be >= 0");
+  if (std::isnan(beta) || beta < 0) return mfail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
+  if (h->t + (uint64_t)n > ((uint64_t)1 << 32)) return mfail(SPIN_EINVAL, "sweep index would exceed 2^32");
+  MscArgs a = msc_args(h, beta);
+  uint32_t rec = 0;
+  for (int i = 0; i < n; ++i) {
+    a.t = (uint32_t)(h->t + (uint64_t)i);
+    for (uint32_t c = 0; c < 2; ++c) {
+      a.colour = c;
+      hipError_t e = launch_msc_phase(h->S, h->J, a, (uint32_t)h->d, h->stream);
+      if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin phase launch: %s", hipGetErrorString(e));
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      hipError_t e = launch_msc_measure(h->S, h->J, (uint32_t)h->L, (uint32_t)h->d, h->N, h->part, dE + 32 * rec,
+                                        dM + 32 * rec, h->stream);
+      if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin measure launch: %s", hipGetErrorString(e));
+      ++rec;
+    }
+  }
+  h->t += (uint64_t)n;
+  return SPIN_OK;
+}
+
+static int ensure_rec(spin_msc* h, size_t nrec) {
+  if (nrec <= h->rec_cap) return SPIN_OK;
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(h->rec);
+  h->rec_cap = 0;
+  if (!dalloc(&h->rec, 2 * 32 * nrec * sizeof(int64_t))) return mfail(SPIN_ENOMEM, "record buffer allocation failed");
+  h->rec_cap = nrec;
+  return SPIN_OK;
+}
+
+extern "C" {
+
+spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisation0, uint64_t seed,
+                          uint32_t replica0, void* stream) {
+  if (d != 2 && d != 3) {
+    mfail(SPIN_EINVAL, "d must be 2 or 3 (got %d)", d);
+    return nullptr;
+  }
+  if (L < 8 || L % 8 != 0) {
+    mfail(SPIN_EINVAL, "L must be a multiple of 8 (got %d)", L);
+    return nullptr;
+  }
+  uint64_t N = 1;
+  for (int k = 0; k < d; ++k) N *= (uint64_t)L;
+  if (N / 8 >= ((uint64_t)1 << 32)) {
+    mfail(SPIN_EINVAL, "L^d/8 must be < 2^32");
+    return nullptr;
+  }
+  spin_msc* h = new spin_msc();
+  h->L = L;
+  h->d = d;
+  h->N = N;
+  h->seed = seed;
+  h->p0 = replica0;
+  h->t = 0;
+  h->S = nullptr;
+  h->J = nullptr;
+  h->part = nullptr;
+  h->rec = nullptr;
+  h->rec_cap = 0;
+  h->stream = (hipStream_t)stream;
+  if (!dalloc(&h->S, N * 4) || !dalloc(&h->J, (size_t)d * N * 4) ||
+      !dalloc(&h->part, (size_t)msc_count_parts(N) * 64 * sizeof(int64_t))) {
+    mfail(SPIN_ENOMEM, "device allocation failed (%llu sites)", (unsigned long long)N);
+    msc_destroy(h);
+    return nullptr;
+  }
+  hipError_t e = launch_msc_init(h->S, N, seed, replica0, h->stream);
+  if (e == hipSuccess) e = launch_msc_couplings(h->J, N, (uint32_t)d, coupling_seed, realisation0, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    mfail(SPIN_EDEVICE, "multi-spin setup: %s", hipGetErrorString(e));
+    msc_destroy(h);
+    return nullptr;
+  }
+  return h;
+}
+
+void spin_msc_free(spin_msc* h) { msc_destroy(h); }
+
+int spin_msc_sweep(spin_msc* h, int n, double beta) { return msc_run(h, n, beta, 0, nullptr, nullptr); }
+
+int spin_msc_sweep_record(spin_msc* h, int n, double beta, int every, int64_t* E, int64_t* M) {
+  if (!h || !E || !M) return mfail(SPIN_EINVAL, "NULL argument");
+  if (every < 1) return mfail(SPIN_EINVAL, "every must be >= 1");
+  const size_t nrec = (size_t)(n > 0 ? n / every : 0);
+  if (int rc = ensure_rec(h, nrec ? nrec : 1)) return rc;
+  int rc = msc_run(h, n, beta, every, h->rec, h->rec + 32 * h->rec_cap);
+  if (rc != SPIN_OK) return rc;
+  hipError_t e = hipSuccess;
+  if (nrec) {
+    e = hipMemcpyAsync(E, h->rec, 32 * nrec * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(M, h->rec + 32 * h->rec_cap, 32 * nrec * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin records: %s", hipGetErrorString(e));
+  return SPIN_OK;
+}
+
+int spin_msc_measure(spin_msc* h, int64_t* E, int64_t* M) {
+  if (!h || !E || !M) return mfail(SPIN_EINVAL, "NULL argument");
+  if (int rc = ensure_rec(h, 1)) return rc;
+  hipError_t e = launch_msc_measure(h->S, h->J, (uint32_t)h->L, (uint32_t)h->d, h->N, h->part, h->rec,
+                                    h->rec + 32 * h->rec_cap, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(E, h->rec, 32 * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(M, h->rec + 32 * h->rec_cap, 32 * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin measure: %s", hipGetErrorString(e));
+  return SPIN_OK;
+}
+
+int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n) {
+  if (!h || !out) return mfail(SPIN_EINVAL, "NULL argument");
+  if (system < 0 || system >= 32) return mfail(SPIN_EINVAL, "system must be in 0..31 (got %d)", system);
+  if (n != h->N) return mfail(SPIN_EINVAL, "n must equal L^d");
+  std::vector<uint32_t> w(h->N);
+  hipError_t e = hipMemcpyAsync(w.data(), h->S, h->N * 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin get spins: %s", hipGetErrorString(e));
+  for (size_t s = 0; s < n; ++s) out[s] = ((w[s] >> system) & 1u) ? (int8_t)-1 : (int8_t)1;
+  return SPIN_OK;
+}
+
+uint64_t spin_msc_sweeps_done(const spin_msc* h) { return h ? h->t : 0; }
+
+int spin_msc_synchronize(spin_msc* h) {
+  if (!h) return mfail(SPIN_EINVAL, "NULL handle");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin synchronize: %s", hipGetErrorString(e));
+  return SPIN_OK;
+}
+
+}  // extern "C"

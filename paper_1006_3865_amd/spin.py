@@ -63,6 +63,14 @@ SIGNATURES = {
     "spin_get_kernel": (_c.c_int, [_P]),
     "spin_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
     "spin_set_schedule": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int]),
+    "spin_msc_create": (_P, [_c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _c.c_void_p]),
+    "spin_msc_free": (None, [_P]),
+    "spin_msc_sweep": (_c.c_int, [_P, _c.c_int, _c.c_double]),
+    "spin_msc_sweep_record": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _i64p, _i64p]),
+    "spin_msc_measure": (_c.c_int, [_P, _i64p, _i64p]),
+    "spin_msc_get_spins": (_c.c_int, [_P, _c.c_int, _i8p, _c.c_size_t]),
+    "spin_msc_sweeps_done": (_c.c_uint64, [_P]),
+    "spin_msc_synchronize": (_c.c_int, [_P]),
     "spin_synchronize": (_c.c_int, [_P]),
     "spin_device_spins": (_c.c_void_p, [_P]),
     "spin_threshold_table": (_c.c_int, [_c.c_double, _c.c_int, _u64p]),
@@ -480,3 +488,59 @@ class Batch:
 
     def synchronize(self):
         _check(load().spin_batch_synchronize(self.h))
+
+
+# ------------------------------------------------------------ multi-spin coding
+
+class Msc:
+    """32 +-J systems in the bits of one word per site (see spin_msc_* in spin.h)."""
+
+    def __init__(self, L, d, coupling_seed, realisation0, seed, replica0=0, stream=None):
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        lib = load()
+        self.h = lib.spin_msc_create(L, d, coupling_seed, realisation0, seed, replica0, sp)
+        if not self.h:
+            raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+        self.L, self.d, self.N = L, d, L ** d
+
+    def close(self):
+        if self.h:
+            load().spin_msc_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n, beta):
+        _check(load().spin_msc_sweep(self.h, int(n), float(beta)))
+
+    def sweep_record(self, n, beta, every):
+        nrec = n // every
+        E = np.zeros(max(nrec, 1) * 32, dtype=np.int64)
+        M = np.zeros(max(nrec, 1) * 32, dtype=np.int64)
+        _check(load().spin_msc_sweep_record(self.h, int(n), float(beta), int(every), E.ctypes.data_as(_i64p),
+                                            M.ctypes.data_as(_i64p)))
+        return E[:nrec * 32].reshape(nrec, 32), M[:nrec * 32].reshape(nrec, 32)
+
+    def measure(self):
+        E = np.zeros(32, dtype=np.int64)
+        M = np.zeros(32, dtype=np.int64)
+        _check(load().spin_msc_measure(self.h, E.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p)))
+        return E, M
+
+    def spins(self, system):
+        out = np.empty(self.N, dtype=np.int8)
+        _check(load().spin_msc_get_spins(self.h, int(system), _i8(out), out.size))
+        return out
+
+    @property
+    def t(self):
+        return int(load().spin_msc_sweeps_done(self.h))
+
+    def synchronize(self):
+        _check(load().spin_msc_synchronize(self.h))

@@ -1,0 +1,68 @@
+"""GPU parity of the multi-spin-coded +-J glass (32 systems per word) against the oracle.
+
+Every one of the 32 systems' spins, and the 32 energies and magnetisations
+after every sweep, equal the oracle's multi-spin-coded mode bit for bit, in
+2D and 3D, at several inverse temperatures (including 0, inf and 3).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1006_3865_amd import spin, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    spin.load()
+    return torch
+
+
+@pytest.mark.parametrize("L,d", [(8, 2), (16, 2), (64, 2), (8, 3), (16, 3), (24, 3)])
+def test_msc_matches_oracle(oracle_mod, L, d):
+    cs, seed, r0, p0 = workloads.seed(0x60), workloads.seed(0x61), 5, 70
+    note("msc", L, d)
+    m = spin.Msc(L, d, cs, r0, seed, p0)
+    ch = oracle_mod.MscChain(L, d, cs, r0, seed, p0)
+    for b in (0, 13, 31):
+        np.testing.assert_array_equal(m.spins(b), ch.spins[b])
+    np.testing.assert_array_equal(np.stack(m.measure()), np.stack(ch.measure()))
+    for beta in (0.5, 1.1, 0.0, math.inf, 3.0, workloads.BETA_3D):
+        E, M = m.sweep_record(2, beta, 1)
+        Eo, Mo = ch.sweep(2, beta, every=1)
+        np.testing.assert_array_equal(E, Eo)
+        np.testing.assert_array_equal(M, Mo)
+    for b in range(32):
+        np.testing.assert_array_equal(m.spins(b), ch.spins[b], err_msg="system %d" % b)
+    assert m.t == ch.t
+    m.close()
+
+
+def test_msc_system_equals_its_own_lattice_inputs():
+    """System b starts from the hot start and couplings a lone lattice of replica p0+b, realisation r0+b has."""
+    L, d, cs, seed, r0, p0 = 16, 3, workloads.seed(0x62), workloads.seed(0x63), 9, 3
+    m = spin.Msc(L, d, cs, r0, seed, p0)
+    for b in (0, 31):
+        lone = spin.Lattice(1, L, d, seed, coupling_seed=cs, realisation=r0 + b, replica=p0 + b)
+        np.testing.assert_array_equal(m.spins(b), lone.spins())
+        E, M = m.measure()
+        assert (E[b], M[b]) == lone.measure()
+        lone.close()
+    m.close()
+
+
+def test_msc_rejects_bad_shapes():
+    for (L, d) in ((12, 2), (4, 3), (16, 4)):
+        with pytest.raises(spin.SpinError):
+            spin.Msc(L, d, 1, 0, 1)
