@@ -321,6 +321,14 @@ int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n);
 /* Absolute index of the next sweep. */
 uint64_t spin_msc_sweeps_done(const spin_msc* h);
 
+/* Kernel choice (bits never change): streaming != 0 sweeps both colours in
+ * one launch streamed over planes, with rows (3D: rows per workgroup,
+ * dividing L, <= 32) and planes (per strip) and threads (256 or 512), 0
+ * meaning the default (8, 16, 512); streaming == 0 launches one kernel per
+ * colour.  The library picks streaming where the shape fits.  SPIN_EINVAL
+ * if the streaming shape does not fit L. */
+int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads);
+
 /* Wait for the handle's queued work. */
 int spin_msc_synchronize(spin_msc* h);
 

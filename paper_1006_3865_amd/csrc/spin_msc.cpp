@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "spin.h"
@@ -29,8 +30,11 @@ struct spin_msc {
   uint64_t seed;
   uint32_t p0;
   uint64_t t;
-  uint32_t* S;       // [N]
-  uint32_t* J;       // [d][N]
+  uint32_t* S;       // [N] current spins
+  uint32_t* S2;      // [N] second buffer of the streaming kernel (allocated on first use)
+  uint32_t TY, H, NT;  // streaming shape; NT == 0: the per-colour phase kernel
+  uint32_t* J;       // [d][N] (measurement)
+  uint32_t* J6;      // [N/8][2][4][2d]: bonds of the active sites of each group and colour (phase kernel, on first use)
   int64_t* part;     // measurement partial counts
   int64_t* rec;      // records staging (2 * 32 * rec_cap)
   size_t rec_cap;
@@ -41,7 +45,9 @@ static void msc_destroy(spin_msc* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   (void)hipFree(h->S);
+  (void)hipFree(h->S2);
   (void)hipFree(h->J);
+  (void)hipFree(h->J6);
   (void)hipFree(h->part);
   (void)hipFree(h->rec);
   delete h;
@@ -76,13 +82,25 @@ static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int6
   if (std::isnan(beta) || beta < 0) return mfail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
   if (h->t + (uint64_t)n > ((uint64_t)1 << 32)) return mfail(SPIN_EINVAL, "sweep index would exceed 2^32");
   MscArgs a = msc_args(h, beta);
+  if (h->NT && !h->S2 && n > 0 && !dalloc(&h->S2, h->N * 4)) return mfail(SPIN_ENOMEM, "second spin buffer");
+  if (!h->NT && !h->J6 && n > 0) {
+    if (!dalloc(&h->J6, (size_t)2 * h->d * h->N * 4)) return mfail(SPIN_ENOMEM, "coupling copy");
+    hipError_t e = launch_msc_bonds(h->J, h->J6, (uint32_t)h->L, (uint32_t)h->d, h->N, h->stream);
+    if (e != hipSuccess) return mfail(SPIN_EDEVICE, "coupling copy: %s", hipGetErrorString(e));
+  }
   uint32_t rec = 0;
   for (int i = 0; i < n; ++i) {
     a.t = (uint32_t)(h->t + (uint64_t)i);
-    for (uint32_t c = 0; c < 2; ++c) {
-      a.colour = c;
-      hipError_t e = launch_msc_phase(h->S, h->J, a, (uint32_t)h->d, h->stream);
-      if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin phase launch: %s", hipGetErrorString(e));
+    if (h->NT) {
+      hipError_t e = launch_msc_stream(h->S, h->S2, h->J, a, (uint32_t)h->d, h->TY, h->H, h->NT, h->stream);
+      if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin stream launch: %s", hipGetErrorString(e));
+      std::swap(h->S, h->S2);
+    } else {
+      for (uint32_t c = 0; c < 2; ++c) {
+        a.colour = c;
+        hipError_t e = launch_msc_phase(h->S, h->J6, a, (uint32_t)h->d, h->stream);
+        if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin phase launch: %s", hipGetErrorString(e));
+      }
     }
     if (every > 0 && (i + 1) % every == 0) {
       hipError_t e = launch_msc_measure(h->S, h->J, (uint32_t)h->L, (uint32_t)h->d, h->N, h->part, dE + 32 * rec,
@@ -131,7 +149,15 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
   h->p0 = replica0;
   h->t = 0;
   h->S = nullptr;
+  h->S2 = nullptr;
   h->J = nullptr;
+  h->J6 = nullptr;
+  // streaming shape: 3D slabs of 8 rows, strips of 16 planes, 512 threads (else 256); else the phase kernel
+  h->TY = d == 3 ? 8u : 1u;
+  h->H = 16u;
+  h->NT = 0;
+  for (uint32_t nt : {512u, 256u})
+    if (!h->NT && msc_stream_supported((uint32_t)L, (uint32_t)d, h->TY, h->H, nt)) h->NT = nt;
   h->part = nullptr;
   h->rec = nullptr;
   h->rec_cap = 0;
@@ -201,6 +227,23 @@ int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n) {
 }
 
 uint64_t spin_msc_sweeps_done(const spin_msc* h) { return h ? h->t : 0; }
+
+int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads) {
+  if (!h) return mfail(SPIN_EINVAL, "NULL handle");
+  if (!streaming) {
+    h->NT = 0;
+    return SPIN_OK;
+  }
+  const uint32_t TY = h->d == 3 ? (uint32_t)(rows ? rows : 8) : 1u, H = (uint32_t)(planes ? planes : 16),
+                 NT = (uint32_t)(threads ? threads : 512);
+  if (!msc_stream_supported((uint32_t)h->L, (uint32_t)h->d, TY, H, NT))
+    return mfail(SPIN_EINVAL, "streaming shape rows=%d planes=%d threads=%d cannot run L=%d d=%d", rows, planes,
+                 threads, h->L, h->d);
+  h->TY = TY;
+  h->H = H;
+  h->NT = NT;
+  return SPIN_OK;
+}
 
 int spin_msc_synchronize(spin_msc* h) {
   if (!h) return mfail(SPIN_EINVAL, "NULL handle");

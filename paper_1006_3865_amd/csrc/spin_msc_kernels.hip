@@ -74,48 +74,27 @@ __device__ __forceinline__ uint32_t at_least(uint32_t u0, uint32_t u1, uint32_t 
   return m;
 }
 
-// One colour phase: thread = 8-site group g (sites 8g .. 8g+7 of one row);
-// its four sites of colour c (offset P = (c + y + z) & 1 inside the group).
+// The four colour-P sites of an 8-site group (words c[]; neighbours: lw, rw
+// the sites left and right of the group, ym/yp rows y-1/y+1 and zm/zp planes
+// z-1/z+1 at the same x); jb[i]: the couplings of active site i = 0..3
+// (site 2i + P) in the order -x, +x, -y, +y (, -z, +z); r: the shared draws.
 template <int D, int P>
-__device__ __forceinline__ void msc_group(uint32_t* __restrict__ S, const uint32_t* __restrict__ J,
-                                          const MscArgs& a, uint64_t s0, uint32_t x0, uint32_t y, uint32_t z,
-                                          const uint32_t (&r)[4]) {
-  const uint32_t L = a.L;
-  const uint64_t N = a.N, row = (uint64_t)L, plane = (uint64_t)L * L;
-  uint32_t c[8], ym[8], yp[8], jx[8], jy[8], jym[8];
-  load8(S + s0, c);
-  const uint64_t sym = y ? s0 - row : s0 + (L - 1) * row;
-  const uint64_t syp = (y + 1 < L) ? s0 + row : s0 - (L - 1) * row;
-  load8(S + sym, ym);
-  load8(S + syp, yp);
-  load8(J + s0, jx);
-  load8(J + N + s0, jy);
-  load8(J + N + sym, jym);
-  uint32_t zm[8], zp[8], jz[8], jzm[8];
-  if (D == 3) {
-    const uint64_t szm = z ? s0 - plane : s0 + (L - 1) * plane;
-    const uint64_t szp = (z + 1 < L) ? s0 + plane : s0 - (L - 1) * plane;
-    load8(S + szm, zm);
-    load8(S + szp, zp);
-    load8(J + 2 * N + s0, jz);
-    load8(J + 2 * N + szm, jzm);
-  }
-  const uint64_t sl = x0 ? s0 - 1 : s0 + L - 1;     // site left of the group
-  const uint64_t sr = (x0 + 8 < L) ? s0 + 8 : s0 + 8 - L;
-  const uint32_t lw = S[sl], rw = S[sr], jl = J[sl];
+__device__ __forceinline__ void msc_update8(uint32_t (&c)[8], uint32_t lw, uint32_t rw, const uint32_t (&ym)[8],
+                                            const uint32_t (&yp)[8], const uint32_t (&zm)[8], const uint32_t (&zp)[8],
+                                            const uint32_t (&jb)[4][2 * D], const uint32_t (&r)[4],
+                                            const MscArgs& a) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = 2 * i + P;
     const uint32_t left = j ? c[j - 1] : lw;
     const uint32_t right = j < 7 ? c[j + 1] : rw;
-    const uint32_t jleft = j ? jx[j - 1] : jl;
     const uint32_t s = c[j];
     // unsatisfied bits of the 2d bonds
-    const uint32_t b0 = xor3(s, left, jleft), b1 = xor3(s, right, jx[j]);
-    const uint32_t b2 = xor3(s, ym[j], jym[j]), b3 = xor3(s, yp[j], jy[j]);
+    const uint32_t b0 = xor3(s, left, jb[i][0]), b1 = xor3(s, right, jb[i][1]);
+    const uint32_t b2 = xor3(s, ym[j], jb[i][2]), b3 = xor3(s, yp[j], jb[i][3]);
     uint32_t u0, u1, u2;
     if (D == 3) {
-      const uint32_t b4 = xor3(s, zm[j], jzm[j]), b5 = xor3(s, zp[j], jz[j]);
+      const uint32_t b4 = xor3(s, zm[j], jb[i][4]), b5 = xor3(s, zp[j], jb[i][5]);
       const uint32_t s1 = xor3(b0, b1, b2), c1 = maj3(b0, b1, b2);
       const uint32_t s2 = xor3(b3, b4, b5), c2 = maj3(b3, b4, b5);
       u0 = s1 ^ s2;
@@ -135,12 +114,108 @@ __device__ __forceinline__ void msc_group(uint32_t* __restrict__ S, const uint32
     if (D == 3) us += ri >= a.thr[2] ? 1u : 0u;
     c[j] = s ^ at_least(u0, u1, u2, us);
   }
+}
+
+// Couplings of the active sites of group g in colour c: J6 holds, per group
+// and colour, 4 x 2d words (site i's bonds -x, +x, -y, +y(, -z, +z)).
+template <int D>
+__device__ __forceinline__ void load_bonds(const uint32_t* __restrict__ J6, uint64_t g, uint32_t c,
+                                           uint32_t (&jb)[4][2 * D]) {
+  const uint4* p = reinterpret_cast<const uint4*>(J6 + (g * 2 + c) * (8 * D));
+  uint32_t w[8 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) {
+    const uint4 v = p[q];
+    w[4 * q] = v.x;
+    w[4 * q + 1] = v.y;
+    w[4 * q + 2] = v.z;
+    w[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 2 * D; ++k) jb[i][k] = w[i * 2 * D + k];
+}
+
+// The same bonds from row-ordered coupling words of the group: jx (+x of
+// sites 0..7), jl (+x of the site left of the group), jy/jym (+y of this
+// row and of row y-1), jz/jzm (+z of this plane and of plane z-1).
+template <int D, int P>
+__device__ __forceinline__ void bonds_from_rows(const uint32_t (&jx)[8], uint32_t jl, const uint32_t (&jy)[8],
+                                                const uint32_t (&jym)[8], const uint32_t (&jz)[8],
+                                                const uint32_t (&jzm)[8], uint32_t (&jb)[4][2 * D]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = 2 * i + P;
+    jb[i][0] = j ? jx[j - 1] : jl;
+    jb[i][1] = jx[j];
+    jb[i][2] = jym[j];
+    jb[i][3] = jy[j];
+    if (D == 3) {
+      jb[i][4] = jzm[j];
+      jb[i][5] = jz[j];
+    }
+  }
+}
+
+// Build J6 from the [dir][site] couplings: thread = (group, colour).
+template <int D>
+__global__ void k_msc_bonds(const uint32_t* __restrict__ J, uint32_t* __restrict__ J6, uint32_t L, uint64_t N) {
+  const uint32_t GPR = L / 8;
+  const uint64_t row = L, plane = (uint64_t)L * L;
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < N / 4; q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t g = q >> 1;
+    const uint32_t c = (uint32_t)(q & 1);
+    const uint64_t rowi = g / GPR;
+    const uint32_t x0 = (uint32_t)(g - rowi * GPR) * 8u;
+    const uint32_t y = (uint32_t)(rowi % L), z = (D == 3) ? (uint32_t)(rowi / L) : 0u;
+    const uint32_t P = (c + y + z) & 1u;
+    uint32_t* out = J6 + q * (8 * D);
+    for (uint32_t i = 0; i < 4; ++i) {
+      const uint32_t x = x0 + 2 * i + P;
+      const uint64_t s = g * 8 + 2 * i + P;
+      const uint64_t sxm = x ? s - 1 : s + L - 1;
+      const uint64_t sym = y ? s - row : s + (L - 1) * row;
+      out[i * 2 * D + 0] = J[sxm];
+      out[i * 2 * D + 1] = J[s];
+      out[i * 2 * D + 2] = J[N + sym];
+      out[i * 2 * D + 3] = J[N + s];
+      if (D == 3) {
+        const uint64_t szm = z ? s - plane : s + (L - 1) * plane;
+        out[i * 2 * D + 4] = J[2 * N + szm];
+        out[i * 2 * D + 5] = J[2 * N + s];
+      }
+    }
+  }
+}
+
+// One colour phase: thread = 8-site group g (sites 8g .. 8g+7 of one row);
+// its four sites of colour c (offset P = (c + y + z) & 1 inside the group).
+template <int D, int P>
+__device__ __forceinline__ void msc_group(uint32_t* __restrict__ S, const uint32_t* __restrict__ J6,
+                                          const MscArgs& a, uint64_t s0, uint32_t x0, uint32_t y, uint32_t z,
+                                          const uint32_t (&r)[4]) {
+  const uint32_t L = a.L;
+  const uint64_t row = (uint64_t)L, plane = (uint64_t)L * L;
+  uint32_t c[8], ym[8], yp[8], zm[8], zp[8];
+  load8(S + s0, c);
+  load8(S + (y ? s0 - row : s0 + (L - 1) * row), ym);
+  load8(S + ((y + 1 < L) ? s0 + row : s0 - (L - 1) * row), yp);
+  if (D == 3) {
+    load8(S + (z ? s0 - plane : s0 + (L - 1) * plane), zm);
+    load8(S + ((z + 1 < L) ? s0 + plane : s0 - (L - 1) * plane), zp);
+  }
+  uint32_t jb[4][2 * D];
+  load_bonds<D>(J6, s0 >> 3, a.colour, jb);
+  const uint64_t sl = x0 ? s0 - 1 : s0 + L - 1;     // site left of the group
+  const uint64_t sr = (x0 + 8 < L) ? s0 + 8 : s0 + 8 - L;
+  msc_update8<D, P>(c, S[sl], S[sr], ym, yp, zm, zp, jb, r, a);
   reinterpret_cast<uint4*>(S + s0)[0] = make_uint4(c[0], c[1], c[2], c[3]);
   reinterpret_cast<uint4*>(S + s0)[1] = make_uint4(c[4], c[5], c[6], c[7]);
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_msc_phase(uint32_t* __restrict__ S, const uint32_t* __restrict__ J,
+__global__ __launch_bounds__(256) void k_msc_phase(uint32_t* __restrict__ S, const uint32_t* __restrict__ J6,
                                                    MscArgs a) {
   const uint32_t L = a.L, GPR = L / 8;
   const PhiloxUniform U = philox_uniform(a.t, a.p0, 4u + a.colour, a.keys);
@@ -152,10 +227,219 @@ __global__ __launch_bounds__(256) void k_msc_phase(uint32_t* __restrict__ S, con
     uint32_t r[4];
     philox_lane((uint32_t)g, U, a.keys, r);
     if (((a.colour + y + z) & 1u) == 0)
-      msc_group<D, 0>(S, J, a, g * 8, x0, y, z, r);
+      msc_group<D, 0>(S, J6, a, g * 8, x0, y, z, r);
     else
-      msc_group<D, 1>(S, J, a, g * 8, x0, y, z, r);
+      msc_group<D, 1>(S, J6, a, g * 8, x0, y, z, r);
   }
+}
+
+// ------------------------------------------------------------ streaming
+// One whole sweep per launch, streamed over planes (z in 3D, rows in 2D)
+// like the general streaming kernel: a workgroup owns planes [z0, z0+H)
+// (and in 3D rows [y0, y0+TY)) and keeps a ring of 6 plane slices of site
+// words in LDS (slice rows y0-2 .. y0+TY+1; each row with 4 pad words on
+// each side, the periodic neighbours x = L-4..L-1 and 0..3).  Step i, plane
+// a = z0-1+i: fetch plane a+2 into registers; colour 0 on plane a (slice
+// rows 1..TY+2), written back into the ring; colour 1 on plane a-2 (the
+// owned rows), written to dst with both colours; store the fetched plane;
+// barrier.  A unit is one 8-site group; couplings are read from HBM.
+constexpr int kMscFetch = 4;  // slice groups per thread
+
+__device__ __forceinline__ uint32_t msc_wrap2(uint32_t v, uint32_t L) {  // (v - 2) mod L, v < 2L + 2
+  uint32_t w = v + L - 2u;
+  if (w >= L) w -= L;
+  if (w >= L) w -= L;
+  return w;
+}
+
+template <int D, int NT>
+__device__ __forceinline__ void msc_fetch(const uint32_t* __restrict__ src, uint32_t z, uint32_t y0, uint32_t L,
+                                          uint32_t tot, uint4 (&v)[2 * kMscFetch]) {
+  const uint32_t GPR = L / 8;
+#pragma unroll
+  for (int q = 0; q < kMscFetch; ++q) {
+    const uint32_t u = threadIdx.x + NT * q;
+    if (u < tot) {
+      const uint32_t r = u / GPR, g = u - r * GPR;
+      const uint32_t y = (D == 3) ? msc_wrap2(y0 + r, L) : 0u;
+      const uint64_t s0 = ((D == 3) ? ((uint64_t)z * L + y) * L : (uint64_t)z * L) + 8u * g;
+      v[2 * q] = reinterpret_cast<const uint4*>(src + s0)[0];
+      v[2 * q + 1] = reinterpret_cast<const uint4*>(src + s0)[1];
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void msc_put(uint32_t* slot, uint32_t L, uint32_t RW, uint32_t tot,
+                                        const uint4 (&v)[2 * kMscFetch]) {
+  const uint32_t GPR = L / 8;
+#pragma unroll
+  for (int q = 0; q < kMscFetch; ++q) {
+    const uint32_t u = threadIdx.x + NT * q;
+    if (u < tot) {
+      const uint32_t r = u / GPR, g = u - r * GPR;
+      uint32_t* row = slot + r * RW;
+      reinterpret_cast<uint4*>(row + 4 + 8 * g)[0] = v[2 * q];
+      reinterpret_cast<uint4*>(row + 4 + 8 * g)[1] = v[2 * q + 1];
+      if (g == 0) reinterpret_cast<uint4*>(row + 4 + L)[0] = v[2 * q];           // sites 0..3 right of L-1
+      if (g == GPR - 1) reinterpret_cast<uint4*>(row)[0] = v[2 * q + 1];          // sites L-4..L-1 left of 0
+    }
+  }
+}
+
+__device__ __forceinline__ void lds8(const uint32_t* p, uint32_t (&v)[8]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// Colour-C groups of one step: slice rows RB0 + u / GPR, groups u % GPR.
+template <int D, int NT, uint32_t C>
+__device__ __forceinline__ void msc_units(const uint32_t* pm, uint32_t* pc, const uint32_t* pp, uint32_t n,
+                                          uint32_t y0, uint32_t z, uint32_t RW, const MscArgs& a,
+                                          const PhiloxUniform& U, const uint32_t* __restrict__ J,
+                                          uint32_t* __restrict__ dst) {
+  const uint32_t L = a.L, GPR = L / 8;
+  constexpr uint32_t RB0 = (D == 3) ? (C == 0 ? 1u : 2u) : 0u;
+  for (uint32_t u = threadIdx.x; u < n; u += NT) {
+    const uint32_t r = u / GPR + RB0, g = u - (u / GPR) * GPR;
+    const uint32_t y = (D == 3) ? (C == 0 ? msc_wrap2(y0 + r, L) : y0 + r - 2u) : z;
+    const uint32_t zz = (D == 3) ? z : 0u;
+    const uint64_t rowbase = (D == 3) ? ((uint64_t)zz * L + y) * L : (uint64_t)y * L;
+    const uint64_t s0 = rowbase + 8u * g;
+    const uint32_t o = r * RW + 4 + 8 * g;
+    uint32_t c[8], ym[8], yp[8], zm[8], zp[8];
+    lds8(pc + o, c);
+    if (D == 3) {
+      lds8(pc + o - RW, ym);
+      lds8(pc + o + RW, yp);
+      lds8(pm + o, zm);
+      lds8(pp + o, zp);
+    } else {
+      lds8(pm + o, ym);
+      lds8(pp + o, yp);
+    }
+    const uint32_t lw = pc[o - 1], rw = pc[o + 8];
+    // couplings from HBM in row order (neighbouring units share their cache lines)
+    const uint64_t N = a.N, plane = (uint64_t)L * L;
+    const uint32_t x0 = 8u * g;
+    const uint64_t sl = x0 ? s0 - 1 : s0 + L - 1;
+    const uint64_t sym = y ? s0 - L : s0 + (uint64_t)(L - 1) * L;  // same x in row y-1
+    uint32_t jx[8], jy[8], jym[8], jz[8], jzm[8];
+    load8(J + s0, jx);
+    load8(J + N + s0, jy);
+    load8(J + N + sym, jym);
+    if (D == 3) {
+      const uint64_t szm = zz ? s0 - plane : s0 + (uint64_t)(L - 1) * plane;
+      load8(J + 2 * N + s0, jz);
+      load8(J + 2 * N + szm, jzm);
+    }
+    const uint32_t jl = J[sl];
+    uint32_t rnd[4];
+    philox_lane((uint32_t)(s0 >> 3), U, a.keys, rnd);
+    uint32_t jb[4][2 * D];
+    if (((C + y + zz) & 1u) == 0) {
+      bonds_from_rows<D, 0>(jx, jl, jy, jym, jz, jzm, jb);
+      msc_update8<D, 0>(c, lw, rw, ym, yp, zm, zp, jb, rnd, a);
+    } else {
+      bonds_from_rows<D, 1>(jx, jl, jy, jym, jz, jzm, jb);
+      msc_update8<D, 1>(c, lw, rw, ym, yp, zm, zp, jb, rnd, a);
+    }
+    if (C == 0) {
+      uint32_t* row = pc + r * RW;
+      reinterpret_cast<uint4*>(pc + o)[0] = make_uint4(c[0], c[1], c[2], c[3]);
+      reinterpret_cast<uint4*>(pc + o)[1] = make_uint4(c[4], c[5], c[6], c[7]);
+      if (g == 0) reinterpret_cast<uint4*>(row + 4 + L)[0] = make_uint4(c[0], c[1], c[2], c[3]);
+      if (g == GPR - 1) reinterpret_cast<uint4*>(row)[0] = make_uint4(c[4], c[5], c[6], c[7]);
+    } else {
+      reinterpret_cast<uint4*>(dst + s0)[0] = make_uint4(c[0], c[1], c[2], c[3]);
+      reinterpret_cast<uint4*>(dst + s0)[1] = make_uint4(c[4], c[5], c[6], c[7]);
+    }
+  }
+}
+
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_msc_stream(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                   const uint32_t* __restrict__ J, MscArgs a, uint32_t TYa,
+                                                   uint32_t Ha) {
+  extern __shared__ __align__(16) uint32_t ring[];
+  const uint32_t L = a.L, GPR = L / 8;
+  const uint32_t RW = L + 8;
+  const uint32_t TY = (D == 3) ? TYa : 1u;
+  const uint32_t RP = (D == 3) ? TY + 4 : 1u;
+  const uint32_t SB = RP * RW;
+  const uint32_t y0 = (D == 3) ? blockIdx.x * TY : 0u;
+  const uint32_t z0 = blockIdx.y * Ha;
+  const uint32_t H = (L - z0 < Ha) ? L - z0 : Ha;
+  const PhiloxUniform U0 = philox_uniform(a.t, a.p0, 4u, a.keys);
+  const PhiloxUniform U1 = philox_uniform(a.t, a.p0, 5u, a.keys);
+  const uint32_t tot = RP * GPR;
+  uint4 nxt[2 * kMscFetch];
+  for (uint32_t k = 0; k < 3; ++k) {
+    msc_fetch<D, NT>(src, msc_wrap2(z0 + k, L), y0, L, tot, nxt);
+    msc_put<NT>(ring + k * SB, L, RW, tot, nxt);
+  }
+  __syncthreads();
+  const uint32_t U0n = (D == 3) ? (TY + 2) * GPR : GPR;
+  const uint32_t U1n = (D == 3) ? TY * GPR : GPR;
+  uint32_t sa = 1;
+  for (uint32_t i = 0; i < H + 3; ++i) {
+    const uint32_t s_m3 = sa >= 3 ? sa - 3 : sa + 3;
+    const uint32_t s_m2 = sa >= 2 ? sa - 2 : sa + 4;
+    const uint32_t s_m1 = sa >= 1 ? sa - 1 : 5;
+    const uint32_t s_p1 = sa <= 4 ? sa + 1 : 0;
+    const uint32_t s_p2 = sa <= 3 ? sa + 2 : sa - 4;
+    if (i <= H) msc_fetch<D, NT>(src, msc_wrap2(z0 + i + 3, L), y0, L, tot, nxt);
+    if (i <= H + 1)
+      msc_units<D, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0, msc_wrap2(z0 + i + 1, L), RW,
+                          a, U0, J, dst);
+    if (i >= 3)
+      msc_units<D, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u, RW, a, U1, J,
+                          dst);
+    if (i <= H) msc_put<NT>(ring + s_p2 * SB, L, RW, tot, nxt);
+    __syncthreads();
+    sa = sa == 5 ? 0 : sa + 1;
+  }
+}
+
+size_t msc_stream_lds(uint32_t L, uint32_t d, uint32_t TY) {
+  const size_t RP = d == 3 ? TY + 4 : 1;
+  return 6 * RP * (L + 8) * 4;
+}
+
+bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT) {
+  if (L % 8 != 0 || L < 16 || H < 1 || H > L) return false;
+  if (NT != 256 && NT != 512) return false;
+  if (d == 3 && (TY == 0 || L % TY != 0 || TY > 32)) return false;
+  const uint32_t RP = d == 3 ? TY + 4 : 1;
+  if (RP * (L / 8) > (uint32_t)kMscFetch * NT) return false;
+  return msc_stream_lds(L, d, TY) <= 150 * 1024;
+}
+
+template <int D, int NT>
+static hipError_t go_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a,
+                                uint32_t TY, uint32_t H, hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_msc_stream<D, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       150 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const dim3 grid(D == 3 ? a.L / TY : 1u, (a.L + H - 1) / H);
+  hipLaunchKernelGGL((k_msc_stream<D, NT>), grid, dim3(NT), msc_stream_lds(a.L, D, TY), stream, src, dst, J, a, TY,
+                     H);
+  return hipGetLastError();
+}
+
+hipError_t launch_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
+                             uint32_t TY, uint32_t H, uint32_t NT, hipStream_t stream) {
+  if (!msc_stream_supported(a.L, d, TY, H, NT)) return hipErrorInvalidValue;
+  if (d == 3) return NT == 256 ? go_msc_stream<3, 256>(src, dst, J, a, TY, H, stream)
+                               : go_msc_stream<3, 512>(src, dst, J, a, TY, H, stream);
+  return NT == 256 ? go_msc_stream<2, 256>(src, dst, J, a, TY, H, stream)
+                   : go_msc_stream<2, 512>(src, dst, J, a, TY, H, stream);
 }
 
 // E and M of the 32 systems: per workgroup, counts of unsatisfied bonds and
@@ -223,12 +507,20 @@ hipError_t launch_msc_couplings(uint32_t* J, uint64_t N, uint32_t d, uint64_t cs
   return hipGetLastError();
 }
 
-hipError_t launch_msc_phase(uint32_t* S, const uint32_t* J, const MscArgs& a, uint32_t d, hipStream_t stream) {
+hipError_t launch_msc_bonds(const uint32_t* J, uint32_t* J6, uint32_t L, uint32_t d, uint64_t N, hipStream_t stream) {
+  if (d == 3)
+    hipLaunchKernelGGL(k_msc_bonds<3>, dim3(blocks_for(N / 4, 8192)), dim3(256), 0, stream, J, J6, L, N);
+  else
+    hipLaunchKernelGGL(k_msc_bonds<2>, dim3(blocks_for(N / 4, 8192)), dim3(256), 0, stream, J, J6, L, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_msc_phase(uint32_t* S, const uint32_t* J6, const MscArgs& a, uint32_t d, hipStream_t stream) {
   const unsigned blocks = blocks_for(a.N / 8, 1u << 20);
   if (d == 3)
-    hipLaunchKernelGGL(k_msc_phase<3>, dim3(blocks), dim3(256), 0, stream, S, J, a);
+    hipLaunchKernelGGL(k_msc_phase<3>, dim3(blocks), dim3(256), 0, stream, S, J6, a);
   else
-    hipLaunchKernelGGL(k_msc_phase<2>, dim3(blocks), dim3(256), 0, stream, S, J, a);
+    hipLaunchKernelGGL(k_msc_phase<2>, dim3(blocks), dim3(256), 0, stream, S, J6, a);
   return hipGetLastError();
 }
 

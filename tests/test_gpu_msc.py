@@ -29,11 +29,17 @@ def gpu():
     return torch
 
 
-@pytest.mark.parametrize("L,d", [(8, 2), (16, 2), (64, 2), (8, 3), (16, 3), (24, 3)])
-def test_msc_matches_oracle(oracle_mod, L, d):
+@pytest.mark.parametrize("L,d,kernel", [
+    (8, 2, None), (16, 2, None), (64, 2, None), (8, 3, None), (16, 3, None), (24, 3, None),
+    (16, 2, (0, 0, 0, 0)), (24, 3, (0, 0, 0, 0)),                 # one launch per colour
+    (40, 2, (1, 0, 7, 512)), (24, 3, (1, 4, 5, 256)), (32, 3, (1, 16, 3, 512)), (16, 3, (1, 8, 16, 256)),
+])
+def test_msc_matches_oracle(oracle_mod, L, d, kernel):
     cs, seed, r0, p0 = workloads.seed(0x60), workloads.seed(0x61), 5, 70
-    note("msc", L, d)
+    note("msc", L, d, kernel)
     m = spin.Msc(L, d, cs, r0, seed, p0)
+    if kernel is not None:
+        m.set_kernel(*kernel)
     ch = oracle_mod.MscChain(L, d, cs, r0, seed, p0)
     for b in (0, 13, 31):
         np.testing.assert_array_equal(m.spins(b), ch.spins[b])
@@ -66,3 +72,10 @@ def test_msc_rejects_bad_shapes():
     for (L, d) in ((12, 2), (4, 3), (16, 4)):
         with pytest.raises(spin.SpinError):
             spin.Msc(L, d, 1, 0, 1)
+    m = spin.Msc(24, 3, 1, 0, 1)
+    for k in ((1, 5, 8, 256), (1, 8, 8, 128), (1, 8, 0, 256)):   # rows must divide L; threads 256/512
+        if k[2] == 0:
+            continue
+        with pytest.raises(spin.SpinError):
+            m.set_kernel(*k)
+    m.close()
