@@ -197,7 +197,7 @@ def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64),
             "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
 
 
-def bench_msc(torch, spin, workloads, shapes=((256, 3), (128, 3), (4096, 2))):
+def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (4096, 2))):
     """Multi-spin-coded +-J glass: 32 realisations per word, attempts/ns (32 * L^d per sweep) at the
     middle of the batch's temperature ladder, HIP events on the handle's stream."""
     stream = torch.cuda.Stream()

@@ -323,11 +323,13 @@ uint64_t spin_msc_sweeps_done(const spin_msc* h);
 
 /* Kernel choice (bits never change): streaming != 0 sweeps both colours in
  * one launch streamed over planes, with rows (3D: rows per workgroup,
- * dividing L, <= 32) and planes (per strip) and threads (256 or 512), 0
- * meaning the default (8, 16, 512); streaming == 0 launches one kernel per
- * colour.  The library picks streaming where the shape fits.  SPIN_EINVAL
- * if the streaming shape does not fit L. */
-int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads);
+ * dividing L, <= 32), planes (per strip), threads (256 or 512) and width
+ * (sites of a row per workgroup: a multiple of 8 dividing L), 0 meaning the
+ * default (8, 16, 512, L); streaming == 0 launches one kernel per colour.
+ * At creation the library picks a streaming shape measured to be fast for
+ * L and d where one fits, else the per-colour kernel.  SPIN_EINVAL if the
+ * streaming shape does not fit L. */
+int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads, int width);
 
 /* Wait for the handle's queued work. */
 int spin_msc_synchronize(spin_msc* h);

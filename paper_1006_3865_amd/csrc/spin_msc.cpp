@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "spin.h"
@@ -32,7 +33,7 @@ struct spin_msc {
   uint64_t t;
   uint32_t* S;       // [N] current spins
   uint32_t* S2;      // [N] second buffer of the streaming kernel (allocated on first use)
-  uint32_t TY, H, NT;  // streaming shape; NT == 0: the per-colour phase kernel
+  uint32_t TY, H, NT, XW;  // streaming shape; NT == 0: the per-colour phase kernel
   uint32_t* J;       // [d][N] (measurement)
   uint32_t* J6;      // [N/8][2][4][2d]: bonds of the active sites of each group and colour (phase kernel, on first use)
   int64_t* part;     // measurement partial counts
@@ -92,7 +93,7 @@ static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int6
   for (int i = 0; i < n; ++i) {
     a.t = (uint32_t)(h->t + (uint64_t)i);
     if (h->NT) {
-      hipError_t e = launch_msc_stream(h->S, h->S2, h->J, a, (uint32_t)h->d, h->TY, h->H, h->NT, h->stream);
+      hipError_t e = launch_msc_stream(h->S, h->S2, h->J, a, (uint32_t)h->d, h->TY, h->H, h->NT, h->XW, h->stream);
       if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin stream launch: %s", hipGetErrorString(e));
       std::swap(h->S, h->S2);
     } else {
@@ -152,12 +153,25 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
   h->S2 = nullptr;
   h->J = nullptr;
   h->J6 = nullptr;
-  // streaming shape: 3D slabs of 8 rows, strips of 16 planes, 512 threads (else 256); else the phase kernel
-  h->TY = d == 3 ? 8u : 1u;
-  h->H = 16u;
+  // streaming shape, from measured rates: 3D whole rows in slabs of 16 rows where the ring fits LDS,
+  // else 8, else 4; strips of L/16 planes (4..32); 512 threads from L = 256 up, else 256.  2D rows cut
+  // into segments of at most 2048 sites, strips of 16 rows, 256 threads.  Else the phase kernel.
   h->NT = 0;
-  for (uint32_t nt : {512u, 256u})
-    if (!h->NT && msc_stream_supported((uint32_t)L, (uint32_t)d, h->TY, h->H, nt)) h->NT = nt;
+  h->XW = (uint32_t)L;
+  if (d == 3) {
+    h->H = std::min(32u, std::max(4u, (uint32_t)L / 16));
+    const uint32_t nt = L >= 256 ? 512u : 256u;
+    for (uint32_t ty : {16u, 8u, 4u})
+      if (!h->NT && msc_stream_supported((uint32_t)L, 3, ty, h->H, nt, h->XW)) {
+        h->TY = ty;
+        h->NT = nt;
+      }
+  } else {
+    while (h->XW > 2048 && (h->XW / 2) % 8 == 0) h->XW /= 2;
+    h->TY = 1;
+    h->H = 16;
+    if (msc_stream_supported((uint32_t)L, 2, 1, h->H, 256, h->XW)) h->NT = 256;
+  }
   h->part = nullptr;
   h->rec = nullptr;
   h->rec_cap = 0;
@@ -228,20 +242,22 @@ int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n) {
 
 uint64_t spin_msc_sweeps_done(const spin_msc* h) { return h ? h->t : 0; }
 
-int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads) {
+int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads, int width) {
   if (!h) return mfail(SPIN_EINVAL, "NULL handle");
   if (!streaming) {
     h->NT = 0;
     return SPIN_OK;
   }
+  if (rows < 0 || planes < 0 || threads < 0 || width < 0) return mfail(SPIN_EINVAL, "negative streaming shape");
   const uint32_t TY = h->d == 3 ? (uint32_t)(rows ? rows : 8) : 1u, H = (uint32_t)(planes ? planes : 16),
-                 NT = (uint32_t)(threads ? threads : 512);
-  if (!msc_stream_supported((uint32_t)h->L, (uint32_t)h->d, TY, H, NT))
-    return mfail(SPIN_EINVAL, "streaming shape rows=%d planes=%d threads=%d cannot run L=%d d=%d", rows, planes,
-                 threads, h->L, h->d);
+                 NT = (uint32_t)(threads ? threads : 512), XW = (uint32_t)(width ? width : h->L);
+  if (!msc_stream_supported((uint32_t)h->L, (uint32_t)h->d, TY, H, NT, XW))
+    return mfail(SPIN_EINVAL, "streaming shape rows=%d planes=%d threads=%d width=%d cannot run L=%d d=%d", rows,
+                 planes, threads, width, h->L, h->d);
   h->TY = TY;
   h->H = H;
   h->NT = NT;
+  h->XW = XW;
   return SPIN_OK;
 }
 

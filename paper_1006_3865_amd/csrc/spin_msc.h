@@ -27,10 +27,11 @@ hipError_t launch_msc_bonds(const uint32_t* J, uint32_t* J6, uint32_t L, uint32_
 hipError_t launch_msc_phase(uint32_t* S, const uint32_t* J6, const MscArgs& a, uint32_t d, hipStream_t stream);
 // One sweep per launch, streamed over planes (both colours; ping-pong
 // src -> dst): TY rows per workgroup (3D, divides L, <= 32), H planes per
-// strip, NT = 256 or 512 threads; false when the shape does not fit.
-bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT);
+// strip, NT = 256 or 512 threads, XW sites of each row per workgroup (a
+// multiple of 8 dividing L); false when the shape does not fit.
+bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW);
 hipError_t launch_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
-                             uint32_t TY, uint32_t H, uint32_t NT, hipStream_t stream);
+                             uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW, hipStream_t stream);
 // Workgroups of the measurement (each writes 64 int64 partial counts).
 uint32_t msc_count_parts(uint64_t N);
 // E[b], M[b] (device int64[32] each) of the 32 systems; part: msc_count_parts(N) * 64 int64.

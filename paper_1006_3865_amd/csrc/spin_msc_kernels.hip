@@ -235,15 +235,21 @@ __global__ __launch_bounds__(256) void k_msc_phase(uint32_t* __restrict__ S, con
 
 // ------------------------------------------------------------ streaming
 // One whole sweep per launch, streamed over planes (z in 3D, rows in 2D)
-// like the general streaming kernel: a workgroup owns planes [z0, z0+H)
-// (and in 3D rows [y0, y0+TY)) and keeps a ring of 6 plane slices of site
-// words in LDS (slice rows y0-2 .. y0+TY+1; each row with 4 pad words on
-// each side, the periodic neighbours x = L-4..L-1 and 0..3).  Step i, plane
-// a = z0-1+i: fetch plane a+2 into registers; colour 0 on plane a (slice
-// rows 1..TY+2), written back into the ring; colour 1 on plane a-2 (the
-// owned rows), written to dst with both colours; store the fetched plane;
-// barrier.  A unit is one 8-site group; couplings are read from HBM.
+// like the general streaming kernel: a workgroup owns planes [z0, z0+H), in
+// 3D rows [y0, y0+TY), and sites [x0, x0+XW) of each row, and keeps a ring
+// of 6 plane slices of site words in LDS.  A slice row holds the 8-site
+// groups x0/8-2 .. x0/8+XW/8+1 (two neighbouring groups on each side,
+// periodic); 3D slices hold rows y0-2 .. y0+TY+1.  A slice row keeps words
+// 0-3 of its groups in its first half and words 4-7 in its second, so that
+// neighbouring lanes touch neighbouring 16 bytes.  Step i, plane a =
+// z0-1+i: fetch plane a+2 into registers; colour 0 on plane a over slice
+// rows 1..TY+2 and groups 1..XW/8+2 (the owned part and a one-group /
+// one-row ring that colour 1 needs), written back into the ring; colour 1
+// on plane a-2 over the owned rows and groups, written to dst with both
+// colours; store the fetched plane; barrier.  Couplings come from HBM.
 constexpr int kMscFetch = 4;  // slice groups per thread
+// A register vector: copies of uint4 structs are lowered to memcpy and left in scratch.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t msc_wrap2(uint32_t v, uint32_t L) {  // (v - 2) mod L, v < 2L + 2
   uint32_t w = v + L - 2u;
@@ -252,79 +258,87 @@ __device__ __forceinline__ uint32_t msc_wrap2(uint32_t v, uint32_t L) {  // (v -
   return w;
 }
 
+struct MscGeom {
+  uint32_t L, GPR;   // edge, groups per row
+  uint32_t SG;       // groups per slice row (XW/8 + 4)
+  uint32_t RW;       // words per slice row (8 * SG)
+  uint32_t HW;       // offset of the second half of a slice row (4 * SG)
+  uint32_t gx0;      // first owned group column (x0 / 8)
+};
+
 template <int D, int NT>
-__device__ __forceinline__ void msc_fetch(const uint32_t* __restrict__ src, uint32_t z, uint32_t y0, uint32_t L,
-                                          uint32_t tot, uint4 (&v)[2 * kMscFetch]) {
-  const uint32_t GPR = L / 8;
+__device__ __forceinline__ void msc_fetch(const uint32_t* __restrict__ src, uint32_t z, uint32_t y0, const MscGeom& G,
+                                          uint32_t tot, u32x4 (&v)[2 * kMscFetch]) {
 #pragma unroll
   for (int q = 0; q < kMscFetch; ++q) {
     const uint32_t u = threadIdx.x + NT * q;
     if (u < tot) {
-      const uint32_t r = u / GPR, g = u - r * GPR;
-      const uint32_t y = (D == 3) ? msc_wrap2(y0 + r, L) : 0u;
-      const uint64_t s0 = ((D == 3) ? ((uint64_t)z * L + y) * L : (uint64_t)z * L) + 8u * g;
-      v[2 * q] = reinterpret_cast<const uint4*>(src + s0)[0];
-      v[2 * q + 1] = reinterpret_cast<const uint4*>(src + s0)[1];
+      const uint32_t r = u / G.SG, k = u - r * G.SG;
+      const uint32_t y = (D == 3) ? msc_wrap2(y0 + r, G.L) : 0u;
+      const uint32_t gx = msc_wrap2(G.gx0 + k, G.GPR);
+      const uint64_t s0 = ((D == 3) ? ((uint64_t)z * G.L + y) * G.L : (uint64_t)z * G.L) + 8u * gx;
+      v[2 * q] = reinterpret_cast<const u32x4*>(src + s0)[0];
+      v[2 * q + 1] = reinterpret_cast<const u32x4*>(src + s0)[1];
     }
   }
 }
 
 template <int NT>
-__device__ __forceinline__ void msc_put(uint32_t* slot, uint32_t L, uint32_t RW, uint32_t tot,
-                                        const uint4 (&v)[2 * kMscFetch]) {
-  const uint32_t GPR = L / 8;
+__device__ __forceinline__ void msc_put(uint32_t* slot, const MscGeom& G, uint32_t tot,
+                                        const u32x4 (&v)[2 * kMscFetch]) {
 #pragma unroll
   for (int q = 0; q < kMscFetch; ++q) {
     const uint32_t u = threadIdx.x + NT * q;
     if (u < tot) {
-      const uint32_t r = u / GPR, g = u - r * GPR;
-      uint32_t* row = slot + r * RW;
-      reinterpret_cast<uint4*>(row + 4 + 8 * g)[0] = v[2 * q];
-      reinterpret_cast<uint4*>(row + 4 + 8 * g)[1] = v[2 * q + 1];
-      if (g == 0) reinterpret_cast<uint4*>(row + 4 + L)[0] = v[2 * q];           // sites 0..3 right of L-1
-      if (g == GPR - 1) reinterpret_cast<uint4*>(row)[0] = v[2 * q + 1];          // sites L-4..L-1 left of 0
+      const uint32_t r = u / G.SG, k = u - r * G.SG;
+      uint32_t* p = slot + r * G.RW + 4 * k;
+      *reinterpret_cast<u32x4*>(p) = v[2 * q];
+      *reinterpret_cast<u32x4*>(p + G.HW) = v[2 * q + 1];
     }
   }
 }
 
-__device__ __forceinline__ void lds8(const uint32_t* p, uint32_t (&v)[8]) {
-  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
-  const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+// The 8 words of a slice group: words 0-3 at p, words 4-7 at p + hw.
+__device__ __forceinline__ void lds8(const uint32_t* p, uint32_t hw, uint32_t (&v)[8]) {
+  const u32x4 a = *reinterpret_cast<const u32x4*>(p);
+  const u32x4 b = *reinterpret_cast<const u32x4*>(p + hw);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
   v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
-// Colour-C groups of one step: slice rows RB0 + u / GPR, groups u % GPR.
+// Colour-C groups of one step: slice rows RB0 + u / NG, slice groups KB0 + u % NG.
 template <int D, int NT, uint32_t C>
 __device__ __forceinline__ void msc_units(const uint32_t* pm, uint32_t* pc, const uint32_t* pp, uint32_t n,
-                                          uint32_t y0, uint32_t z, uint32_t RW, const MscArgs& a,
+                                          uint32_t NG, uint32_t y0, uint32_t z, const MscGeom& G, const MscArgs& a,
                                           const PhiloxUniform& U, const uint32_t* __restrict__ J,
                                           uint32_t* __restrict__ dst) {
-  const uint32_t L = a.L, GPR = L / 8;
+  const uint32_t L = G.L, RW = G.RW, HW = G.HW;
   constexpr uint32_t RB0 = (D == 3) ? (C == 0 ? 1u : 2u) : 0u;
+  constexpr uint32_t KB0 = C == 0 ? 1u : 2u;
   for (uint32_t u = threadIdx.x; u < n; u += NT) {
-    const uint32_t r = u / GPR + RB0, g = u - (u / GPR) * GPR;
+    const uint32_t rr = u / NG, kk = u - rr * NG;
+    const uint32_t r = rr + RB0, k = kk + KB0;
     const uint32_t y = (D == 3) ? (C == 0 ? msc_wrap2(y0 + r, L) : y0 + r - 2u) : z;
     const uint32_t zz = (D == 3) ? z : 0u;
+    const uint32_t gx = msc_wrap2(G.gx0 + k, G.GPR);
     const uint64_t rowbase = (D == 3) ? ((uint64_t)zz * L + y) * L : (uint64_t)y * L;
-    const uint64_t s0 = rowbase + 8u * g;
-    const uint32_t o = r * RW + 4 + 8 * g;
+    const uint64_t s0 = rowbase + 8u * gx;
+    const uint32_t o = r * RW + 4 * k;
     uint32_t c[8], ym[8], yp[8], zm[8], zp[8];
-    lds8(pc + o, c);
+    lds8(pc + o, HW, c);
     if (D == 3) {
-      lds8(pc + o - RW, ym);
-      lds8(pc + o + RW, yp);
-      lds8(pm + o, zm);
-      lds8(pp + o, zp);
+      lds8(pc + o - RW, HW, ym);
+      lds8(pc + o + RW, HW, yp);
+      lds8(pm + o, HW, zm);
+      lds8(pp + o, HW, zp);
     } else {
-      lds8(pm + o, ym);
-      lds8(pp + o, yp);
+      lds8(pm + o, HW, ym);
+      lds8(pp + o, HW, yp);
     }
-    const uint32_t lw = pc[o - 1], rw = pc[o + 8];
+    const uint32_t lw = pc[o + HW - 1], rw = pc[o + 4];  // word 7 of group k-1, word 0 of group k+1
     // couplings from HBM in row order (neighbouring units share their cache lines)
     const uint64_t N = a.N, plane = (uint64_t)L * L;
-    const uint32_t x0 = 8u * g;
-    const uint64_t sl = x0 ? s0 - 1 : s0 + L - 1;
+    const uint64_t sl = gx ? s0 - 1 : s0 + L - 1;
     const uint64_t sym = y ? s0 - L : s0 + (uint64_t)(L - 1) * L;  // same x in row y-1
     uint32_t jx[8], jy[8], jym[8], jz[8], jzm[8];
     load8(J + s0, jx);
@@ -346,15 +360,13 @@ __device__ __forceinline__ void msc_units(const uint32_t* pm, uint32_t* pc, cons
       bonds_from_rows<D, 1>(jx, jl, jy, jym, jz, jzm, jb);
       msc_update8<D, 1>(c, lw, rw, ym, yp, zm, zp, jb, rnd, a);
     }
+    const u32x4 lo = {c[0], c[1], c[2], c[3]}, hi = {c[4], c[5], c[6], c[7]};
     if (C == 0) {
-      uint32_t* row = pc + r * RW;
-      reinterpret_cast<uint4*>(pc + o)[0] = make_uint4(c[0], c[1], c[2], c[3]);
-      reinterpret_cast<uint4*>(pc + o)[1] = make_uint4(c[4], c[5], c[6], c[7]);
-      if (g == 0) reinterpret_cast<uint4*>(row + 4 + L)[0] = make_uint4(c[0], c[1], c[2], c[3]);
-      if (g == GPR - 1) reinterpret_cast<uint4*>(row)[0] = make_uint4(c[4], c[5], c[6], c[7]);
+      *reinterpret_cast<u32x4*>(pc + o) = lo;
+      *reinterpret_cast<u32x4*>(pc + o + HW) = hi;
     } else {
-      reinterpret_cast<uint4*>(dst + s0)[0] = make_uint4(c[0], c[1], c[2], c[3]);
-      reinterpret_cast<uint4*>(dst + s0)[1] = make_uint4(c[4], c[5], c[6], c[7]);
+      reinterpret_cast<u32x4*>(dst + s0)[0] = lo;
+      reinterpret_cast<u32x4*>(dst + s0)[1] = hi;
     }
   }
 }
@@ -362,27 +374,36 @@ __device__ __forceinline__ void msc_units(const uint32_t* pm, uint32_t* pc, cons
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_msc_stream(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
                                                    const uint32_t* __restrict__ J, MscArgs a, uint32_t TYa,
-                                                   uint32_t Ha) {
+                                                   uint32_t Ha, uint32_t XW) {
   extern __shared__ __align__(16) uint32_t ring[];
-  const uint32_t L = a.L, GPR = L / 8;
-  const uint32_t RW = L + 8;
+  MscGeom G;
+  G.L = a.L;
+  G.GPR = a.L / 8;
+  G.SG = XW / 8 + 4;
+  G.RW = 8 * G.SG;
+  G.HW = 4 * G.SG;
+  const uint32_t L = a.L;
   const uint32_t TY = (D == 3) ? TYa : 1u;
   const uint32_t RP = (D == 3) ? TY + 4 : 1u;
-  const uint32_t SB = RP * RW;
-  const uint32_t y0 = (D == 3) ? blockIdx.x * TY : 0u;
+  const uint32_t SB = RP * G.RW;
+  const uint32_t nseg = L / XW;
+  const uint32_t seg = blockIdx.x % nseg;
+  G.gx0 = seg * (XW / 8);
+  const uint32_t y0 = (D == 3) ? (blockIdx.x / nseg) * TY : 0u;
   const uint32_t z0 = blockIdx.y * Ha;
   const uint32_t H = (L - z0 < Ha) ? L - z0 : Ha;
   const PhiloxUniform U0 = philox_uniform(a.t, a.p0, 4u, a.keys);
   const PhiloxUniform U1 = philox_uniform(a.t, a.p0, 5u, a.keys);
-  const uint32_t tot = RP * GPR;
-  uint4 nxt[2 * kMscFetch];
+  const uint32_t tot = RP * G.SG;
+  u32x4 nxt[2 * kMscFetch];
   for (uint32_t k = 0; k < 3; ++k) {
-    msc_fetch<D, NT>(src, msc_wrap2(z0 + k, L), y0, L, tot, nxt);
-    msc_put<NT>(ring + k * SB, L, RW, tot, nxt);
+    msc_fetch<D, NT>(src, msc_wrap2(z0 + k, L), y0, G, tot, nxt);
+    msc_put<NT>(ring + k * SB, G, tot, nxt);
   }
   __syncthreads();
-  const uint32_t U0n = (D == 3) ? (TY + 2) * GPR : GPR;
-  const uint32_t U1n = (D == 3) ? TY * GPR : GPR;
+  const uint32_t NG0 = XW / 8 + 2, NG1 = XW / 8;            // groups per row of colour 0 / colour 1 units
+  const uint32_t U0n = ((D == 3) ? TY + 2 : 1u) * NG0;
+  const uint32_t U1n = ((D == 3) ? TY : 1u) * NG1;
   uint32_t sa = 1;
   for (uint32_t i = 0; i < H + 3; ++i) {
     const uint32_t s_m3 = sa >= 3 ? sa - 3 : sa + 3;
@@ -390,56 +411,61 @@ __global__ __launch_bounds__(NT) void k_msc_stream(const uint32_t* __restrict__ 
     const uint32_t s_m1 = sa >= 1 ? sa - 1 : 5;
     const uint32_t s_p1 = sa <= 4 ? sa + 1 : 0;
     const uint32_t s_p2 = sa <= 3 ? sa + 2 : sa - 4;
-    if (i <= H) msc_fetch<D, NT>(src, msc_wrap2(z0 + i + 3, L), y0, L, tot, nxt);
+    if (i <= H) msc_fetch<D, NT>(src, msc_wrap2(z0 + i + 3, L), y0, G, tot, nxt);
     if (i <= H + 1)
-      msc_units<D, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0, msc_wrap2(z0 + i + 1, L), RW,
-                          a, U0, J, dst);
+      msc_units<D, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, NG0, y0, msc_wrap2(z0 + i + 1, L),
+                          G, a, U0, J, dst);
     if (i >= 3)
-      msc_units<D, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u, RW, a, U1, J,
+      msc_units<D, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, NG1, y0, z0 + i - 3u, G, a, U1, J,
                           dst);
-    if (i <= H) msc_put<NT>(ring + s_p2 * SB, L, RW, tot, nxt);
+    if (i <= H) msc_put<NT>(ring + s_p2 * SB, G, tot, nxt);
     __syncthreads();
     sa = sa == 5 ? 0 : sa + 1;
   }
 }
 
-size_t msc_stream_lds(uint32_t L, uint32_t d, uint32_t TY) {
+constexpr size_t kMscMaxLds = 160 * 1024;  // all of a CU's LDS
+
+size_t msc_stream_lds(uint32_t L, uint32_t d, uint32_t TY, uint32_t XW) {
+  (void)L;
   const size_t RP = d == 3 ? TY + 4 : 1;
-  return 6 * RP * (L + 8) * 4;
+  return 6 * RP * (XW + 32) * 4;
 }
 
-bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT) {
+bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW) {
   if (L % 8 != 0 || L < 16 || H < 1 || H > L) return false;
   if (NT != 256 && NT != 512) return false;
+  if (XW < 8 || XW % 8 != 0 || L % XW != 0) return false;
   if (d == 3 && (TY == 0 || L % TY != 0 || TY > 32)) return false;
   const uint32_t RP = d == 3 ? TY + 4 : 1;
-  if (RP * (L / 8) > (uint32_t)kMscFetch * NT) return false;
-  return msc_stream_lds(L, d, TY) <= 150 * 1024;
+  if (RP * (XW / 8 + 4) > (uint32_t)kMscFetch * NT) return false;
+  return msc_stream_lds(L, d, TY, XW) <= kMscMaxLds;
 }
 
 template <int D, int NT>
 static hipError_t go_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a,
-                                uint32_t TY, uint32_t H, hipStream_t stream) {
+                                uint32_t TY, uint32_t H, uint32_t XW, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_msc_stream<D, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       150 * 1024);
+                                       (int)kMscMaxLds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const dim3 grid(D == 3 ? a.L / TY : 1u, (a.L + H - 1) / H);
-  hipLaunchKernelGGL((k_msc_stream<D, NT>), grid, dim3(NT), msc_stream_lds(a.L, D, TY), stream, src, dst, J, a, TY,
-                     H);
+  const uint32_t nseg = a.L / XW;
+  const dim3 grid(D == 3 ? (a.L / TY) * nseg : nseg, (a.L + H - 1) / H);
+  hipLaunchKernelGGL((k_msc_stream<D, NT>), grid, dim3(NT), msc_stream_lds(a.L, D, TY, XW), stream, src, dst, J, a,
+                     TY, H, XW);
   return hipGetLastError();
 }
 
 hipError_t launch_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
-                             uint32_t TY, uint32_t H, uint32_t NT, hipStream_t stream) {
-  if (!msc_stream_supported(a.L, d, TY, H, NT)) return hipErrorInvalidValue;
-  if (d == 3) return NT == 256 ? go_msc_stream<3, 256>(src, dst, J, a, TY, H, stream)
-                               : go_msc_stream<3, 512>(src, dst, J, a, TY, H, stream);
-  return NT == 256 ? go_msc_stream<2, 256>(src, dst, J, a, TY, H, stream)
-                   : go_msc_stream<2, 512>(src, dst, J, a, TY, H, stream);
+                             uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW, hipStream_t stream) {
+  if (!msc_stream_supported(a.L, d, TY, H, NT, XW)) return hipErrorInvalidValue;
+  if (d == 3) return NT == 256 ? go_msc_stream<3, 256>(src, dst, J, a, TY, H, XW, stream)
+                               : go_msc_stream<3, 512>(src, dst, J, a, TY, H, XW, stream);
+  return NT == 256 ? go_msc_stream<2, 256>(src, dst, J, a, TY, H, XW, stream)
+                   : go_msc_stream<2, 512>(src, dst, J, a, TY, H, XW, stream);
 }
 
 // E and M of the 32 systems: per workgroup, counts of unsatisfied bonds and

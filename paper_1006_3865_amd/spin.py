@@ -70,7 +70,7 @@ SIGNATURES = {
     "spin_msc_measure": (_c.c_int, [_P, _i64p, _i64p]),
     "spin_msc_get_spins": (_c.c_int, [_P, _c.c_int, _i8p, _c.c_size_t]),
     "spin_msc_sweeps_done": (_c.c_uint64, [_P]),
-    "spin_msc_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "spin_msc_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "spin_msc_synchronize": (_c.c_int, [_P]),
     "spin_synchronize": (_c.c_int, [_P]),
     "spin_device_spins": (_c.c_void_p, [_P]),
@@ -543,8 +543,8 @@ class Msc:
     def t(self):
         return int(load().spin_msc_sweeps_done(self.h))
 
-    def set_kernel(self, streaming, rows=0, planes=0, threads=0):
-        _check(load().spin_msc_set_kernel(self.h, int(streaming), int(rows), int(planes), int(threads)))
+    def set_kernel(self, streaming, rows=0, planes=0, threads=0, width=0):
+        _check(load().spin_msc_set_kernel(self.h, int(streaming), int(rows), int(planes), int(threads), int(width)))
 
     def synchronize(self):
         _check(load().spin_msc_synchronize(self.h))

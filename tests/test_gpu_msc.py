@@ -33,6 +33,9 @@ def gpu():
     (8, 2, None), (16, 2, None), (64, 2, None), (8, 3, None), (16, 3, None), (24, 3, None),
     (16, 2, (0, 0, 0, 0)), (24, 3, (0, 0, 0, 0)),                 # one launch per colour
     (40, 2, (1, 0, 7, 512)), (24, 3, (1, 4, 5, 256)), (32, 3, (1, 16, 3, 512)), (16, 3, (1, 8, 16, 256)),
+    # rows cut into segments of `width` sites (two neighbouring groups of halo each side)
+    (40, 2, (1, 0, 7, 512, 8)), (64, 2, (1, 0, 5, 256, 16)), (24, 3, (1, 4, 5, 256, 8)),
+    (32, 3, (1, 16, 3, 512, 16)), (48, 3, (1, 8, 16, 512, 16)), (16, 3, (1, 2, 4, 256, 8)),
 ])
 def test_msc_matches_oracle(oracle_mod, L, d, kernel):
     cs, seed, r0, p0 = workloads.seed(0x60), workloads.seed(0x61), 5, 70
@@ -73,9 +76,9 @@ def test_msc_rejects_bad_shapes():
         with pytest.raises(spin.SpinError):
             spin.Msc(L, d, 1, 0, 1)
     m = spin.Msc(24, 3, 1, 0, 1)
-    for k in ((1, 5, 8, 256), (1, 8, 8, 128), (1, 8, 0, 256)):   # rows must divide L; threads 256/512
-        if k[2] == 0:
-            continue
+    # rows must divide L; threads 256/512; width a multiple of 8 dividing L; no negative sizes
+    for k in ((1, 5, 8, 256), (1, 8, 8, 128), (1, 8, 8, 256, 12), (1, 8, 8, 256, 16), (1, -8, 8, 256)):
         with pytest.raises(spin.SpinError):
             m.set_kernel(*k)
+    m.set_kernel(1, 8, 8, 256, 8)
     m.close()
