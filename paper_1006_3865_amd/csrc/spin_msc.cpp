@@ -153,15 +153,16 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
   h->S2 = nullptr;
   h->J = nullptr;
   h->J6 = nullptr;
-  // streaming shape, from measured rates: 3D whole rows in slabs of 16 rows where the ring fits LDS,
-  // else 8, else 4; strips of L/16 planes (4..32); 512 threads from L = 256 up, else 256.  2D rows cut
+  // streaming shape, from measured rates: 3D whole rows in slabs of 16 rows (from L = 256 up, where
+  // the ring fits LDS), else 8, else 4; strips of L/16 planes (4..32); 512 threads from L = 256 up, else 256.  2D rows cut
   // into segments of at most 2048 sites, strips of 16 rows, 256 threads.  Else the phase kernel.
   h->NT = 0;
   h->XW = (uint32_t)L;
   if (d == 3) {
     h->H = std::min(32u, std::max(4u, (uint32_t)L / 16));
     const uint32_t nt = L >= 256 ? 512u : 256u;
-    for (uint32_t ty : {16u, 8u, 4u})
+    const uint32_t first = L >= 256 ? 16u : 8u;
+    for (uint32_t ty : {first, 8u, 4u})
       if (!h->NT && msc_stream_supported((uint32_t)L, 3, ty, h->H, nt, h->XW)) {
         h->TY = ty;
         h->NT = nt;
@@ -183,7 +184,7 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
     return nullptr;
   }
   hipError_t e = launch_msc_init(h->S, N, seed, replica0, h->stream);
-  if (e == hipSuccess) e = launch_msc_couplings(h->J, N, (uint32_t)d, coupling_seed, realisation0, h->stream);
+  if (e == hipSuccess) e = launch_msc_couplings(h->J, N, (uint32_t)L, (uint32_t)d, coupling_seed, realisation0, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     mfail(SPIN_EDEVICE, "multi-spin setup: %s", hipGetErrorString(e));

@@ -20,7 +20,10 @@ struct MscArgs {
 };
 
 hipError_t launch_msc_init(uint32_t* S, uint64_t N, uint64_t seed, uint32_t p0, hipStream_t stream);
-hipError_t launch_msc_couplings(uint32_t* J, uint64_t N, uint32_t d, uint64_t cseed, uint32_t r0, hipStream_t stream);
+// J: d*N words; the x bonds in site order, the y and z bonds with each row
+// split by x parity (even-x words first).
+hipError_t launch_msc_couplings(uint32_t* J, uint64_t N, uint32_t L, uint32_t d, uint64_t cseed, uint32_t r0,
+                                hipStream_t stream);
 // J6: per 8-site group and colour, the 2d coupling words of each of the 4
 // active sites (-x, +x, -y, +y, -z, +z), 2d*N words, built from J.
 hipError_t launch_msc_bonds(const uint32_t* J, uint32_t* J6, uint32_t L, uint32_t d, uint64_t N, hipStream_t stream);

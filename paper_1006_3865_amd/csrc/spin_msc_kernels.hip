@@ -41,9 +41,21 @@ __global__ void k_msc_init(uint32_t* __restrict__ S, uint64_t nquads, RoundKeys 
   }
 }
 
-// Couplings: bit b of J[dir][s] is set iff bit 31 of word s&3 of
-// Philox(cseed, (s>>2, dir, r0 + b, 3)) is set (J = -1).
-__global__ void k_msc_couplings(uint32_t* __restrict__ J, uint64_t nquads, uint32_t d, RoundKeys K, uint32_t r0) {
+// Device layout of the couplings: J[dir * N + jidx(dir, s)].  The x bonds
+// (dir 0) are in site order; the y and z bonds (dir 1, 2) keep each row of L
+// words split by x parity, the L/2 even-x words first, then the odd-x ones,
+// so that the four same-colour sites of an 8-site group find their y and z
+// bonds in 16 contiguous bytes.
+__device__ __forceinline__ uint64_t msc_split(uint64_t s, uint32_t L) {
+  const uint32_t x = (uint32_t)(s % L);
+  return s - x + (x & 1u) * (L / 2) + (x >> 1);
+}
+
+// Couplings: bit b of the word of bond (dir, s) is set iff bit 31 of word
+// s&3 of Philox(cseed, (s>>2, dir, r0 + b, 3)) is set (J = -1).
+__global__ void k_msc_couplings(uint32_t* __restrict__ J, uint64_t nquads, uint32_t L, uint32_t d, RoundKeys K,
+                                uint32_t r0) {
+  const uint64_t N = nquads * 4;
   for (uint32_t dir = 0; dir < d; ++dir)
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nquads;
          q += (uint64_t)gridDim.x * blockDim.x) {
@@ -54,8 +66,19 @@ __global__ void k_msc_couplings(uint32_t* __restrict__ J, uint64_t nquads, uint3
 #pragma unroll
         for (int j = 0; j < 4; ++j) w[j] |= (r[j] >> 31) << b;
       }
-      reinterpret_cast<uint4*>(J)[(uint64_t)dir * nquads + q] = make_uint4(w[0], w[1], w[2], w[3]);
+      if (dir == 0) {
+        reinterpret_cast<uint4*>(J)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+      } else {  // sites 4q .. 4q+3 start at an even x of one row (L % 8 == 0)
+        const uint64_t e = (uint64_t)dir * N + msc_split(4 * q, L);
+        reinterpret_cast<uint2*>(J + e)[0] = make_uint2(w[0], w[2]);
+        reinterpret_cast<uint2*>(J + e + L / 2)[0] = make_uint2(w[1], w[3]);
+      }
     }
+}
+
+__device__ __forceinline__ void load4(const uint32_t* p, uint32_t (&v)[4]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
 __device__ __forceinline__ void load8(const uint32_t* p, uint32_t (&v)[8]) {
@@ -137,23 +160,24 @@ __device__ __forceinline__ void load_bonds(const uint32_t* __restrict__ J6, uint
     for (int k = 0; k < 2 * D; ++k) jb[i][k] = w[i * 2 * D + k];
 }
 
-// The same bonds from row-ordered coupling words of the group: jx (+x of
-// sites 0..7), jl (+x of the site left of the group), jy/jym (+y of this
-// row and of row y-1), jz/jzm (+z of this plane and of plane z-1).
+// The couplings of the four active sites of a group in the order of
+// msc_update8: x bonds from the group's x-bond words jx (jl: the word left of
+// the group), y and z bonds from the parity-P halves jy/jym (rows y, y-1) and
+// jz/jzm (planes z, z-1), word i for site 2i + P.
 template <int D, int P>
-__device__ __forceinline__ void bonds_from_rows(const uint32_t (&jx)[8], uint32_t jl, const uint32_t (&jy)[8],
-                                                const uint32_t (&jym)[8], const uint32_t (&jz)[8],
-                                                const uint32_t (&jzm)[8], uint32_t (&jb)[4][2 * D]) {
+__device__ __forceinline__ void bonds_split(const uint32_t (&jx)[8], uint32_t jl, const uint32_t (&jy)[4],
+                                            const uint32_t (&jym)[4], const uint32_t (&jz)[4],
+                                            const uint32_t (&jzm)[4], uint32_t (&jb)[4][2 * D]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int j = 2 * i + P;
     jb[i][0] = j ? jx[j - 1] : jl;
     jb[i][1] = jx[j];
-    jb[i][2] = jym[j];
-    jb[i][3] = jy[j];
+    jb[i][2] = jym[i];
+    jb[i][3] = jy[i];
     if (D == 3) {
-      jb[i][4] = jzm[j];
-      jb[i][5] = jz[j];
+      jb[i][4] = jzm[i];
+      jb[i][5] = jz[i];
     }
   }
 }
@@ -178,12 +202,12 @@ __global__ void k_msc_bonds(const uint32_t* __restrict__ J, uint32_t* __restrict
       const uint64_t sym = y ? s - row : s + (L - 1) * row;
       out[i * 2 * D + 0] = J[sxm];
       out[i * 2 * D + 1] = J[s];
-      out[i * 2 * D + 2] = J[N + sym];
-      out[i * 2 * D + 3] = J[N + s];
+      out[i * 2 * D + 2] = J[N + msc_split(sym, L)];
+      out[i * 2 * D + 3] = J[N + msc_split(s, L)];
       if (D == 3) {
         const uint64_t szm = z ? s - plane : s + (L - 1) * plane;
-        out[i * 2 * D + 4] = J[2 * N + szm];
-        out[i * 2 * D + 5] = J[2 * N + s];
+        out[i * 2 * D + 4] = J[2 * N + msc_split(szm, L)];
+        out[i * 2 * D + 5] = J[2 * N + msc_split(s, L)];
       }
     }
   }
@@ -336,28 +360,31 @@ __device__ __forceinline__ void msc_units(const uint32_t* pm, uint32_t* pc, cons
       lds8(pp + o, HW, yp);
     }
     const uint32_t lw = pc[o + HW - 1], rw = pc[o + 4];  // word 7 of group k-1, word 0 of group k+1
-    // couplings from HBM in row order (neighbouring units share their cache lines)
+    // couplings from HBM: the group's 8 x-bond words and the one left of it; the y and z bonds of
+    // the four active sites (x parity P) from the parity-P halves of rows y and y-1 (planes z, z-1)
     const uint64_t N = a.N, plane = (uint64_t)L * L;
     const uint64_t sl = gx ? s0 - 1 : s0 + L - 1;
-    const uint64_t sym = y ? s0 - L : s0 + (uint64_t)(L - 1) * L;  // same x in row y-1
-    uint32_t jx[8], jy[8], jym[8], jz[8], jzm[8];
+    const uint32_t P = (C + y + zz) & 1u;
+    const uint64_t hoff = (uint64_t)P * (L / 2) + 4u * gx;
+    const uint64_t rym = y ? rowbase - L : rowbase + (uint64_t)(L - 1) * L;  // start of row y-1
+    uint32_t jx[8], jy[4], jym[4], jz[4], jzm[4];
     load8(J + s0, jx);
-    load8(J + N + s0, jy);
-    load8(J + N + sym, jym);
+    load4(J + N + rowbase + hoff, jy);
+    load4(J + N + rym + hoff, jym);
     if (D == 3) {
-      const uint64_t szm = zz ? s0 - plane : s0 + (uint64_t)(L - 1) * plane;
-      load8(J + 2 * N + s0, jz);
-      load8(J + 2 * N + szm, jzm);
+      const uint64_t rzm = zz ? rowbase - plane : rowbase + (uint64_t)(L - 1) * plane;  // row y of plane z-1
+      load4(J + 2 * N + rowbase + hoff, jz);
+      load4(J + 2 * N + rzm + hoff, jzm);
     }
     const uint32_t jl = J[sl];
     uint32_t rnd[4];
     philox_lane((uint32_t)(s0 >> 3), U, a.keys, rnd);
     uint32_t jb[4][2 * D];
-    if (((C + y + zz) & 1u) == 0) {
-      bonds_from_rows<D, 0>(jx, jl, jy, jym, jz, jzm, jb);
+    if (P == 0) {
+      bonds_split<D, 0>(jx, jl, jy, jym, jz, jzm, jb);
       msc_update8<D, 0>(c, lw, rw, ym, yp, zm, zp, jb, rnd, a);
     } else {
-      bonds_from_rows<D, 1>(jx, jl, jy, jym, jz, jzm, jb);
+      bonds_split<D, 1>(jx, jl, jy, jym, jz, jzm, jb);
       msc_update8<D, 1>(c, lw, rw, ym, yp, zm, zp, jb, rnd, a);
     }
     const u32x4 lo = {c[0], c[1], c[2], c[3]}, hi = {c[4], c[5], c[6], c[7]};
@@ -387,10 +414,14 @@ __global__ __launch_bounds__(NT) void k_msc_stream(const uint32_t* __restrict__ 
   const uint32_t RP = (D == 3) ? TY + 4 : 1u;
   const uint32_t SB = RP * G.RW;
   const uint32_t nseg = L / XW;
-  const uint32_t seg = blockIdx.x % nseg;
+  const uint32_t gx = (D == 3) ? (L / TY) * nseg : nseg;
+  uint32_t blk = blockIdx.x;
+  if ((gridDim.x & 7u) == 0) blk = (blk & 7u) * (gridDim.x >> 3) + (blk >> 3);
+  const uint32_t bx = blk % gx, by = blk / gx;
+  const uint32_t seg = bx % nseg;
   G.gx0 = seg * (XW / 8);
-  const uint32_t y0 = (D == 3) ? (blockIdx.x / nseg) * TY : 0u;
-  const uint32_t z0 = blockIdx.y * Ha;
+  const uint32_t y0 = (D == 3) ? (bx / nseg) * TY : 0u;
+  const uint32_t z0 = by * Ha;
   const uint32_t H = (L - z0 < Ha) ? L - z0 : Ha;
   const PhiloxUniform U0 = philox_uniform(a.t, a.p0, 4u, a.keys);
   const PhiloxUniform U1 = philox_uniform(a.t, a.p0, 5u, a.keys);
@@ -453,7 +484,7 @@ static hipError_t go_msc_stream(const uint32_t* src, uint32_t* dst, const uint32
     attr = true;
   }
   const uint32_t nseg = a.L / XW;
-  const dim3 grid(D == 3 ? (a.L / TY) * nseg : nseg, (a.L + H - 1) / H);
+  const dim3 grid((D == 3 ? (a.L / TY) * nseg : nseg) * ((a.L + H - 1) / H));
   hipLaunchKernelGGL((k_msc_stream<D, NT>), grid, dim3(NT), msc_stream_lds(a.L, D, TY, XW), stream, src, dst, J, a,
                      TY, H, XW);
   return hipGetLastError();
@@ -485,9 +516,10 @@ __global__ __launch_bounds__(256) void k_msc_count(const uint32_t* __restrict__ 
     const uint32_t x = (uint32_t)(s % L), y = (uint32_t)((s / L) % L), z = (D == 3) ? (uint32_t)(s / plane) : 0u;
     const uint32_t v = S[s];
     const uint32_t bx = v ^ S[x + 1 < L ? s + 1 : s + 1 - L] ^ J[s];
-    const uint32_t by = v ^ S[y + 1 < L ? s + row : s - (L - 1) * row] ^ J[N + s];
+    const uint64_t sj = msc_split(s, L);
+    const uint32_t by = v ^ S[y + 1 < L ? s + row : s - (L - 1) * row] ^ J[N + sj];
     uint32_t bz = 0;
-    if (D == 3) bz = v ^ S[z + 1 < L ? s + plane : s - (L - 1) * plane] ^ J[2 * N + s];
+    if (D == 3) bz = v ^ S[z + 1 < L ? s + plane : s - (L - 1) * plane] ^ J[2 * N + sj];
 #pragma unroll
     for (int b = 0; b < 32; ++b) {
       cu[b] += ((bx >> b) & 1u) + ((by >> b) & 1u) + ((bz >> b) & 1u);
@@ -527,8 +559,9 @@ hipError_t launch_msc_init(uint32_t* S, uint64_t N, uint64_t seed, uint32_t p0, 
   return hipGetLastError();
 }
 
-hipError_t launch_msc_couplings(uint32_t* J, uint64_t N, uint32_t d, uint64_t cseed, uint32_t r0, hipStream_t stream) {
-  hipLaunchKernelGGL(k_msc_couplings, dim3(blocks_for(N / 4, 8192)), dim3(256), 0, stream, J, N / 4, d,
+hipError_t launch_msc_couplings(uint32_t* J, uint64_t N, uint32_t L, uint32_t d, uint64_t cseed, uint32_t r0,
+                                hipStream_t stream) {
+  hipLaunchKernelGGL(k_msc_couplings, dim3(blocks_for(N / 4, 8192)), dim3(256), 0, stream, J, N / 4, L, d,
                      make_round_keys(cseed), r0);
   return hipGetLastError();
 }
