@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-tile multi-hit schedule")
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
+    ap.add_argument("--msc-shapes", default="512x3,256x3,128x3,4096x2",
+                    help="multi-spin-coded lattices as LxD, comma separated")
     return ap.parse_args()
 
 
@@ -64,6 +66,7 @@ KERNEL_SOURCES = {
     "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h"),
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
+    "k_msc_stream": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),
 }
 
 
@@ -214,8 +217,18 @@ def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (409
         b.record(stream)
         m.synchronize()
         ms = a.elapsed_time(b)
-        out["d%d_L%d" % (d, L)] = {"attempts_per_ns": round(32 * N * n / (ms * 1e6), 1),
-                                   "ps_per_attempt": round(ms * 1e9 / (32 * N * n), 4), "sweeps": n}
+        # fewest HBM bytes a sweep can move: read and write each site word, read the d coupling words
+        hbm_min = N * (8 + 4 * d)
+        rec = {"attempts_per_ns": round(32 * N * n / (ms * 1e6), 1),
+               "ps_per_attempt": round(ms * 1e9 / (32 * N * n), 4), "sweeps": n,
+               "ms_per_sweep": round(ms / n, 4),
+               "min_hbm_GBps": round(hbm_min * n / (ms * 1e6), 1),
+               "min_hbm_frac": round(hbm_min * n / (ms * 1e-3) / 8e12, 4)}
+        traffic = profiled_traffic("k_msc_stream", L) if d == 3 else None
+        if traffic is not None:   # HBM bytes per sweep counted by rocprofv3 for this kernel and L
+            rec["traffic_bytes_per_sweep"] = traffic
+            rec["traffic_GBps"] = round(traffic * n / (ms * 1e6), 1)
+        out["d%d_L%d" % (d, L)] = rec
         m.close()
     return {"workload": "ea multi-spin-coded (32 realisations per word)", "beta": beta, "rates": out}
 
@@ -370,7 +383,8 @@ def main():
         out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
     if not args.no_msc:
-        out["multispin"] = bench_msc(torch, spin, workloads)
+        shapes = tuple(tuple(int(v) for v in t.split("x")) for t in args.msc_shapes.split(",") if t)
+        out["multispin"] = bench_msc(torch, spin, workloads, shapes)
         print("multispin:", json.dumps(out["multispin"]), file=sys.stderr, flush=True)
     if not args.no_serving:
         from paper_1006_3865_amd import serve

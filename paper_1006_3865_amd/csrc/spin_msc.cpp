@@ -154,19 +154,31 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
   h->J = nullptr;
   h->J6 = nullptr;
   // streaming shape, from measured rates: 3D whole rows in slabs of 16 rows (from L = 256 up, where
-  // the ring fits LDS), else 8, else 4; strips of L/16 planes (4..32); 512 threads from L = 256 up, else 256.  2D rows cut
-  // into segments of at most 2048 sites, strips of 16 rows, 256 threads.  Else the phase kernel.
+  // the ring fits LDS), else 8, else 4, and strips of planes sized so that the grid holds about one
+  // workgroup per compute unit (at least 4 planes); 512 threads from L = 256 up, else 256.  2D rows
+  // cut into segments of at most 2048 sites, strips of 16 rows, 256 threads.  Else the phase kernel.
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  (void)hipGetLastError();
   h->NT = 0;
+  h->TY = d == 3 ? 8u : 1u;
+  h->H = 16;
   h->XW = (uint32_t)L;
   if (d == 3) {
-    h->H = std::min(32u, std::max(4u, (uint32_t)L / 16));
     const uint32_t nt = L >= 256 ? 512u : 256u;
     const uint32_t first = L >= 256 ? 16u : 8u;
-    for (uint32_t ty : {first, 8u, 4u})
-      if (!h->NT && msc_stream_supported((uint32_t)L, 3, ty, h->H, nt, h->XW)) {
+    for (uint32_t ty : {first, 8u, 4u}) {
+      const uint32_t strips = std::max(1u, (uint32_t)cus / ((uint32_t)L / ty));
+      const uint32_t H = std::min((uint32_t)L, std::max(4u, ((uint32_t)L + strips - 1) / strips));
+      if (!h->NT && msc_stream_supported((uint32_t)L, 3, ty, H, nt, h->XW)) {
         h->TY = ty;
+        h->H = H;
         h->NT = nt;
       }
+    }
   } else {
     while (h->XW > 2048 && (h->XW / 2) % 8 == 0) h->XW /= 2;
     h->TY = 1;
