@@ -213,6 +213,16 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
   const int L = h->L;
   if (kernel == SPIN_KERNEL_STREAM) {  // each field: the request if given, else the default
     Tile d = h->d == 3 ? Tile{L, 8, L >= 8 ? 8 : L, 512} : Tile{L, 1, 8, 512};
+    if (h->d == 3) {
+      // 3D defaults from measured rates (Ising and +-J alike): rows per slab, planes per strip and
+      // threads by lattice size
+      Tile m = L >= 384   ? Tile{L, 16, L >= 512 ? 16 : 8, 256}
+               : L >= 256 ? Tile{L, 16, 8, 512}
+               : L >= 192 ? Tile{L, 8, 4, 256}
+                          : Tile{L, 16, 4, 512};
+      if (L % m.y != 0) m.y = 8;
+      if (streamg_supported(lat_of(h), m)) d = m;
+    }
     if (t.y && h->d == 3) d.y = t.y;
     if (t.z) d.z = t.z;
     if (t.threads) d.threads = t.threads;
@@ -272,7 +282,10 @@ static int resolve(const spin_lattice* h, Tile* tile) {
     *tile = default_tile(h, SPIN_KERNEL_RESIDENT);
     return SPIN_KERNEL_RESIDENT;
   }
-  const int order[3] = {SPIN_KERNEL_FUSED, SPIN_KERNEL_TILED, SPIN_KERNEL_STREAM};
+  // 3D lattices from L = 160 up stream faster than they tile (measured); below that, tiles win
+  const bool stream_first = h->d == 3 && h->L >= 160;
+  const int order[3] = {SPIN_KERNEL_FUSED, stream_first ? SPIN_KERNEL_STREAM : SPIN_KERNEL_TILED,
+                        stream_first ? SPIN_KERNEL_TILED : SPIN_KERNEL_STREAM};
   for (int k : order) {
     Tile t = default_tile(h, k);
     if (family_ok(h, k, t)) {
@@ -485,7 +498,7 @@ static std::vector<Tuned> tune_candidates(const spin_lattice* h) {
     for (auto& f : t3) c.push_back({SPIN_KERNEL_TILED, Tile{f[0], f[1], f[2], f[3]}});
     for (int th : {256, 512})
       for (int TY : {4, 8, 16, 32})
-        for (int H : {8, 16, 32}) c.push_back({SPIN_KERNEL_STREAM, Tile{L, TY, H, th}});
+        for (int H : {4, 8, 16, 32}) c.push_back({SPIN_KERNEL_STREAM, Tile{L, TY, H, th}});
   }
   c.push_back({SPIN_KERNEL_GENERIC, Tile{0, 0, 0, 256}});
   return c;

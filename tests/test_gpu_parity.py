@@ -184,6 +184,17 @@ def test_auto_picks_stream(oracle_mod, model, L, d):
                  cseed=workloads.seed(0x11) if model else None, tag="auto-stream")
 
 
+@pytest.mark.parametrize("model,L", [(0, 160), (1, 200), (0, 256), (1, 384)])
+def test_auto_3d_stream_defaults(oracle_mod, model, L):
+    """Large 3D lattices stream with the size-dependent default tiles (slab rows, strip planes and
+    threads chosen by L); the bits are the oracle's."""
+    lat = make(model, L, 3, workloads.seed(80 + L), 1, None, workloads.seed(0x11) if model else None)
+    assert lat.kernel == STR, spin.KERNEL_NAMES[lat.kernel]
+    lat.close()
+    compare_runs(oracle_mod, model, L, 3, workloads.seed(80 + L), [(1, 0.3, 1), (1, 0.9, 1)], replica=1,
+                 cseed=workloads.seed(0x11) if model else None, tag="auto-3d-stream")
+
+
 def test_auto_choice_and_switching(oracle_mod):
     """Switch families between calls of one chain; bits must not change."""
     L, s = 64, workloads.seed(50)
