@@ -82,3 +82,51 @@ def test_msc_rejects_bad_shapes():
             m.set_kernel(*k)
     m.set_kernel(1, 8, 8, 256, 8)
     m.close()
+
+
+def test_msc_full_size_sampled_sites(oracle_mod):
+    """The 3D L = 512 handle in the launch shape the benchmark times: one sweep checked site by site
+    on a sample.  A colour-0 site is decided from the state before the sweep (its neighbours are
+    colour 1), a colour-1 site from its old value and the final colour-0 neighbours; each decision is
+    the oracle's rule (Eq. 2) with the shared Philox word of the site."""
+    L, d = 512, 3
+    N = L ** d
+    cs, seed, r0, p0 = workloads.seed(0x11), workloads.seed(0x10), 0, 0
+    beta = workloads.ea_betas()[7]
+    note("msc full size", L, d)
+    m = spin.Msc(L, d, cs, r0, seed, p0)
+    m.sweep(2, beta)
+    systems = (0, 19, 31)
+    before = {b: m.spins(b) for b in systems}
+    t = m.t
+    m.sweep(1, beta)
+    after = {b: m.spins(b) for b in systems}
+    m.close()
+    T = oracle_mod.table(beta, d)
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    rng = np.random.default_rng(0x5A)
+    sites = rng.choice(N, 3000, replace=False)
+    x, y, z = sites % L, (sites // L) % L, sites // (L * L)
+    step = (1, L, L * L)
+    coord = (x, y, z)
+    draws = {}
+    for s in sites.tolist():
+        c = ((s % L) + (s // L) % L + s // (L * L)) & 1
+        w = oracle_mod.philox4x32_10((s >> 3, t, p0, 4 + c), key)
+        draws[s] = (c, int(w[(s >> 1) & 3]))
+    for b in systems:
+        J = oracle_mod.couplings(L, d, cs, r0 + b)
+        old, new = before[b], after[b]
+        for i, s in enumerate(sites.tolist()):
+            c, r = draws[s]
+            nbr = new if c == 1 else old   # colour-1 sites see final colour-0 neighbours
+            h = 0
+            for dr in range(d):
+                v = int(coord[dr][i])
+                sp = s + step[dr] if v + 1 < L else s - (L - 1) * step[dr]
+                sm = s - step[dr] if v > 0 else s + (L - 1) * step[dr]
+                h += int(J[dr * N + s]) * int(nbr[sp]) + int(J[dr * N + sm]) * int(nbr[sm])
+            k = int(old[s]) * h
+            flip = r < int(T[(k + 2 * d) // 2])
+            expect = -int(old[s]) if flip else int(old[s])
+            assert int(new[s]) == expect, ("system", b, "site", s, "colour", c)
