@@ -95,3 +95,10 @@ def test_bad_schedules_rejected():
     with pytest.raises(spin.SpinError):
         lat3.set_schedule(COARSE, 32, 1)          # 3D tiles are 8 or 16
     lat3.close()
+
+
+@pytest.mark.parametrize("L,T,k,n", [(1024, 16, 4, 2), (8192, 32, 8, 1), (8192, 64, 2, 1)])
+def test_coarse_benchmark_sizes(oracle_mod, L, T, k, n):
+    """The coarse-tile mode at the sizes, tiles and hit counts the benchmark times, whole lattice
+    against the oracle (spins, E and M after every sweep)."""
+    run(oracle_mod, 0, L, 2, T, k, [(n, workloads.BETA_2D_CRIT, 1)])
