@@ -36,6 +36,13 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # 4 + 8 + 4 sums + 4 x (extract, compare, select) + 2 flip XORs + 1 counter = 31 -> 7.75.
 ALG_OPS_PER_ATTEMPT = {2: 10.0 + 31 / 4.0, 3: 10.0 + (4 + 12 + 8 + 12 + 2 + 1) / 4.0}
 BYTES_PER_ATTEMPT = 2.0  # int8 spin read once and written once per sweep (Ising)
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz.  Algorithmic LDS bytes of the streaming kernels per
+# 8-site group and sweep: the row (2D) or plane-slice row (3D) stored once (8 B); per colour unit the
+# group and its in-LDS neighbours (2D: 3 x 8 B + 2 x 4 B = 32 B; 3D: 5 x 8 B + 2 x 4 B = 48 B) and four
+# 4-byte bound lookups (16 B); colour 0 stores the group back (8 B).  2D: 8 + 56 + 48 = 112 B, 3D:
+# 8 + 72 + 64 = 144 B, per 8 attempts.
+LDS_PEAK_GBS = 256 * 128 * 2.4
+LDS_BYTES_PER_ATTEMPT = {2: 112 / 8.0, 3: 144 / 8.0}
 
 
 def parse():
@@ -347,6 +354,11 @@ def main():
             "hbm": {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                     "alg_bytes_per_launch": int(BYTES_PER_ATTEMPT * attempts_per_launch)}}
+    if kname == "fused":  # the streaming kernels
+        lds_gbs = LDS_BYTES_PER_ATTEMPT[d] * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
+        roof["lds"] = {"achieved": round(lds_gbs, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
+                       "frac": round(lds_gbs / LDS_PEAK_GBS, 4),
+                       "alg_bytes_per_launch": int(LDS_BYTES_PER_ATTEMPT[d] * attempts_per_launch)}
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
