@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-tile multi-hit schedule")
+    ap.add_argument("--no-autocorr", action="store_true",
+                    help="skip the multi-hit autocorrelation measurement near the critical point")
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     ap.add_argument("--msc-shapes", default="512x3,256x3,128x3,4096x2",
@@ -205,6 +207,56 @@ def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64),
         lat.close()
     return {"workload": "ising2d coarse-tile multi-hit", "beta": workloads.BETA_2D_CRIT,
             "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
+
+
+def bench_multihit_autocorr(torch, spin, workloads, L=64, T=16, hits=(1, 2, 4, 8), sweeps=200_000, therm=5_000,
+                            chunk=20_000):
+    """The autocorrelation cost of the multi-hit schedule near the critical point (Sec. 3, multi-hit
+    paragraph): 2D Ising L=64 at beta 0.4406868, the canonical checkerboard and coarse tiles of edge T
+    with k hits; E and M recorded after every sweep (device records), integrated autocorrelation times
+    of E and |M| in sweeps (self-consistent window, c = 6), and the GPU time per independent sample
+    (tau_int x time per sweep, records included)."""
+    import numpy as np
+    from paper_1006_3865_amd import analysis
+    beta = workloads.BETA_2D_CRIT
+    stream = torch.cuda.Stream()
+    N = L * L
+    out = {}
+    for k in (0,) + tuple(hits):
+        lat = spin.Lattice(0, L, 2, workloads.seed(0x30), stream=stream)
+        if k:
+            lat.set_schedule(spin.SPIN_SCHEDULE_COARSE, T, k)
+        lat.sweep(therm, beta)
+        E = torch.zeros(sweeps, dtype=torch.int64, device="cuda")
+        M = torch.zeros(sweeps, dtype=torch.int64, device="cuda")
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for c0 in range(0, sweeps, chunk):
+            lat.sweep_record_device(chunk, beta, 1, E[c0:], M[c0:])
+        b.record(stream)
+        lat.synchronize()
+        ms = a.elapsed_time(b)
+        lat.close()
+        e, m = E.cpu().numpy(), np.abs(M.cpu().numpy())
+        tE, wE, dE = analysis.tau_int(e)
+        tM, wM, dM = analysis.tau_int(m)
+        us = ms * 1e3 / sweeps
+        name = "checkerboard" if k == 0 else "coarse_T%d_k%d" % (T, k)
+        out[name] = {"hits": max(k, 1), "us_per_sweep": round(us, 3),
+                     "attempts_per_ns": round(max(k, 1) * N * sweeps / (ms * 1e6), 2),
+                     "tau_int_E": round(tE, 2), "tau_int_E_err": round(dE, 2),
+                     "tau_int_absM": round(tM, 1), "tau_int_absM_err": round(dM, 1),
+                     "us_per_independent_E": round(tE * us, 2), "us_per_independent_absM": round(tM * us, 1),
+                     "mean_e_per_site": round(float(e.mean()) / N, 6)}
+    # attempts per independent sample in units of N attempts (hits x tau), relative to the checkerboard
+    ref = out["checkerboard"]
+    for v in out.values():
+        v["attempt_sweeps_per_independent_E"] = round(v["hits"] * v["tau_int_E"], 1)
+        v["attempt_sweeps_per_independent_absM"] = round(v["hits"] * v["tau_int_absM"], 1)
+        v["penalty_E"] = round(v["hits"] * v["tau_int_E"] / ref["tau_int_E"], 3)
+        v["penalty_absM"] = round(v["hits"] * v["tau_int_absM"] / ref["tau_int_absM"], 3)
+    return {"workload": "2D Ising L=%d at beta 0.4406868, %d sweeps recorded after %d" % (L, sweeps, therm),
+            "tile": T, "window_c": 6, "modes": out}
 
 
 def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (4096, 2))):
@@ -393,6 +445,8 @@ def main():
         print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
     if not args.no_coarse:
         out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
+    if not args.no_coarse and not args.no_autocorr:
+        out["multihit_autocorr"] = bench_multihit_autocorr(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
     if not args.no_msc:
         shapes = tuple(tuple(int(v) for v in t.split("x")) for t in args.msc_shapes.split(",") if t)
