@@ -20,6 +20,10 @@ from .oracle import (  # noqa: F401
     sweeps,
     coarse_sweeps,
     msc_sweeps,
+    lcg_skip,
+    lcg_init,
+    lcg_sweeps,
     MscChain,
+    LcgChain,
     Chain,
 )

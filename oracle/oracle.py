@@ -67,6 +67,13 @@ class OracleLib:
         lib.oracle_msc_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int, i64p, i64p]
         lib.oracle_msc_sweeps.restype = ctypes.c_int
+        lib.oracle_lcg_skip.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_lcg_skip.restype = ctypes.c_uint64
+        lib.oracle_lcg_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, u64p]
+        lib.oracle_lcg_init.restype = ctypes.c_int
+        lib.oracle_lcg_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, u64p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_int, i64p, i64p]
+        lib.oracle_lcg_sweeps.restype = ctypes.c_int
         self.lib = lib
 
     def philox4x32_10(self, ctr, key):
@@ -157,6 +164,32 @@ class OracleLib:
             raise ValueError("oracle_msc_sweeps rejected its arguments")
         return E[:nrec * 32].reshape(nrec, 32).copy(), M[:nrec * 32].reshape(nrec, 32).copy()
 
+    def lcg_skip(self, mode, x, k):
+        """State x of LCG mode 1/2 (32-bit) or 3 (64-bit) advanced by k steps."""
+        return int(self.lib.oracle_lcg_skip(int(mode), int(x), int(k)))
+
+    def lcg_init(self, L, d, mode, seed, replica=0):
+        """Initial generator states (uint64[L^d/8]) of LCG mode 1, 2 or 3."""
+        st = np.zeros((L ** d) // 8, dtype=np.uint64)
+        if self.lib.oracle_lcg_init(L, d, int(mode), seed, replica, _ptr(st, ctypes.c_uint64)) != 0:
+            raise ValueError("oracle_lcg_init rejected its arguments")
+        return st
+
+    def lcg_sweeps(self, L, d, J, spins, state, mode, n, beta, every=0):
+        """n sweeps of the canonical chain drawing from per-group LCG states (advanced in place)."""
+        assert spins.dtype == np.int8 and spins.flags.c_contiguous
+        assert state.dtype == np.uint64 and state.flags.c_contiguous and state.size == (L ** d) // 8
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1), dtype=np.int64)
+        M = np.zeros(max(nrec, 1), dtype=np.int64)
+        Jarr = None if J is None else np.ascontiguousarray(J, dtype=np.int8)
+        Jp = None if Jarr is None else _ptr(Jarr, ctypes.c_int8)
+        rc = self.lib.oracle_lcg_sweeps(L, d, Jp, _ptr(spins, ctypes.c_int8), _ptr(state, ctypes.c_uint64), int(mode),
+                                        n, float(beta), every, _ptr(E, ctypes.c_int64), _ptr(M, ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle_lcg_sweeps rejected its arguments")
+        return E[:nrec].copy(), M[:nrec].copy()
+
 
 _default = None
 
@@ -202,6 +235,18 @@ def msc_sweeps(L, d, J, spins, seed, p0, t0, n, beta, every=0):
     return default().msc_sweeps(L, d, J, spins, seed, p0, t0, n, beta, every)
 
 
+def lcg_skip(mode, x, k):
+    return default().lcg_skip(mode, x, k)
+
+
+def lcg_init(L, d, mode, seed, replica=0):
+    return default().lcg_init(L, d, mode, seed, replica)
+
+
+def lcg_sweeps(L, d, J, spins, state, mode, n, beta, every=0):
+    return default().lcg_sweeps(L, d, J, spins, state, mode, n, beta, every)
+
+
 class MscChain:
     """32 multi-spin-coded +-J systems: realisations r0 + b, hot starts of replicas p0 + b."""
 
@@ -220,6 +265,21 @@ class MscChain:
     def measure(self):
         out = [self.lib.measure(self.L, self.d, self.J[b], self.spins[b]) for b in range(32)]
         return np.array([e for e, _ in out]), np.array([m for _, m in out])
+
+class LcgChain:
+    """One lattice of the canonical chain whose draws come from per-group LCG streams (mode 1..3)."""
+
+    def __init__(self, L, d, seed, mode, replica=0, J=None, lib=None):
+        self.lib = lib or default()
+        self.L, self.d, self.mode, self.J = L, d, mode, J
+        self.spins = self.lib.init_spins(L, d, seed, replica)
+        self.state = self.lib.lcg_init(L, d, mode, seed, replica)
+
+    def sweep(self, n, beta, every=0):
+        return self.lib.lcg_sweeps(self.L, self.d, self.J, self.spins, self.state, self.mode, n, beta, every)
+
+    def measure(self):
+        return self.lib.measure(self.L, self.d, self.J, self.spins)
 
 
 class Chain:

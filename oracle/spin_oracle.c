@@ -71,6 +71,24 @@
  *  spin iff r < T[(k_b + z)/2] with its own k_b.  Each system alone is a
  *  Metropolis chain of its realisation; the systems are coupled only
  *  through the shared draws.
+ *
+ *  Linear congruential generators (Sec. 4, first paragraph: the RNG-quality
+ *  experiment), a mode of the canonical chain with another source of draws:
+ *  every 8-site group g = s>>3 (the "thread") owns one generator state; in
+ *  each colour phase the group's four sites of that colour draw the next
+ *  four numbers of its stream in increasing x.  Step x -> a x + c with
+ *      32-bit: a = 1664525, c = 1013904223 (mod 2^32), draw = x,
+ *      64-bit: a = 6364136223846793005, c = 1442695040888963407 (mod 2^64),
+ *              draw = the high 32 bits of x,
+ *  the new state being the draw's source.  Initial states, G = L^d/8 groups:
+ *      mode 1 (array, one multiplier, random seeds): 32-bit, state of g =
+ *              word 0 of Philox counter (g, 0, replica, 6);
+ *      mode 2 (disjoint sub-sequences of one 32-bit LCG): x0 = word 0 of
+ *              Philox counter (0, 0, replica, 7); group g starts g*len steps
+ *              after x0, len = floor(2^32 / G);
+ *      mode 3 (disjoint sub-sequences of one 64-bit LCG): x0 = word 1 of
+ *              that block * 2^32 + word 0; len = floor(2^64 / G).
+ *  Everything else (table, acceptance compare, colour order) is as above.
  */
 #include <math.h>
 #include <stddef.h>
@@ -399,6 +417,97 @@ int oracle_msc_sweeps(int L, int d, const int8_t* J, int8_t* spins,
       for (int b = 0; b < 32; ++b)
         oracle_measure(L, d, J + (int64_t)b * d * N, spins + (int64_t)b * N,
                        &E[rec * 32 + b], &M[rec * 32 + b]);
+      ++rec;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------- LCG experiment mode */
+
+#define LCG32_A 1664525u
+#define LCG32_C 1013904223u
+#define LCG64_A 6364136223846793005ull
+#define LCG64_C 1442695040888963407ull
+
+static uint64_t lcg_step(int mode, uint64_t x) {
+  if (mode == 3) return x * LCG64_A + LCG64_C;
+  return (uint64_t)(uint32_t)((uint32_t)x * LCG32_A + LCG32_C);
+}
+
+static uint32_t lcg_draw(int mode, uint64_t x) {
+  return mode == 3 ? (uint32_t)(x >> 32) : (uint32_t)x;
+}
+
+/* x advanced by k steps.  f(x) = a x + c composed with itself is
+ * x -> a^2 x + (a + 1) c; binary powers of f are combined for the set bits
+ * of k (all arithmetic mod 2^64, then reduced mod 2^32 for the 32-bit
+ * generator). */
+uint64_t oracle_lcg_skip(int mode, uint64_t x, uint64_t k) {
+  uint64_t A = mode == 3 ? LCG64_A : LCG32_A, C = mode == 3 ? LCG64_C : LCG32_C;
+  uint64_t ga = 1, gc = 0; /* accumulated map g(x) = ga x + gc */
+  while (k) {
+    if (k & 1) {
+      ga = A * ga;
+      gc = A * gc + C;
+    }
+    C = (A + 1) * C;
+    A = A * A;
+    k >>= 1;
+  }
+  uint64_t r = ga * x + gc;
+  return mode == 3 ? r : (uint64_t)(uint32_t)r;
+}
+
+/* floor(2^32 / G) and floor(2^64 / G) for G >= 1. */
+static uint64_t block_len(int mode, uint64_t G) {
+  if (mode != 3) return (((uint64_t)1) << 32) / G;
+  uint64_t q = UINT64_MAX / G;
+  return (UINT64_MAX % G == G - 1) ? q + 1 : q; /* G divides 2^64 */
+}
+
+/* Initial generator states of the G = L^d/8 groups (see the header).
+ * Returns 0, or -1 on bad arguments (mode not 1..3, L % 8 != 0). */
+int oracle_lcg_init(int L, int d, int mode, uint64_t seed, uint32_t replica, uint64_t* state) {
+  if (!valid_shape(L, d) || L % 8 != 0 || mode < 1 || mode > 3) return -1;
+  uint64_t G = (uint64_t)site_count(L, d) / 8;
+  if (mode == 1) {
+    for (uint64_t g = 0; g < G; ++g) state[g] = draw(seed, (uint32_t)g, 0, replica, 6, 0);
+    return 0;
+  }
+  uint64_t x0 = draw(seed, 0, 0, replica, 7, 0);
+  if (mode == 3) x0 |= (uint64_t)draw(seed, 0, 0, replica, 7, 1) << 32;
+  uint64_t len = block_len(mode, G);
+  for (uint64_t g = 0; g < G; ++g) state[g] = oracle_lcg_skip(mode, x0, g * len);
+  return 0;
+}
+
+/* n sweeps of the canonical chain with LCG draws (modes 1..3); state[G] is
+ * advanced in place.  Records as in oracle_sweeps.  Returns 0, or -1 on bad
+ * arguments. */
+int oracle_lcg_sweeps(int L, int d, const int8_t* J, int8_t* spins, uint64_t* state, int mode, int n,
+                      double beta, int every, int64_t* E, int64_t* M) {
+  if (!valid_shape(L, d) || L % 8 != 0 || mode < 1 || mode > 3 || n < 0) return -1;
+  if (isnan(beta) || beta < 0) return -1;
+  int z = 2 * d;
+  uint64_t T[7];
+  oracle_table(beta, d, T);
+  int64_t N = site_count(L, d);
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int64_t s = 0; s < N; ++s) {
+        if (colour_of(s, L, d) != colour) continue;
+        const int field = local_field(s, L, d, J, spins, N);
+        const int k = spins[s] * field;
+        uint64_t* st = &state[s >> 3];
+        *st = lcg_step(mode, *st);
+        uint32_t r = lcg_draw(mode, *st);
+        if ((uint64_t)r < T[(k + z) / 2]) spins[s] = (int8_t)(-spins[s]);
+      }
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      oracle_measure(L, d, J, spins, &E[rec], &M[rec]);
       ++rec;
     }
   }

@@ -16,6 +16,14 @@ import bruteforce as bf
 import oracle
 
 MUTANTS = {
+    "lcg64_low_word": ("return mode == 3 ? (uint32_t)(x >> 32) : (uint32_t)x;", "return (uint32_t)x;"),
+    "lcg_draw_before_step": ("*st = lcg_step(mode, *st);\n        uint32_t r = lcg_draw(mode, *st);",
+                             "uint32_t r = lcg_draw(mode, *st);\n        *st = lcg_step(mode, *st);"),
+    "lcg_block_len_wrong_count": ("uint64_t len = block_len(mode, G);", "uint64_t len = block_len(mode, G + 1);"),
+    "lcg_stream_per_four_sites": ("uint64_t* st = &state[s >> 3];",
+                                  "uint64_t* st = &state[(uint64_t)(s >> 2) % ((uint64_t)N / 8)];"),
+    "lcg_skip_square_wrong": ("    C = (A + 1) * C;", "    C = A * C;"),
+    "lcg32_multiplier": ("#define LCG32_A 1664525u", "#define LCG32_A 1664521u"),
     "drop_backward_neighbour": ("h += coupling(J, dir, dn, N) * spins[dn];", "(void)dn;"),
     "wrong_sign_of_k": ("int k = spins[s] * h;", "int k = -spins[s] * h;"),
     "dE_is_k_not_2k": ("double dE = (double)(2 * k);", "double dE = (double)k;"),
@@ -125,6 +133,40 @@ def _quick_pins(lib, rocrand_philox):
         for t in range(t0, t0 + n):
             bf.sweep(ref, L, d, J[b], beta, t, lambda s, tt, c: int(w[(s >> 3, tt, c)][(s >> 1) & 3]))
         np.testing.assert_array_equal(spins[b], ref)
+
+    # LCG mode: published sequence, skip-ahead, contiguous blocks, brute force with per-group streams
+    x, seq = 0, []
+    for _ in range(3):
+        x = lib.lcg_skip(1, x, 1)
+        seq.append(x)
+    assert seq == [1013904223, 1196435762, 3519870697]
+    for mode, mod in ((1, 1 << 32), (3, 1 << 64)):
+        a, c = (1664525, 1013904223) if mode == 1 else (6364136223846793005, 1442695040888963407)
+        y = 987654321
+        for _ in range(7):
+            y = (a * y + c) % mod
+        assert lib.lcg_skip(mode, 987654321, 7) == y
+    for mode in (2, 3):
+        st = lib.lcg_init(16, 2, mode, 0x77, 1)
+        ln = (1 << (64 if mode == 3 else 32)) // 32
+        assert all(lib.lcg_skip(mode, int(st[g]), ln) == int(st[g + 1]) for g in range(31))
+    for mode in (2, 3):
+        L, d, beta = 8, 2, 0.44
+        spins = lib.init_spins(L, d, 0x77, 1)
+        state = lib.lcg_init(L, d, mode, 0x77, 1)
+        ref, py = spins.copy(), [int(v) for v in state]
+        lib.lcg_sweeps(L, d, None, spins, state, mode, 1, beta)
+
+        def lcg_draw(s, t, c, mode=mode, py=py):
+            g = s >> 3
+            if mode == 3:
+                py[g] = (6364136223846793005 * py[g] + 1442695040888963407) % (1 << 64)
+                return py[g] >> 32
+            py[g] = (1664525 * py[g] + 1013904223) % (1 << 32)
+            return py[g]
+        bf.sweep(ref, L, d, None, beta, 0, lcg_draw)
+        np.testing.assert_array_equal(spins, ref)
+
 
 def test_unmodified_oracle_passes_quick_pins(oracle_mod, rocrand_philox):
     _quick_pins(oracle_mod.default(), rocrand_philox)
