@@ -69,6 +69,26 @@ enum spin_kernel {
                                any L % 8 == 0 with L >= 16, both models, ping-pong buffers */
 };
 
+/* Source of the update draws (spin_set_rng).  SPIN_RNG_PHILOX is the
+ * canonical chain above.  The others reproduce the generators of the
+ * paper's RNG-quality experiment (Sec. 4, first paragraph) on the same
+ * checkerboard chain: every 8-site group s>>3 owns one generator whose next
+ * four numbers decide its four sites of a colour phase, in increasing x.
+ *   SPIN_RNG_LCG32_ARRAY: x -> 1664525 x + 1013904223 (mod 2^32), draw x;
+ *     each group seeded by word 0 of Philox (g, 0, replica, 6);
+ *   SPIN_RNG_LCG32_DISJOINT: the same generator, one sequence from x0 =
+ *     word 0 of Philox (0, 0, replica, 7), group g starting
+ *     g * floor(2^32 / G) steps in (G = L^d/8 groups);
+ *   SPIN_RNG_LCG64_DISJOINT: x -> 6364136223846793005 x +
+ *     1442695040888963407 (mod 2^64), draw = high 32 bits; x0 = words 1:0
+ *     of that Philox block; blocks of floor(2^64 / G). */
+enum spin_rng {
+  SPIN_RNG_PHILOX = 0,
+  SPIN_RNG_LCG32_ARRAY = 1,
+  SPIN_RNG_LCG32_DISJOINT = 2,
+  SPIN_RNG_LCG64_DISJOINT = 3
+};
+
 /* Order of the updates within a sweep (spin_set_schedule). */
 enum spin_schedule {
   SPIN_SCHEDULE_CHECKERBOARD = 0, /* the chain above (default) */
@@ -169,6 +189,17 @@ int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits);
  * AUTO family use it from then on.  Synchronises.  Returns the chosen
  * spin_kernel value, or a negative status.  Bits never change. */
 int spin_autotune(spin_lattice* h, double beta, int sweeps);
+
+/* Select the draw source (enum spin_rng).  An LCG mode (Ising, L % 8 == 0,
+ * checkerboard schedule only) (re)starts every group's generator from its
+ * initial state; the sweeps then run one kernel per colour phase with the
+ * spins in place.  SPIN_EINVAL for an unknown mode or a lattice it cannot
+ * run; switching back to SPIN_RNG_PHILOX keeps the spins. */
+int spin_set_rng(spin_lattice* h, int rng);
+
+/* The LCG modes' generator states (uint64, one per 8-site group, n ==
+ * L^d / 8) into a host array.  Synchronous.  SPIN_ESTATE under Philox. */
+int spin_get_rng_state(const spin_lattice* h, uint64_t* out, size_t n);
 
 /* Kernel family that spin_sweep will use next (spin_kernel value). */
 int spin_get_kernel(const spin_lattice* h);

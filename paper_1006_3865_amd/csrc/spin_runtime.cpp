@@ -16,6 +16,7 @@
 #include "spin.h"
 #include "spin_batch.h"
 #include "spin_internal.h"
+#include "spin_lcg.h"
 
 namespace spin {
 
@@ -139,6 +140,8 @@ struct spin_lattice {
   int hits;             // SPIN_SCHEDULE_COARSE: k
   BatchSingle* single;  // one-task block of the LDS-resident batch kernel (allocated on first use)
   uint32_t* jn;         // EA couplings as nibble words for that kernel (packed on first use)
+  int rng;              // spin_rng
+  uint64_t* lcg;        // LCG modes: one generator state per 8-site group
 };
 
 static const uint64_t kMaxSweepIndex = (uint64_t)1 << 32;
@@ -177,6 +180,7 @@ static void destroy(spin_lattice* h) {
   h->mem.put(h->part);
   h->mem.put(h->single);
   h->mem.put(h->jn);
+  h->mem.put(h->lcg);
   delete h;
 }
 
@@ -388,6 +392,40 @@ static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int6
   return SPIN_OK;
 }
 
+// The canonical chain with LCG draws (spin_set_rng): two colour phases per sweep, records as for the
+// coarse mode.
+static int run_lcg(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM) {
+  const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
+  const uint32_t parts = measure_parts(lat_of(h));
+  if (nrec > 0)
+    if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  LcgArgs a;
+  for (int i = 0; i < 8; ++i) a.T[i] = acc.T[i];
+  a.N = h->N;
+  a.L = (uint32_t)h->L;
+  a.mode = (uint32_t)h->rng;
+  hipError_t e = hipSuccess;
+  uint32_t rec = 0;
+  for (int i = 0; i < n; ++i) {
+    for (uint32_t c = 0; c < 2 && e == hipSuccess; ++c) {
+      a.colour = c;
+      e = launch_lcg_phase(h->buf[h->cur], h->lcg, (uint32_t)h->d, a, h->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "LCG phase launch");
+    if (every > 0 && (i + 1) % every == 0) {
+      e = launch_measure(lat_of(h), Record{h->part + (size_t)rec * parts * 2}, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "measure launch");
+      ++rec;
+    }
+  }
+  if (nrec > 0) {
+    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "record finalize launch");
+  }
+  h->t += (uint64_t)n;
+  return SPIN_OK;
+}
+
 // Enqueue n sweeps; if every > 0 write records into device arrays dE, dM.
 static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
@@ -396,6 +434,7 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   if (h->t + (uint64_t)n > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index would exceed 2^32");
   if (n == 0) return SPIN_OK;
   const Accept acc = make_accept(beta, h->d);
+  if (h->rng != SPIN_RNG_PHILOX) return run_lcg(h, n, acc, every, dE, dM);
   if (h->schedule == SPIN_SCHEDULE_COARSE) return run_coarse(h, n, acc, every, dE, dM);
   Tile tile;
   const int kernel = resolve(h, &tile);
@@ -554,6 +593,8 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   h->buf[0] = h->buf[1] = nullptr;
   h->single = nullptr;
   h->jn = nullptr;
+  h->rng = SPIN_RNG_PHILOX;
+  h->lcg = nullptr;
   h->schedule = SPIN_SCHEDULE_CHECKERBOARD;
   h->coarse_tile = 0;
   h->hits = 1;
@@ -806,6 +847,7 @@ int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits) {
     return SPIN_OK;
   }
   if (schedule != SPIN_SCHEDULE_COARSE) return fail(SPIN_EINVAL, "unknown schedule %d", schedule);
+  if (h->rng != SPIN_RNG_PHILOX) return fail(SPIN_EINVAL, "the coarse schedule draws from Philox only");
   if (hits < 1) return fail(SPIN_EINVAL, "hits must be >= 1 (got %d)", hits);
   if (!coarse_supported(lat_of(h), tile))
     return fail(SPIN_EINVAL, "coarse tile %d cannot run L=%d d=%d (2D: 8, 16, 32, 64; 3D: 8, 16; L/T even)", tile,
@@ -814,6 +856,37 @@ int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits) {
   h->schedule = schedule;
   h->coarse_tile = tile;
   h->hits = hits;
+  return SPIN_OK;
+}
+
+int spin_set_rng(spin_lattice* h, int rng) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (rng == SPIN_RNG_PHILOX) {
+    h->rng = rng;
+    return SPIN_OK;
+  }
+  if (rng != SPIN_RNG_LCG32_ARRAY && rng != SPIN_RNG_LCG32_DISJOINT && rng != SPIN_RNG_LCG64_DISJOINT)
+    return fail(SPIN_EINVAL, "unknown RNG mode %d", rng);
+  if (h->J) return fail(SPIN_EINVAL, "the LCG modes run the Ising model only");
+  if (h->L % 8 != 0) return fail(SPIN_EINVAL, "the LCG modes need L %% 8 == 0 (got %d)", h->L);
+  if (h->schedule != SPIN_SCHEDULE_CHECKERBOARD) return fail(SPIN_EINVAL, "the LCG modes run the checkerboard chain");
+  if (!h->lcg) {
+    h->lcg = (uint64_t*)h->mem.get(h->N / 8 * sizeof(uint64_t));
+    if (!h->lcg) return fail(SPIN_ENOMEM, "LCG state allocation failed");
+  }
+  hipError_t e = launch_lcg_init(h->lcg, h->N / 8, (uint32_t)rng, h->seed, h->replica, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "LCG init launch");
+  h->rng = rng;
+  return SPIN_OK;
+}
+
+int spin_get_rng_state(const spin_lattice* h, uint64_t* out, size_t n) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (h->rng == SPIN_RNG_PHILOX || !h->lcg) return fail(SPIN_ESTATE, "no generator state: the RNG is Philox");
+  if (n != h->N / 8) return fail(SPIN_EINVAL, "n must equal L^d / 8");
+  hipError_t e = hipMemcpyAsync(out, h->lcg, n * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "LCG state copy");
   return SPIN_OK;
 }
 

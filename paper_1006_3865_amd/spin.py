@@ -18,6 +18,7 @@ SPIN_OK, SPIN_EINVAL, SPIN_ENOMEM, SPIN_EDEVICE, SPIN_ESTATE = 0, -1, -2, -3, -4
 SPIN_KERNEL_AUTO, SPIN_KERNEL_GENERIC, SPIN_KERNEL_RESIDENT, SPIN_KERNEL_TILED, SPIN_KERNEL_FUSED = 0, 1, 2, 3, 4
 SPIN_KERNEL_STREAM = 5
 SPIN_SCHEDULE_CHECKERBOARD, SPIN_SCHEDULE_COARSE = 0, 1
+SPIN_RNG_PHILOX, SPIN_RNG_LCG32_ARRAY, SPIN_RNG_LCG32_DISJOINT, SPIN_RNG_LCG64_DISJOINT = 0, 1, 2, 3
 KERNEL_NAMES = {0: "auto", 1: "generic", 2: "resident", 3: "tiled", 4: "fused", 5: "stream"}
 
 # Every symbol include/spin.h declares, with (restype, argtypes).
@@ -63,6 +64,8 @@ SIGNATURES = {
     "spin_get_kernel": (_c.c_int, [_P]),
     "spin_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
     "spin_set_schedule": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int]),
+    "spin_set_rng": (_c.c_int, [_P, _c.c_int]),
+    "spin_get_rng_state": (_c.c_int, [_P, _u64p, _c.c_size_t]),
     "spin_msc_create": (_P, [_c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _c.c_void_p]),
     "spin_msc_free": (None, [_P]),
     "spin_msc_sweep": (_c.c_int, [_P, _c.c_int, _c.c_double]),
@@ -331,6 +334,16 @@ class Lattice:
     def set_schedule(self, schedule, tile=0, hits=1):
         """SPIN_SCHEDULE_COARSE with tile edge and hits: the paper's coarse-tile multi-hit order."""
         _check(load().spin_set_schedule(self.h, int(schedule), int(tile), int(hits)))
+
+    def set_rng(self, rng):
+        """SPIN_RNG_PHILOX (the canonical chain) or one of the LCG modes of the RNG-quality experiment."""
+        _check(load().spin_set_rng(self.h, int(rng)))
+
+    def rng_state(self):
+        """The LCG modes' generator states, one uint64 per 8-site group."""
+        out = np.empty(self.N // 8, dtype=np.uint64)
+        _check(load().spin_get_rng_state(self.h, out.ctypes.data_as(_u64p), out.size))
+        return out
 
     def autotune(self, beta=0.44, sweeps=4):
         """Time every kernel family and tile for this shape, keep the fastest (see spin_autotune)."""
