@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-autocorr", action="store_true",
                     help="skip the multi-hit autocorrelation measurement near the critical point")
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
+    ap.add_argument("--no-rng-quality", action="store_true", help="skip the RNG-quality experiment")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     ap.add_argument("--msc-shapes", default="512x3,256x3,128x3,4096x2",
                     help="multi-spin-coded lattices as LxD, comma separated")
@@ -259,6 +260,42 @@ def bench_multihit_autocorr(torch, spin, workloads, L=64, T=16, hits=(1, 2, 4, 8
             "tile": T, "window_c": 6, "modes": out}
 
 
+def bench_rng_quality(torch, spin, workloads, L=64, sweeps=200_000, therm=10_000, chunk=20_000):
+    """The RNG-quality experiment (Sec. 4, first paragraph): the canonical 2D Ising chain at L=64 and
+    beta 0.4406868 with Philox and with the three LCG set-ups (an array of 32-bit LCGs with one
+    multiplier and random seeds; disjoint sub-sequences of one 32-bit LCG; of one 64-bit LCG); E after
+    every sweep; u and the specific heat c per site with jackknife errors (50 blocks) against the exact
+    finite-lattice values (Kaufman's partition function), as z-scores."""
+    from paper_1006_3865_amd import analysis
+    beta = workloads.BETA_2D_CRIT
+    N = L * L
+    u_ex, c_ex = analysis.exact_u_c(L, beta)
+    stream = torch.cuda.Stream()
+    names = {spin.SPIN_RNG_PHILOX: "philox4x32_10", spin.SPIN_RNG_LCG32_ARRAY: "lcg32_array_random_seeds",
+             spin.SPIN_RNG_LCG32_DISJOINT: "lcg32_disjoint_subsequences",
+             spin.SPIN_RNG_LCG64_DISJOINT: "lcg64_disjoint_subsequences"}
+    out = {}
+    for mode, name in names.items():
+        lat = spin.Lattice(0, L, 2, workloads.seed(0x31), stream=stream)
+        if mode != spin.SPIN_RNG_PHILOX:
+            lat.set_rng(mode)
+        lat.sweep(therm, beta)
+        E = torch.zeros(sweeps, dtype=torch.int64, device="cuda")
+        M = torch.zeros(sweeps, dtype=torch.int64, device="cuda")
+        t0 = time.perf_counter()
+        for c0 in range(0, sweeps, chunk):
+            lat.sweep_record_device(chunk, beta, 1, E[c0:], M[c0:])
+        lat.synchronize()
+        wall = time.perf_counter() - t0
+        lat.close()
+        u, du, c, dc = analysis.energy_stats(E.cpu().numpy(), N, beta)
+        out[name] = {"u": round(u, 6), "u_err": round(du, 6), "z_u": round((u - u_ex) / du, 2),
+                     "c": round(c, 4), "c_err": round(dc, 4), "z_c": round((c - c_ex) / dc, 2),
+                     "wall_s": round(wall, 2)}
+    return {"workload": "2D Ising L=%d at beta 0.4406868, %d sweeps after %d, E every sweep" % (L, sweeps, therm),
+            "exact_u": round(u_ex, 8), "exact_c": round(c_ex, 6), "modes": out}
+
+
 def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (4096, 2))):
     """Multi-spin-coded +-J glass: 32 realisations per word, attempts/ns (32 * L^d per sweep) at the
     middle of the batch's temperature ladder, HIP events on the handle's stream."""
@@ -448,6 +485,8 @@ def main():
     if not args.no_coarse and not args.no_autocorr:
         out["multihit_autocorr"] = bench_multihit_autocorr(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
+    if not args.no_rng_quality:
+        out["rng_quality"] = bench_rng_quality(torch, spin, workloads)
     if not args.no_msc:
         shapes = tuple(tuple(int(v) for v in t.split("x")) for t in args.msc_shapes.split(",") if t)
         out["multispin"] = bench_msc(torch, spin, workloads, shapes)

@@ -50,3 +50,32 @@ def test_constant_and_short_series():
     assert tau == 0.5
     with pytest.raises(ValueError):
         analysis.autocorrelation([1.0])
+
+
+def test_exact_u_c_against_enumeration_and_independent_kaufman():
+    import exact_ising as ex
+    for beta in (0.3, ex.BETA_C, 0.6):
+        u, c = analysis.exact_u_c(4, beta)
+        en = ex.enumeration_averages(4, beta)
+        assert u == pytest.approx(en["u"], abs=1e-12)
+        assert c == pytest.approx(en["c"], abs=1e-10)
+    for L in (8, 64):
+        u, c = analysis.exact_u_c(L, ex.BETA_C)
+        assert u == pytest.approx(ex.kaufman_u(L, ex.BETA_C), abs=1e-12)
+        assert c == pytest.approx(ex.kaufman_c(L, ex.BETA_C), abs=1e-10)
+
+
+def test_exact_u_approaches_onsager():
+    import exact_ising as ex
+    u, _ = analysis.exact_u_c(256, 0.3)
+    assert u == pytest.approx(ex.onsager_u(0.3), abs=1e-9)
+
+
+def test_energy_stats_on_independent_gaussians():
+    rng = np.random.default_rng(9)
+    N, beta, mu, sd = 100, 0.5, -150.0, 12.0
+    E = rng.normal(mu, sd, 200_000)
+    u, du, c, dc = analysis.energy_stats(E, N, beta)
+    assert abs(u - mu / N) < 4 * du and du == pytest.approx(sd / N / np.sqrt(E.size), rel=0.3)
+    c_true = beta * beta * sd * sd / N
+    assert abs(c - c_true) < 4 * dc and dc == pytest.approx(c_true * np.sqrt(2 / E.size), rel=0.3)
