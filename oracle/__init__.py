@@ -23,7 +23,11 @@ from .oracle import (  # noqa: F401
     lcg_skip,
     lcg_init,
     lcg_sweeps,
+    heis_init,
+    heis_measure,
+    heis_sweeps,
     MscChain,
     LcgChain,
+    HeisChain,
     Chain,
 )

@@ -74,6 +74,14 @@ class OracleLib:
         lib.oracle_lcg_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, i8p, i8p, u64p, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_int, i64p, i64p]
         lib.oracle_lcg_sweeps.restype = ctypes.c_int
+        f32p, f64p = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+        lib.oracle_heis_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, f32p]
+        lib.oracle_heis_init.restype = ctypes.c_int
+        lib.oracle_heis_measure.argtypes = [ctypes.c_int, ctypes.c_int, f32p, f64p, f64p]
+        lib.oracle_heis_measure.restype = None
+        lib.oracle_heis_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, f32p, ctypes.c_uint64, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int, f64p, f64p]
+        lib.oracle_heis_sweeps.restype = ctypes.c_int
         self.lib = lib
 
     def philox4x32_10(self, ctr, key):
@@ -190,6 +198,32 @@ class OracleLib:
             raise ValueError("oracle_lcg_sweeps rejected its arguments")
         return E[:nrec].copy(), M[:nrec].copy()
 
+    def heis_init(self, L, d, seed, replica=0):
+        """Heisenberg hot start: float32[N, 4] (x, y, z, 0) per site."""
+        sp = np.zeros((L ** d, 4), dtype=np.float32)
+        if self.lib.oracle_heis_init(L, d, seed, replica, _ptr(sp, ctypes.c_float)) != 0:
+            raise ValueError("oracle_heis_init rejected its arguments")
+        return sp
+
+    def heis_measure(self, L, d, spins):
+        """(E, M vector) of a Heisenberg configuration, in double."""
+        E = ctypes.c_double()
+        M = np.zeros(3, dtype=np.float64)
+        self.lib.oracle_heis_measure(L, d, _ptr(spins, ctypes.c_float), ctypes.byref(E), _ptr(M, ctypes.c_double))
+        return E.value, M
+
+    def heis_sweeps(self, L, d, spins, seed, replica, t0, n, beta, every=0):
+        """n Heisenberg sweeps in place (float32[N, 4]); records (E, |M|) after every every-th sweep."""
+        assert spins.dtype == np.float32 and spins.flags.c_contiguous and spins.shape == (L ** d, 4)
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1), dtype=np.float64)
+        M = np.zeros(max(nrec, 1), dtype=np.float64)
+        rc = self.lib.oracle_heis_sweeps(L, d, _ptr(spins, ctypes.c_float), seed, replica, t0, n, float(beta), every,
+                                         _ptr(E, ctypes.c_double), _ptr(M, ctypes.c_double))
+        if rc != 0:
+            raise ValueError("oracle_heis_sweeps rejected its arguments")
+        return E[:nrec].copy(), M[:nrec].copy()
+
 
 _default = None
 
@@ -247,6 +281,18 @@ def lcg_sweeps(L, d, J, spins, state, mode, n, beta, every=0):
     return default().lcg_sweeps(L, d, J, spins, state, mode, n, beta, every)
 
 
+def heis_init(L, d, seed, replica=0):
+    return default().heis_init(L, d, seed, replica)
+
+
+def heis_measure(L, d, spins):
+    return default().heis_measure(L, d, spins)
+
+
+def heis_sweeps(L, d, spins, seed, replica, t0, n, beta, every=0):
+    return default().heis_sweeps(L, d, spins, seed, replica, t0, n, beta, every)
+
+
 class MscChain:
     """32 multi-spin-coded +-J systems: realisations r0 + b, hot starts of replicas p0 + b."""
 
@@ -280,6 +326,24 @@ class LcgChain:
 
     def measure(self):
         return self.lib.measure(self.L, self.d, self.J, self.spins)
+
+
+class HeisChain:
+    """One classical Heisenberg lattice (float32 unit vectors) advanced by the oracle."""
+
+    def __init__(self, L, d, seed, replica=0, lib=None):
+        self.lib = lib or default()
+        self.L, self.d, self.seed, self.replica = L, d, seed, replica
+        self.spins = self.lib.heis_init(L, d, seed, replica)
+        self.t = 0
+
+    def sweep(self, n, beta, every=0):
+        E, M = self.lib.heis_sweeps(self.L, self.d, self.spins, self.seed, self.replica, self.t, n, beta, every)
+        self.t += n
+        return E, M
+
+    def measure(self):
+        return self.lib.heis_measure(self.L, self.d, self.spins)
 
 
 class Chain:

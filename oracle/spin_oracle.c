@@ -89,6 +89,20 @@
  *      mode 3 (disjoint sub-sequences of one 64-bit LCG): x0 = word 1 of
  *              that block * 2^32 + word 0; len = floor(2^64 / G).
  *  Everything else (table, acceptance compare, colour order) is as above.
+ *
+ *  Continuous spins (Sec. 4, closing paragraph: the remark on generalising to models with
+ *  continuous spins such as the Heisenberg model in single precision): the
+ *  classical Heisenberg ferromagnet, unit vectors S_s in R^3, energy
+ *  E = - sum_s sum_dir S_s . S_{s+e_dir}.  Same lattice, colours and sweep
+ *  order as the canonical chain; arithmetic in IEEE single precision.
+ *  Draw words of site s: hot start Philox (s, 0, replica, 9), update in
+ *  sweep t, colour c Philox (s, t, replica, 10 + c); u_i = (w_i >> 8) 2^-24.
+ *  A direction from (u0, u1): z = 2 u0 - 1, phi = 2 pi u1 (the float
+ *  nearest 2 pi times u1), rho = sqrt(fma(-z, z, 1)), (rho cos phi,
+ *  rho sin phi, z).  Update: h = sum of the 2d neighbour vectors (added in
+ *  the order -x, +x, -y, +y, -z, +z, each component separately); trial S'
+ *  from (u0, u1); dE = S.h - S'.h with a.h = fma(a.x, h.x, fma(a.y, h.y,
+ *  a.z * h.z)); accept iff u2 < exp(-(beta * dE)) (beta rounded to float).
  */
 #include <math.h>
 #include <stddef.h>
@@ -508,6 +522,93 @@ int oracle_lcg_sweeps(int L, int d, const int8_t* J, int8_t* spins, uint64_t* st
     }
     if (every > 0 && (i + 1) % every == 0) {
       oracle_measure(L, d, J, spins, &E[rec], &M[rec]);
+      ++rec;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------- Heisenberg (float) */
+
+static float unit_uniform(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+static void direction(uint32_t w0, uint32_t w1, float v[3]) {
+  const float z = 2.0f * unit_uniform(w0) - 1.0f;
+  const float phi = 6.28318530717958647692f * unit_uniform(w1);
+  const float rho = sqrtf(fmaf(-z, z, 1.0f));
+  v[0] = rho * cosf(phi);
+  v[1] = rho * sinf(phi);
+  v[2] = z;
+}
+
+static float dot_h(const float a[3], const float h[3]) {
+  return fmaf(a[0], h[0], fmaf(a[1], h[1], a[2] * h[2]));
+}
+
+/* Hot start: spins[4 s + 0..2] the direction of site s, [4 s + 3] = 0. */
+int oracle_heis_init(int L, int d, uint64_t seed, uint32_t replica, float* spins) {
+  if (!valid_shape(L, d)) return -1;
+  int64_t N = site_count(L, d);
+  for (int64_t s = 0; s < N; ++s) {
+    uint32_t ctr[4] = {(uint32_t)s, 0u, replica, 9u}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    direction(w[0], w[1], &spins[4 * s]);
+    spins[4 * s + 3] = 0.0f;
+  }
+  return 0;
+}
+
+/* E = -sum of bond dot products and M = (sum S), accumulated in double. */
+void oracle_heis_measure(int L, int d, const float* spins, double* E, double M[3]) {
+  int64_t N = site_count(L, d);
+  double e = 0, m[3] = {0, 0, 0};
+  for (int64_t s = 0; s < N; ++s) {
+    for (int k = 0; k < 3; ++k) m[k] += spins[4 * s + k];
+    for (int dir = 0; dir < d; ++dir) {
+      int64_t u = neighbour(s, dir, +1, L, d);
+      double b = 0;
+      for (int k = 0; k < 3; ++k) b += (double)spins[4 * s + k] * (double)spins[4 * u + k];
+      e -= b;
+    }
+  }
+  *E = e;
+  for (int k = 0; k < 3; ++k) M[k] = m[k];
+}
+
+/* n sweeps from absolute sweep t0 (records of E and |M| after every every-th
+ * sweep).  Returns 0, or -1 on bad arguments. */
+int oracle_heis_sweeps(int L, int d, float* spins, uint64_t seed, uint32_t replica, uint64_t t0, int n, double beta,
+                       int every, double* E, double* Mabs) {
+  if (!valid_shape(L, d) || n < 0 || isnan(beta) || beta < 0) return -1;
+  if (t0 + (uint64_t)n > ((uint64_t)1 << 32)) return -1;
+  const float bf = (float)beta;
+  int64_t N = site_count(L, d);
+  int rec = 0;
+  for (int i = 0; i < n; ++i) {
+    uint32_t t = (uint32_t)(t0 + (uint64_t)i);
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int64_t s = 0; s < N; ++s) {
+        if (colour_of(s, L, d) != colour) continue;
+        float h[3] = {0.0f, 0.0f, 0.0f};
+        for (int dir = 0; dir < d; ++dir) {
+          int64_t dn = neighbour(s, dir, -1, L, d), up = neighbour(s, dir, +1, L, d);
+          for (int k = 0; k < 3; ++k) h[k] = h[k] + spins[4 * dn + k];
+          for (int k = 0; k < 3; ++k) h[k] = h[k] + spins[4 * up + k];
+        }
+        uint32_t ctr[4] = {(uint32_t)s, t, replica, 10u + (uint32_t)colour};
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, w[4];
+        oracle_philox4x32_10(ctr, key, w);
+        float trial[3];
+        direction(w[0], w[1], trial);
+        const float dE = dot_h(&spins[4 * s], h) - dot_h(trial, h);
+        if (unit_uniform(w[2]) < expf(-(bf * dE)))
+          for (int k = 0; k < 3; ++k) spins[4 * s + k] = trial[k];
+      }
+    }
+    if (every > 0 && (i + 1) % every == 0) {
+      double m[3];
+      oracle_heis_measure(L, d, spins, &E[rec], m);
+      Mabs[rec] = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
       ++rec;
     }
   }

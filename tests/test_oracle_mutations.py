@@ -16,6 +16,13 @@ import bruteforce as bf
 import oracle
 
 MUTANTS = {
+    "heis_dE_sign": ("const float dE = dot_h(&spins[4 * s], h) - dot_h(trial, h);",
+                     "const float dE = dot_h(trial, h) - dot_h(&spins[4 * s], h);"),
+    "heis_phi_from_first_word": ("const float phi = 6.28318530717958647692f * unit_uniform(w1);",
+                                 "const float phi = 6.28318530717958647692f * unit_uniform(w0);"),
+    "heis_drop_upper_neighbour": ("for (int k = 0; k < 3; ++k) h[k] = h[k] + spins[4 * up + k];", "(void)up;"),
+    "heis_update_counter_colour": ("uint32_t ctr[4] = {(uint32_t)s, t, replica, 10u + (uint32_t)colour};",
+                                   "uint32_t ctr[4] = {(uint32_t)s, t, replica, 10u};"),
     "lcg64_low_word": ("return mode == 3 ? (uint32_t)(x >> 32) : (uint32_t)x;", "return (uint32_t)x;"),
     "lcg_draw_before_step": ("*st = lcg_step(mode, *st);\n        uint32_t r = lcg_draw(mode, *st);",
                              "uint32_t r = lcg_draw(mode, *st);\n        *st = lcg_step(mode, *st);"),
@@ -166,6 +173,41 @@ def _quick_pins(lib, rocrand_philox):
             return py[g]
         bf.sweep(ref, L, d, None, beta, 0, lcg_draw)
         np.testing.assert_array_equal(spins, ref)
+
+
+    # Heisenberg mode: beta = 0 takes every trial; one sweep against brute force in double precision
+    L, d, rep, hs = 4, 2, 1, 0x5A
+    sp = lib.heis_init(L, d, hs, rep)
+    lib.heis_sweeps(L, d, sp, hs, rep, 0, 1, 0.0)
+    N = L * L
+    col = [((s % L) + (s // L)) & 1 for s in range(N)]
+    w = rocrand_philox([(s, 0, rep, 10 + col[s]) for s in range(N)], (hs, 0))
+    u = (np.asarray(w, dtype=np.uint64) >> 8).astype(np.float64) * 2.0 ** -24
+    zz = 2 * u[:, 0] - 1
+    ph = 2 * math.pi * u[:, 1]
+    rr = np.sqrt(1 - zz * zz)
+    np.testing.assert_allclose(sp[:, :3], np.stack([rr * np.cos(ph), rr * np.sin(ph), zz], axis=1), atol=2e-6)
+    beta = 0.7
+    sp = lib.heis_init(L, d, hs, rep)
+    S = sp[:, :3].astype(np.float64).copy()
+
+    def e_of(S):
+        g = S.reshape(L, L, 3)
+        return -float((g * np.roll(g, -1, axis=1)).sum() + (g * np.roll(g, -1, axis=0)).sum())
+    for c in (0, 1):
+        for s in range(N):
+            if col[s] != c:
+                continue
+            ww = rocrand_philox([(s, 0, rep, 10 + c)], (hs, 0))[0]
+            uu = (np.asarray(ww, dtype=np.uint64) >> 8).astype(np.float64) * 2.0 ** -24
+            z1, p1 = 2 * uu[0] - 1, 2 * math.pi * uu[1]
+            trial = np.array([math.sqrt(1 - z1 * z1) * math.cos(p1), math.sqrt(1 - z1 * z1) * math.sin(p1), z1])
+            e0, old = e_of(S), S[s].copy()
+            S[s] = trial
+            if not uu[2] < math.exp(-beta * (e_of(S) - e0)):
+                S[s] = old
+    lib.heis_sweeps(L, d, sp, hs, rep, 0, 1, beta)
+    np.testing.assert_allclose(sp[:, :3], S, atol=2e-5)
 
 
 def test_unmodified_oracle_passes_quick_pins(oracle_mod, rocrand_philox):
