@@ -317,6 +317,46 @@ int spin_batch_set_workgroups_per_cu(spin_batch* b, int wgs);
 /* Wait for the batch's queued work. */
 int spin_batch_synchronize(spin_batch* b);
 
+/* ---------------------------------------------------- continuous spins
+ * Sec. 4, closing paragraph (the method generalises to continuous spins such
+ * as the Heisenberg model, where single-precision floating point comes into
+ * play): the classical Heisenberg ferromagnet, unit vectors S_s in R^3,
+ * E = - sum_s sum_dir S_s . S_{s+e_dir}, periodic L^d (d = 2, 3, L even),
+ * the red/black sweep of the canonical chain, arithmetic in float.
+ * Site s draws Philox (s, 0, replica, 9) for its hot start and
+ * (s, t, replica, 10 + c) in sweep t, colour c; with u_i = (w_i >> 8) 2^-24
+ * a direction is z = 2 u0 - 1, phi = 2 pi u1, rho = sqrt(fma(-z, z, 1)),
+ * (rho cos phi, rho sin phi, z); the trial S' replaces S iff
+ * u2 < exp(-(beta dE)), dE = S.h - S'.h with h the sum of the 2d neighbour
+ * vectors (order -x, +x, -y, +y, -z, +z) and a.h = fma(a.x, h.x,
+ * fma(a.y, h.y, a.z h.z)).  Spins live on the device as float4 (x, y, z, 0).
+ * A sweep is L^d attempts. */
+typedef struct spin_heis spin_heis;
+
+/* NULL on error (spin_last_error). */
+spin_heis* spin_heis_create(int L, int d, uint64_t seed, uint32_t replica, void* stream);
+void spin_heis_free(spin_heis* h);                 /* NULL-safe; waits for queued work */
+
+/* n >= 0 sweeps at beta >= 0 (rounded to float); asynchronous. */
+int spin_heis_sweep(spin_heis* h, int n, double beta);
+
+/* As spin_heis_sweep, recording after every every-th sweep E[r] and |M|[r]
+ * (n/every records, HOST arrays of double, sums accumulated in double).
+ * Synchronises. */
+int spin_heis_sweep_record(spin_heis* h, int n, double beta, int every, double* E, double* Mabs);
+
+/* Current E and magnetisation vector M[3] (host, double).  Synchronises. */
+int spin_heis_measure(spin_heis* h, double* E, double* M);
+
+/* Spins into a host array of n == 4 L^d floats (x, y, z, 0 per site). */
+int spin_heis_get_spins(const spin_heis* h, float* out, size_t n);
+
+/* Absolute index of the next sweep. */
+uint64_t spin_heis_sweeps_done(const spin_heis* h);
+
+/* Wait for the handle's queued work. */
+int spin_heis_synchronize(spin_heis* h);
+
 /* ---------------------------------------------------- multi-spin coding
  * Sec. 4, last paragraph (many disorder realisations at once, combined with
  * multi-spin coding): 32 +-J systems of edge L (L % 8 == 0, d = 2 or 3) in

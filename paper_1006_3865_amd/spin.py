@@ -27,6 +27,8 @@ _P = _c.c_void_p
 _i8p = _c.POINTER(_c.c_int8)
 _i64p = _c.POINTER(_c.c_int64)
 _u64p = _c.POINTER(_c.c_uint64)
+_f32p = _c.POINTER(_c.c_float)
+_f64p = _c.POINTER(_c.c_double)
 ALLOC_FN = _c.CFUNCTYPE(_c.c_void_p, _c.c_size_t, _c.c_void_p)
 RELEASE_FN = _c.CFUNCTYPE(None, _c.c_void_p, _c.c_void_p)
 
@@ -65,6 +67,14 @@ SIGNATURES = {
     "spin_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
     "spin_set_schedule": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int]),
     "spin_set_rng": (_c.c_int, [_P, _c.c_int]),
+    "spin_heis_create": (_P, [_c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32, _P]),
+    "spin_heis_free": (None, [_P]),
+    "spin_heis_sweep": (_c.c_int, [_P, _c.c_int, _c.c_double]),
+    "spin_heis_sweep_record": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _f64p, _f64p]),
+    "spin_heis_measure": (_c.c_int, [_P, _f64p, _f64p]),
+    "spin_heis_get_spins": (_c.c_int, [_P, _f32p, _c.c_size_t]),
+    "spin_heis_sweeps_done": (_c.c_uint64, [_P]),
+    "spin_heis_synchronize": (_c.c_int, [_P]),
     "spin_get_rng_state": (_c.c_int, [_P, _u64p, _c.c_size_t]),
     "spin_msc_create": (_P, [_c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _c.c_void_p]),
     "spin_msc_free": (None, [_P]),
@@ -561,3 +571,56 @@ class Msc:
 
     def synchronize(self):
         _check(load().spin_msc_synchronize(self.h))
+
+
+class Heis:
+    """Classical Heisenberg lattice (continuous spins, float) owned by the library."""
+
+    def __init__(self, L, d, seed, replica=0, stream=None):
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        self.h = load().spin_heis_create(int(L), int(d), int(seed), int(replica), sp)
+        if not self.h:
+            raise SpinError(SPIN_EINVAL, load().spin_last_error().decode())
+        self.L, self.d, self.N = L, d, L ** d
+
+    def close(self):
+        if self.h:
+            load().spin_heis_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n, beta):
+        _check(load().spin_heis_sweep(self.h, int(n), float(beta)))
+
+    def sweep_record(self, n, beta, every):
+        nrec = n // every if every > 0 else 0
+        E = np.zeros(max(nrec, 1), dtype=np.float64)
+        M = np.zeros(max(nrec, 1), dtype=np.float64)
+        _check(load().spin_heis_sweep_record(self.h, int(n), float(beta), int(every), E.ctypes.data_as(_f64p),
+                                             M.ctypes.data_as(_f64p)))
+        return E[:nrec], M[:nrec]
+
+    def measure(self):
+        E = np.zeros(1, dtype=np.float64)
+        M = np.zeros(3, dtype=np.float64)
+        _check(load().spin_heis_measure(self.h, E.ctypes.data_as(_f64p), M.ctypes.data_as(_f64p)))
+        return float(E[0]), M
+
+    def spins(self):
+        out = np.empty((self.N, 4), dtype=np.float32)
+        _check(load().spin_heis_get_spins(self.h, out.ctypes.data_as(_f32p), out.size))
+        return out
+
+    @property
+    def t(self):
+        return int(load().spin_heis_sweeps_done(self.h))
+
+    def synchronize(self):
+        _check(load().spin_heis_synchronize(self.h))
