@@ -64,6 +64,7 @@ def parse():
                     help="skip the multi-hit autocorrelation measurement near the critical point")
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
     ap.add_argument("--no-rng-quality", action="store_true", help="skip the RNG-quality experiment")
+    ap.add_argument("--no-heisenberg", action="store_true", help="skip the continuous-spin (Heisenberg) model")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     ap.add_argument("--msc-shapes", default="512x3,256x3,128x3,4096x2",
                     help="multi-spin-coded lattices as LxD, comma separated")
@@ -296,6 +297,30 @@ def bench_rng_quality(torch, spin, workloads, L=64, sweeps=200_000, therm=10_000
             "exact_u": round(u_ex, 8), "exact_c": round(c_ex, 6), "modes": out}
 
 
+def bench_heisenberg(torch, spin, workloads, shapes=((4096, 2), (256, 3)), beta=0.7):
+    """Continuous spins (classical Heisenberg, float): attempts/ns over back-to-back sweeps (one launch
+    per colour), HIP events on the handle's stream, with the HBM rate of the algorithmic traffic (each
+    site's float4 read and written once and read once more as a neighbour per sweep: 48 B per attempt)."""
+    stream = torch.cuda.Stream()
+    out = {}
+    for (L, d) in shapes:
+        h = spin.Heis(L, d, workloads.seed(0x12), stream=stream)
+        N = L ** d
+        n = max(4, min(200, int(2e9 / N)))
+        h.sweep(2, beta)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        h.sweep(n, beta)
+        b.record(stream)
+        h.synchronize()
+        ms = a.elapsed_time(b)
+        h.close()
+        rate = N * n / (ms * 1e6)
+        out["d%d_L%d" % (d, L)] = {"attempts_per_ns": round(rate, 1), "ms_per_sweep": round(ms / n, 4), "sweeps": n,
+                                   "alg_hbm_GBps": round(48 * rate, 1), "alg_hbm_frac": round(48 * rate / HBM_PEAK_GBS, 4)}
+    return {"workload": "classical Heisenberg, float, beta %g" % beta, "rates": out}
+
+
 def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (4096, 2))):
     """Multi-spin-coded +-J glass: 32 realisations per word, attempts/ns (32 * L^d per sweep) at the
     middle of the batch's temperature ladder, HIP events on the handle's stream."""
@@ -485,6 +510,8 @@ def main():
     if not args.no_coarse and not args.no_autocorr:
         out["multihit_autocorr"] = bench_multihit_autocorr(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
+    if not args.no_heisenberg:
+        out["heisenberg"] = bench_heisenberg(torch, spin, workloads)
     if not args.no_rng_quality:
         out["rng_quality"] = bench_rng_quality(torch, spin, workloads)
     if not args.no_msc:
