@@ -188,13 +188,46 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* scratch /* NT/6
   return s;
 }
 
+// Sum over the 64 lanes of a wavefront (every lane active) of counts below
+// 2^26 per lane: an inclusive scan inside each row of 16 lanes by DPP row
+// shifts of 1, 2, 4 and 8 lanes (lanes shifted in from outside the row read
+// 0), after which lanes 15, 31, 47 and 63 hold the row totals, read with
+// readlane.
+__device__ __forceinline__ int64_t wave_count_dpp(uint32_t v) {
+  int s = (int)v;
+  s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xf, 0xf, true);  // row_shr:1
+  s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xf, 0xf, true);  // row_shr:2
+  s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xf, true);  // row_shr:4
+  s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xf, true);  // row_shr:8
+  return (int64_t)__builtin_amdgcn_readlane(s, 15) + (int64_t)__builtin_amdgcn_readlane(s, 31) +
+         (int64_t)__builtin_amdgcn_readlane(s, 47) + (int64_t)__builtin_amdgcn_readlane(s, 63);
+}
+
+// Workgroup sum of per-thread counts below 2^26 (DPP within waves, LDS across
+// them); every thread must call it; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ int64_t block_count_dpp(uint32_t v, int64_t* scratch /* NT/64 */) {
+  const int64_t w = wave_count_dpp(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) scratch[wid] = w;
+  __syncthreads();
+  int64_t s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += scratch[i];
+  }
+  __syncthreads();
+  return s;
+}
+
 // Store this workgroup's counts in its record slots.  Every thread calls it
-// (it contains barriers).  red: >= NT/64 int64 in LDS.
+// (it contains barriers); the per-thread counts are below 2^26.  red: >= NT/64
+// int64 in LDS.
 template <int NT>
 __device__ __forceinline__ void record_block(int64_t unsat, int64_t neg, const Record& R,
                                              int64_t* red) {
-  const int64_t bu = block_sum<NT>(unsat, red);
-  const int64_t bn = block_sum<NT>(neg, red);
+  const int64_t bu = block_count_dpp<NT>((uint32_t)unsat, red);
+  const int64_t bn = block_count_dpp<NT>((uint32_t)neg, red);
   if (threadIdx.x == 0) {
     const unsigned wg = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     R.part[2 * wg] = bu;
