@@ -326,3 +326,48 @@ def test_autotune_keeps_chain_and_parity(oracle_mod, model, L, d):
     np.testing.assert_array_equal(M, Mo)
     np.testing.assert_array_equal(lat.spins(), ch.spins)
     lat.close()
+
+
+def check_sweep_sampled(oracle_mod, old, new, L, d, J, seed, replica, t, beta, n_sites, rng_seed):
+    """One canonical sweep verified site by site on a sample: a colour-0 site is decided from the state
+    before the sweep (its neighbours are colour 1), a colour-1 site from its old value and the final
+    colour-0 neighbours; each decision is Eq. 2 with the site's own Philox word."""
+    T = oracle_mod.table(beta, d)
+    N = L ** d
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    step = (1, L, L * L)
+    rng = np.random.default_rng(rng_seed)
+    for s in rng.choice(N, n_sites, replace=False).tolist():
+        x = [s % L, (s // L) % L, s // (L * L)][:d]
+        c = sum(x) & 1
+        nb = new if c == 1 else old
+        h = 0
+        for dr in range(d):
+            sp = s + step[dr] if x[dr] + 1 < L else s - (L - 1) * step[dr]
+            sm = s - step[dr] if x[dr] > 0 else s + (L - 1) * step[dr]
+            jp = int(J[dr * N + s]) if J is not None else 1
+            jm = int(J[dr * N + sm]) if J is not None else 1
+            h += jp * int(nb[sp]) + jm * int(nb[sm])
+        k = int(old[s]) * h
+        r = int(oracle_mod.philox4x32_10((s >> 3, t, replica, c), key)[(s >> 1) & 3])
+        flip = r < int(T[(k + 2 * d) // 2])
+        assert int(new[s]) == (-int(old[s]) if flip else int(old[s])), ("site", s, "colour", c)
+
+
+@pytest.mark.parametrize("model,L,d,beta", [(0, 16384, 2, B_CRIT), (0, 1024, 3, B_3D), (1, 512, 3, 1.0)])
+def test_largest_sizes_sampled(oracle_mod, model, L, d, beta):
+    """The largest lattices the specialised kernels take (2D L = 16384: two 8-site groups per thread of
+    the row-streaming kernel; 3D L = 1024) and a 3D +-J lattice of the benchmark's size: the second
+    sweep checked site by site on a sample."""
+    seed, rep = workloads.seed(0xA0 + d), 1
+    cs = workloads.seed(0x11) if model else None
+    lat = make(model, L, d, seed, rep, None, cs)
+    note("largest", model, L, d, "kernel", spin.KERNEL_NAMES[lat.kernel])
+    lat.sweep(1, beta)
+    old = lat.spins()
+    t = lat.t
+    lat.sweep(1, beta)
+    new = lat.spins()
+    lat.close()
+    J = oracle_mod.couplings(L, d, cs, 0) if model else None
+    check_sweep_sampled(oracle_mod, old, new, L, d, J, seed, rep, t, beta, 3000, 0xA1)
