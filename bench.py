@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-spin-coded +-J glass")
     ap.add_argument("--no-rng-quality", action="store_true", help="skip the RNG-quality experiment")
     ap.add_argument("--no-heisenberg", action="store_true", help="skip the continuous-spin (Heisenberg) model")
+    ap.add_argument("--coarse-only", default="", help="L,T,k: time only this coarse-tile configuration")
+    ap.add_argument("--heis-shapes", default="4096x2,256x3", help="Heisenberg lattices as LxD, comma separated")
     ap.add_argument("--batched-sweeps", type=int, default=5000)
     ap.add_argument("--msc-shapes", default="512x3,256x3,128x3,4096x2",
                     help="multi-spin-coded lattices as LxD, comma separated")
@@ -78,6 +80,8 @@ KERNEL_SOURCES = {
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_msc_stream": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),
+    "k_coarse": ("spin_coarse_kernels.hip", "spin_nibble.h", "spin_device.h"),
+    "k_heis_phase": ("spin_heis_kernels.hip", "spin_heis.h", "spin_device.h"),
 }
 
 
@@ -207,8 +211,12 @@ def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64),
                 lat.synchronize()
                 out["L%d_T%d_k%d" % (L, T, k)] = round(n * k * L * L / (a.elapsed_time(b) * 1e6), 2)
         lat.close()
-    return {"workload": "ising2d coarse-tile multi-hit", "beta": workloads.BETA_2D_CRIT,
-            "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
+    res = {"workload": "ising2d coarse-tile multi-hit", "beta": workloads.BETA_2D_CRIT,
+           "unit": "spin-flip attempts/ns", "attempts_per_ns": out}
+    traffic = profiled_traffic("k_coarse", 8192)
+    if traffic is not None:  # counted HBM bytes per launch (one tile parity) of the L=8192, T=32, k=8 case
+        res["traffic_L8192_T32_k8_bytes_per_launch"] = traffic
+    return res
 
 
 def bench_multihit_autocorr(torch, spin, workloads, L=64, T=16, hits=(1, 2, 4, 8), sweeps=200_000, therm=5_000,
@@ -316,8 +324,13 @@ def bench_heisenberg(torch, spin, workloads, shapes=((4096, 2), (256, 3)), beta=
         ms = a.elapsed_time(b)
         h.close()
         rate = N * n / (ms * 1e6)
-        out["d%d_L%d" % (d, L)] = {"attempts_per_ns": round(rate, 1), "ms_per_sweep": round(ms / n, 4), "sweeps": n,
-                                   "alg_hbm_GBps": round(48 * rate, 1), "alg_hbm_frac": round(48 * rate / HBM_PEAK_GBS, 4)}
+        rec = {"attempts_per_ns": round(rate, 1), "ms_per_sweep": round(ms / n, 4), "sweeps": n,
+               "alg_hbm_GBps": round(48 * rate, 1), "alg_hbm_frac": round(48 * rate / HBM_PEAK_GBS, 4)}
+        traffic = profiled_traffic("k_heis_phase", L) if d == 2 else None
+        if traffic is not None:  # counted HBM bytes per colour launch
+            rec["traffic_bytes_per_sweep"] = 2 * traffic
+            rec["traffic_GBps"] = round(2 * traffic / (ms / n * 1e6), 1)
+        out["d%d_L%d" % (d, L)] = rec
     return {"workload": "classical Heisenberg, float, beta %g" % beta, "rates": out}
 
 
@@ -506,12 +519,17 @@ def main():
         out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps)
         print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
     if not args.no_coarse:
-        out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
-    if not args.no_coarse and not args.no_autocorr:
+        if args.coarse_only:
+            cL, cT, ck = (int(v) for v in args.coarse_only.split(","))
+            out["coarse_schedule"] = bench_coarse(torch, spin, workloads, (cL,), (cT,), (ck,))
+        else:
+            out["coarse_schedule"] = bench_coarse(torch, spin, workloads)
+    if not args.no_coarse and not args.no_autocorr and not args.coarse_only:
         out["multihit_autocorr"] = bench_multihit_autocorr(torch, spin, workloads)
         print("coarse:", json.dumps(out["coarse_schedule"]), file=sys.stderr, flush=True)
     if not args.no_heisenberg:
-        out["heisenberg"] = bench_heisenberg(torch, spin, workloads)
+        hshapes = tuple(tuple(int(v) for v in t.split("x")) for t in args.heis_shapes.split(",") if t)
+        out["heisenberg"] = bench_heisenberg(torch, spin, workloads, hshapes)
     if not args.no_rng_quality:
         out["rng_quality"] = bench_rng_quality(torch, spin, workloads)
     if not args.no_msc:
