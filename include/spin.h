@@ -326,11 +326,17 @@ int spin_batch_synchronize(spin_batch* b);
  * Site s draws Philox (s, 0, replica, 9) for its hot start and
  * (s, t, replica, 10 + c) in sweep t, colour c; with u_i = (w_i >> 8) 2^-24
  * a direction is z = 2 u0 - 1, phi = 2 pi u1, rho = sqrt(fma(-z, z, 1)),
- * (rho cos phi, rho sin phi, z); the trial S' replaces S iff
- * u2 < exp(-(beta dE)), dE = S.h - S'.h with h the sum of the 2d neighbour
- * vectors (order -x, +x, -y, +y, -z, +z) and a.h = fma(a.x, h.x,
- * fma(a.y, h.y, a.z h.z)).  Spins live on the device as float4 (x, y, z, 0).
- * A sweep is L^d attempts. */
+ * (rho cos phi, rho sin phi, z); the trial S' replaces S iff dE <= 0 or
+ * u2 < exp(-(beta dE)) (the Metropolis rule, Sec. 3, Eq. 2), dE = S.h - S'.h
+ * with h the sum of the 2d neighbour vectors (order -x, +x, -y, +y, -z, +z)
+ * and a.h = fma(a.x, h.x, fma(a.y, h.y, a.z h.z)).  cos, sin and exp are
+ * evaluated by one stated method, each step a single IEEE float operation:
+ * the angle reduced to its octant (o = floor(8 u1), exact) and Taylor
+ * polynomials of cos and sin on [0, pi/4] to x^10 and x^9; exp(y) for
+ * -87 < y < 0 as 2^k e^r with k = floor(y log2 e + 1/2), r = y - k ln 2
+ * (ln 2 in two parts) and e^r by its Taylor polynomial to r^7; y <= -87
+ * rejects.  Every result is therefore a definite float.  Spins live on the
+ * device as float4 (x, y, z, 0).  A sweep is L^d attempts. */
 typedef struct spin_heis spin_heis;
 
 /* NULL on error (spin_last_error). */
@@ -348,11 +354,21 @@ int spin_heis_sweep_record(spin_heis* h, int n, double beta, int every, double* 
 /* Current E and magnetisation vector M[3] (host, double).  Synchronises. */
 int spin_heis_measure(spin_heis* h, double* E, double* M);
 
-/* Spins into a host array of n == 4 L^d floats (x, y, z, 0 per site). */
+/* Spins into a host array of n == 4 L^d floats (x, y, z, 0 per site).
+ * Synchronous. */
 int spin_heis_get_spins(const spin_heis* h, float* out, size_t n);
+
+/* Spins from a host array of n == 4 L^d floats (x, y, z, 0 per site):
+ * components finite, the fourth 0 (SPIN_EINVAL otherwise); taken as given,
+ * not normalised.  Synchronous. */
+int spin_heis_set_spins(spin_heis* h, const float* in, size_t n);
 
 /* Absolute index of the next sweep. */
 uint64_t spin_heis_sweeps_done(const spin_heis* h);
+
+/* Set the absolute index of the next sweep (resume from a saved state with
+ * spin_heis_set_spins); index + later sweeps <= 2^32. */
+int spin_heis_set_sweeps_done(spin_heis* h, uint64_t t);
 
 /* Wait for the handle's queued work. */
 int spin_heis_synchronize(spin_heis* h);

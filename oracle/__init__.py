@@ -23,6 +23,8 @@ from .oracle import (  # noqa: F401
     lcg_skip,
     lcg_init,
     lcg_sweeps,
+    heis_accept,
+    heis_direction,
     heis_init,
     heis_measure,
     heis_sweeps,

@@ -82,6 +82,10 @@ class OracleLib:
         lib.oracle_heis_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, f32p, ctypes.c_uint64, ctypes.c_uint32,
                                            ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_int, f64p, f64p]
         lib.oracle_heis_sweeps.restype = ctypes.c_int
+        lib.oracle_heis_direction.argtypes = [ctypes.c_uint32, ctypes.c_uint32, f32p]
+        lib.oracle_heis_direction.restype = None
+        lib.oracle_heis_accept.argtypes = [ctypes.c_float, ctypes.c_float]
+        lib.oracle_heis_accept.restype = ctypes.c_int
         self.lib = lib
 
     def philox4x32_10(self, ctr, key):
@@ -212,6 +216,16 @@ class OracleLib:
         self.lib.oracle_heis_measure(L, d, _ptr(spins, ctypes.c_float), ctypes.byref(E), _ptr(M, ctypes.c_double))
         return E.value, M
 
+    def heis_direction(self, w0, w1):
+        """Trial direction (float32[3]) of the Philox words w0, w1."""
+        v = np.zeros(3, dtype=np.float32)
+        self.lib.oracle_heis_direction(int(w0), int(w1), _ptr(v, ctypes.c_float))
+        return v
+
+    def heis_accept(self, u, y):
+        """The acceptance test u < exp(y) for float u and y, as the sweep takes it."""
+        return bool(self.lib.oracle_heis_accept(float(u), float(y)))
+
     def heis_sweeps(self, L, d, spins, seed, replica, t0, n, beta, every=0):
         """n Heisenberg sweeps in place (float32[N, 4]); records (E, |M|) after every every-th sweep."""
         assert spins.dtype == np.float32 and spins.flags.c_contiguous and spins.shape == (L ** d, 4)
@@ -287,6 +301,14 @@ def heis_init(L, d, seed, replica=0):
 
 def heis_measure(L, d, spins):
     return default().heis_measure(L, d, spins)
+
+
+def heis_direction(w0, w1):
+    return default().heis_direction(w0, w1)
+
+
+def heis_accept(u, y):
+    return default().heis_accept(u, y)
 
 
 def heis_sweeps(L, d, spins, seed, replica, t0, n, beta, every=0):

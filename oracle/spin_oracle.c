@@ -97,12 +97,24 @@
  *  order as the canonical chain; arithmetic in IEEE single precision.
  *  Draw words of site s: hot start Philox (s, 0, replica, 9), update in
  *  sweep t, colour c Philox (s, t, replica, 10 + c); u_i = (w_i >> 8) 2^-24.
- *  A direction from (u0, u1): z = 2 u0 - 1, phi = 2 pi u1 (the float
- *  nearest 2 pi times u1), rho = sqrt(fma(-z, z, 1)), (rho cos phi,
- *  rho sin phi, z).  Update: h = sum of the 2d neighbour vectors (added in
- *  the order -x, +x, -y, +y, -z, +z, each component separately); trial S'
- *  from (u0, u1); dE = S.h - S'.h with a.h = fma(a.x, h.x, fma(a.y, h.y,
- *  a.z * h.z)); accept iff u2 < exp(-(beta * dE)) (beta rounded to float).
+ *  A direction from (u0, u1): z = 2 u0 - 1, rho = sqrt(fma(-z, z, 1)),
+ *  (rho cos phi, rho sin phi, z) with phi = 2 pi u1.  cos and sin are
+ *  evaluated as follows (every step a single IEEE float operation, so the
+ *  result is a definite float): the octant o = floor(8 u1) and r = 8 u1 - o
+ *  (both exact); a = r for even o, 1 - r for odd o (exact); x = a * (pi/4
+ *  rounded to float); C = 1 - x^2/2! + ... - x^10/10!, S = x - x^3/3! + ...
+ *  + x^9/9! by Horner steps in x^2 with fma (coefficients 1/n! rounded to
+ *  float); odd octants swap C and S; quadrant o>>1 rotates (C, S) by
+ *  multiples of pi/2.  Update: h = sum of the 2d neighbour vectors (added
+ *  in the order -x, +x, -y, +y, -z, +z, each component separately); trial
+ *  S' from (u0, u1); dE = S.h - S'.h with a.h = fma(a.x, h.x, fma(a.y, h.y,
+ *  a.z * h.z)); the Metropolis rule (Sec. 3, Eq. 2) accepts every dE <= 0
+ *  (also at beta = inf, where beta * 0 would be undefined); otherwise
+ *  y = -(beta * dE) (beta rounded to float) and accept iff y >= 0 (beta =
+ *  0), or y > -87 and u2 < p with p = 2^k e^r: k = floor(y log2(e) +
+ *  1/2) (fma), r = y - k ln2 in two fma steps with ln2 split into a high
+ *  part exact in float and the rest, e^r = 1 + r + ... + r^7/7! by Horner
+ *  with fma, and the scaling by 2^k exact (ldexp).
  */
 #include <math.h>
 #include <stddef.h>
@@ -532,14 +544,71 @@ int oracle_lcg_sweeps(int L, int d, const int8_t* J, int8_t* spins, uint64_t* st
 
 static float unit_uniform(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 
+/* cos and sin of x in [0, pi/4] (Taylor polynomials, Horner steps in x^2). */
+static void cos_sin_octant(float x, float* c, float* sn) {
+  const float x2 = x * x;
+  float pc = -1.0f / 3628800.0f;
+  pc = fmaf(pc, x2, 1.0f / 40320.0f);
+  pc = fmaf(pc, x2, -1.0f / 720.0f);
+  pc = fmaf(pc, x2, 1.0f / 24.0f);
+  pc = fmaf(pc, x2, -0.5f);
+  *c = fmaf(pc, x2, 1.0f);
+  float ps = 1.0f / 362880.0f;
+  ps = fmaf(ps, x2, -1.0f / 5040.0f);
+  ps = fmaf(ps, x2, 1.0f / 120.0f);
+  ps = fmaf(ps, x2, -1.0f / 6.0f);
+  *sn = fmaf(ps * x2, x, x);
+}
+
 static void direction(uint32_t w0, uint32_t w1, float v[3]) {
   const float z = 2.0f * unit_uniform(w0) - 1.0f;
-  const float phi = 6.28318530717958647692f * unit_uniform(w1);
   const float rho = sqrtf(fmaf(-z, z, 1.0f));
-  v[0] = rho * cosf(phi);
-  v[1] = rho * sinf(phi);
+  const float t = 8.0f * unit_uniform(w1);
+  const int o = (int)t;
+  const float r = t - (float)o;
+  const float a = (o & 1) ? 1.0f - r : r;
+  float c, sn;
+  cos_sin_octant(a * 0.785398163397448309616f, &c, &sn);
+  if (o & 1) {
+    const float tmp = c;
+    c = sn;
+    sn = tmp;
+  }
+  float cx, sy;
+  switch (o >> 1) {
+    case 0: cx = c; sy = sn; break;
+    case 1: cx = -sn; sy = c; break;
+    case 2: cx = -c; sy = -sn; break;
+    default: cx = sn; sy = -c; break;
+  }
+  v[0] = rho * cx;
+  v[1] = rho * sy;
   v[2] = z;
 }
+
+/* Metropolis acceptance u < exp(y) for the float y = -(beta dE). */
+static int accept_exp(float u, float y) {
+  if (y >= 0.0f) return 1;
+  if (!(y > -87.0f)) return 0;    /* exp(y) < 2^-125: p stays a normal float above this */
+  const float k = floorf(fmaf(y, 1.44269504088896340736f, 0.5f));
+  float r = fmaf(-k, 0.693145751953125f, y);       /* ln2 high part, exact in float */
+  r = fmaf(-k, 1.428606765330187045e-06f, r);      /* the rest of ln2 */
+  float p = 1.0f / 5040.0f;
+  p = fmaf(p, r, 1.0f / 720.0f);
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
+  return u < ldexpf(p, (int)k);
+}
+
+/* The two float steps above, exported so that tests can pin them against cos, sin and exp in
+ * double precision. */
+void oracle_heis_direction(uint32_t w0, uint32_t w1, float v[3]) { direction(w0, w1, v); }
+
+int oracle_heis_accept(float u, float y) { return accept_exp(u, y); }
 
 static float dot_h(const float a[3], const float h[3]) {
   return fmaf(a[0], h[0], fmaf(a[1], h[1], a[2] * h[2]));
@@ -601,7 +670,7 @@ int oracle_heis_sweeps(int L, int d, float* spins, uint64_t seed, uint32_t repli
         float trial[3];
         direction(w[0], w[1], trial);
         const float dE = dot_h(&spins[4 * s], h) - dot_h(trial, h);
-        if (unit_uniform(w[2]) < expf(-(bf * dE)))
+        if (dE <= 0.0f || accept_exp(unit_uniform(w[2]), -(bf * dE)))
           for (int k = 0; k < 3; ++k) spins[4 * s + k] = trial[k];
       }
     }

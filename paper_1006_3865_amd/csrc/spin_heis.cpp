@@ -183,7 +183,27 @@ int spin_heis_get_spins(const spin_heis* h, float* out, size_t n) {
   return SPIN_OK;
 }
 
+int spin_heis_set_spins(spin_heis* h, const float* in, size_t n) {
+  if (!h || !in) return hfail(SPIN_EINVAL, "NULL argument");
+  if (n != 4 * h->N) return hfail(SPIN_EINVAL, "n must equal 4 L^d");
+  for (size_t i = 0; i < n; ++i) {
+    if (!std::isfinite(in[i])) return hfail(SPIN_EINVAL, "spin component %zu is not finite", i);
+    if (i % 4 == 3 && in[i] != 0.0f) return hfail(SPIN_EINVAL, "fourth component of site %zu must be 0", i / 4);
+  }
+  hipError_t e = hipMemcpyAsync(h->S, in, h->N * sizeof(float4), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hfail(SPIN_EDEVICE, "Heisenberg set spins: %s", hipGetErrorString(e));
+  return SPIN_OK;
+}
+
 uint64_t spin_heis_sweeps_done(const spin_heis* h) { return h ? h->t : 0; }
+
+int spin_heis_set_sweeps_done(spin_heis* h, uint64_t t) {
+  if (!h) return hfail(SPIN_EINVAL, "NULL handle");
+  if (t > ((uint64_t)1 << 32)) return hfail(SPIN_EINVAL, "sweep index must be <= 2^32");
+  h->t = t;
+  return SPIN_OK;
+}
 
 int spin_heis_synchronize(spin_heis* h) {
   if (!h) return hfail(SPIN_EINVAL, "NULL handle");

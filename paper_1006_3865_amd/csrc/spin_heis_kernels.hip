@@ -10,24 +10,81 @@
 //   (rho cos phi, rho sin phi, z);
 //   h = neighbour vectors added in the order -x, +x, -y, +y, -z, +z;
 //   dE = S.h - S'.h, a.h = fma(a.x, h.x, fma(a.y, h.y, a.z h.z));
-//   accept iff u2 < exp(-(beta dE)).
-// The float operations are written out (explicit fma, no reassociation), so
-// they round as stated; cos, sin and exp are the device library's.
+//   accept iff dE <= 0 (the Metropolis rule of Sec. 3, Eq. 2, also at beta =
+//   inf) or u2 < exp(-(beta dE)).
+// cos, sin and exp are evaluated by one stated method (octant reduction of
+// u1 and Taylor polynomials; Cody-Waite reduction by ln 2 and a Taylor
+// polynomial, scaled by 2^k), every step a single IEEE float operation with
+// fused multiply-adds written out and contraction switched off, so each
+// result is a definite float.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "spin_device.h"
 #include "spin_heis.h"
 
+#pragma clang fp contract(off)
+
 namespace spin {
 
 __device__ __forceinline__ float heis_uniform(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 
+// cos and sin of x in [0, pi/4]: Taylor polynomials to x^10 and x^9, Horner steps in x^2.
+__device__ __forceinline__ void heis_cos_sin(float x, float& c, float& sn) {
+  const float x2 = x * x;
+  float pc = -1.0f / 3628800.0f;
+  pc = __builtin_fmaf(pc, x2, 1.0f / 40320.0f);
+  pc = __builtin_fmaf(pc, x2, -1.0f / 720.0f);
+  pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
+  pc = __builtin_fmaf(pc, x2, -0.5f);
+  c = __builtin_fmaf(pc, x2, 1.0f);
+  float ps = 1.0f / 362880.0f;
+  ps = __builtin_fmaf(ps, x2, -1.0f / 5040.0f);
+  ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);
+  ps = __builtin_fmaf(ps, x2, -1.0f / 6.0f);
+  sn = __builtin_fmaf(ps * x2, x, x);
+}
+
+// Direction from (u0, u1): z = 2 u0 - 1; the angle 2 pi u1 reduced to its octant o = floor(8 u1) and
+// the offset r = 8 u1 - o (exact), the polynomial taken at r pi/4 (even o) or (1 - r) pi/4 (odd o,
+// cos and sin swapped), then rotated by the quadrant o >> 1.
 __device__ __forceinline__ float4 heis_direction(uint32_t w0, uint32_t w1) {
   const float z = 2.0f * heis_uniform(w0) - 1.0f;
-  const float phi = 6.28318530717958647692f * heis_uniform(w1);
   const float rho = sqrtf(__builtin_fmaf(-z, z, 1.0f));
-  return make_float4(rho * cosf(phi), rho * sinf(phi), z, 0.0f);
+  const float t = 8.0f * heis_uniform(w1);
+  const int o = (int)t;
+  const float r = t - (float)o;
+  float c, sn;
+  heis_cos_sin(((o & 1) ? 1.0f - r : r) * 0.785398163397448309616f, c, sn);
+  if (o & 1) {
+    const float tmp = c;
+    c = sn;
+    sn = tmp;
+  }
+  const int q = o >> 1;
+  const float cx = q == 0 ? c : q == 1 ? -sn : q == 2 ? -c : sn;
+  const float sy = q == 0 ? sn : q == 1 ? c : q == 2 ? -sn : -c;
+  return make_float4(rho * cx, rho * sy, z, 0.0f);
+}
+
+// u < exp(y): true for y >= 0, false for y <= -87 (exp(y) < 2^-125), else against 2^k e^r with
+// k = floor(y log2(e) + 1/2), r = y - k ln 2 (ln 2 split into a high part exact in float and the
+// rest) and e^r by its Taylor polynomial to r^7.
+__device__ __forceinline__ bool heis_accept(float u, float y) {
+  if (y >= 0.0f) return true;
+  if (!(y > -87.0f)) return false;
+  const float k = __builtin_floorf(__builtin_fmaf(y, 1.44269504088896340736f, 0.5f));
+  float r = __builtin_fmaf(-k, 0.693145751953125f, y);
+  r = __builtin_fmaf(-k, 1.428606765330187045e-06f, r);
+  float p = 1.0f / 5040.0f;
+  p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+  p = __builtin_fmaf(p, r, 0.5f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  return u < __builtin_ldexpf(p, (int)k);
 }
 
 __device__ __forceinline__ float heis_dot(const float4& a, const float4& h) {
@@ -72,7 +129,7 @@ __global__ void k_heis_phase(float4* __restrict__ S, HeisArgs a) {
     const float4 cur = S[s];
     const float4 trial = heis_direction(w[0], w[1]);
     const float dE = heis_dot(cur, h) - heis_dot(trial, h);
-    if (heis_uniform(w[2]) < expf(-(a.beta * dE))) S[s] = trial;
+    if (dE <= 0.0f || heis_accept(heis_uniform(w[2]), -(a.beta * dE))) S[s] = trial;
   }
 }
 

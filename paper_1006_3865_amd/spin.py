@@ -74,6 +74,8 @@ SIGNATURES = {
     "spin_heis_measure": (_c.c_int, [_P, _f64p, _f64p]),
     "spin_heis_get_spins": (_c.c_int, [_P, _f32p, _c.c_size_t]),
     "spin_heis_sweeps_done": (_c.c_uint64, [_P]),
+    "spin_heis_set_spins": (_c.c_int, [_P, _f32p, _c.c_size_t]),
+    "spin_heis_set_sweeps_done": (_c.c_int, [_P, _c.c_uint64]),
     "spin_heis_synchronize": (_c.c_int, [_P]),
     "spin_get_rng_state": (_c.c_int, [_P, _u64p, _c.c_size_t]),
     "spin_msc_create": (_P, [_c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32, _c.c_uint64, _c.c_uint32, _c.c_void_p]),
@@ -618,9 +620,17 @@ class Heis:
         _check(load().spin_heis_get_spins(self.h, out.ctypes.data_as(_f32p), out.size))
         return out
 
+    def set_spins(self, spins):
+        a = np.ascontiguousarray(spins, dtype=np.float32).reshape(self.N, 4)
+        _check(load().spin_heis_set_spins(self.h, a.ctypes.data_as(_f32p), a.size))
+
     @property
     def t(self):
         return int(load().spin_heis_sweeps_done(self.h))
+
+    @t.setter
+    def t(self, value):
+        _check(load().spin_heis_set_sweeps_done(self.h, int(value)))
 
     def synchronize(self):
         _check(load().spin_heis_synchronize(self.h))

@@ -1,11 +1,9 @@
 """GPU parity of the classical Heisenberg mode (continuous spins, float) against the oracle.
 
-Bar (floating point): every accept decision equal, spin components within
-1e-6 (a few ulps: the device's cos, sin and exp may differ from the host
-library's by an ulp; every other operation is written to round the same way,
-and an accepted spin is a fresh trial, so differences do not accumulate),
-E and |M| within 1e-5 per site.  A differing decision would move a spin by
-O(1) and fail the component check.
+Bar: every spin component bit for bit (each step of the update, including
+cos, sin and exp, is a single IEEE float operation in an order both sides
+state, so each result is a definite float); E and |M|, sums of float
+products accumulated in double in different orders, within 1e-9 per site.
 """
 import math
 import sys
@@ -38,19 +36,19 @@ def test_heis_matches_oracle(oracle_mod, L, d):
     note("heis", L, d)
     h = spin.Heis(L, d, seed, replica=3)
     ch = oracle_mod.HeisChain(L, d, seed, 3)
-    np.testing.assert_allclose(h.spins(), ch.spins, atol=1e-6, rtol=0)
+    np.testing.assert_array_equal(h.spins(), ch.spins)
     N = L ** d
-    for beta in (0.3, 0.7, 0.0, math.inf, 2.0, 1.1):
+    for beta in (0.3, 0.7, 0.0, math.inf, 2.0, 1.1, 40.0):
         E, M = h.sweep_record(2, beta, 1)
         Eo, Mo = ch.sweep(2, beta, every=1)
-        np.testing.assert_allclose(h.spins(), ch.spins, atol=1e-6, rtol=0, err_msg="beta %g" % beta)
-        np.testing.assert_allclose(E, Eo, atol=1e-5 * N, rtol=0)
-        np.testing.assert_allclose(M, Mo, atol=1e-5 * N, rtol=0)
+        np.testing.assert_array_equal(h.spins(), ch.spins, err_msg="beta %g" % beta)
+        np.testing.assert_allclose(E, Eo, atol=1e-9 * N, rtol=0)
+        np.testing.assert_allclose(M, Mo, atol=1e-9 * N, rtol=0)
     E, Mv = h.measure()
     Eo, Mvo = ch.measure()
-    assert abs(E - Eo) <= 1e-5 * N
-    np.testing.assert_allclose(Mv, Mvo, atol=1e-5 * N, rtol=0)
-    assert h.t == ch.t == 12
+    assert abs(E - Eo) <= 1e-9 * N
+    np.testing.assert_allclose(Mv, Mvo, atol=1e-9 * N, rtol=0)
+    assert h.t == ch.t == 14
     h.close()
 
 
@@ -90,6 +88,42 @@ def test_heis_full_size_sampled_sites():
     assert judged > 2900
 
 
+def test_heis_zero_energy_change_at_zero_temperature(oracle_mod):
+    """Colour-1 spins (0, 0, s(x) s(y)), s = (+, +, -, -), cancel around every colour-0 site of the
+    L = 4 square lattice, so dE = 0 exactly there; at beta = inf each such trial is accepted."""
+    L, d, seed = 4, 2, workloads.seed(0x9A)
+    ch = oracle_mod.HeisChain(L, d, seed, 0)
+    sgn = [1.0, 1.0, -1.0, -1.0]
+    for s in range(L * L):
+        if (s % L + s // L) & 1:
+            ch.spins[s] = [0.0, 0.0, sgn[s % L] * sgn[s // L], 0.0]
+    h = spin.Heis(L, d, seed, 0)
+    h.set_spins(ch.spins)
+    np.testing.assert_array_equal(h.spins(), ch.spins)
+    before = ch.spins.copy()
+    h.sweep(1, math.inf)
+    ch.sweep(1, math.inf)
+    np.testing.assert_array_equal(h.spins(), ch.spins)
+    even = [s for s in range(L * L) if (s % L + s // L) & 1 == 0]
+    assert not np.any(np.all(ch.spins[even] == before[even], axis=1))
+    h.close()
+
+
+@pytest.mark.parametrize("L,d", [(32, 2), (8, 3)])
+def test_heis_resume_from_saved_state(oracle_mod, L, d):
+    seed, rep = workloads.seed(0x9B + d), 5
+    ch = oracle_mod.HeisChain(L, d, seed, rep)
+    ch.sweep(3, 0.8)
+    h = spin.Heis(L, d, seed, rep)
+    h.set_spins(ch.spins)
+    h.t = ch.t
+    h.sweep(4, 0.8)
+    ch.sweep(4, 0.8)
+    assert h.t == ch.t == 7
+    np.testing.assert_array_equal(h.spins(), ch.spins)
+    h.close()
+
+
 def test_heis_rejects_bad_shapes():
     for (L, d) in ((7, 2), (2, 2), (8, 4)):
         with pytest.raises(spin.SpinError):
@@ -97,4 +131,15 @@ def test_heis_rejects_bad_shapes():
     h = spin.Heis(8, 2, 1)
     with pytest.raises(spin.SpinError):
         h.sweep(1, -1.0)
+    good = h.spins()
+    for bad in (np.where(np.arange(good.size).reshape(good.shape) == 5, np.nan, good),
+                np.where(np.arange(good.size).reshape(good.shape) == 7, 1.0, good)):
+        with pytest.raises(spin.SpinError):
+            h.set_spins(bad)
+    with pytest.raises(spin.SpinError):
+        load_n = spin.load().spin_heis_set_spins(h.h, good.ctypes.data_as(spin._f32p), good.size - 4)
+        spin._check(load_n)
+    with pytest.raises(spin.SpinError):
+        h.t = (1 << 32) + 1
+    np.testing.assert_array_equal(h.spins(), good)
     h.close()

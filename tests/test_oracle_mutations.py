@@ -18,8 +18,14 @@ import oracle
 MUTANTS = {
     "heis_dE_sign": ("const float dE = dot_h(&spins[4 * s], h) - dot_h(trial, h);",
                      "const float dE = dot_h(trial, h) - dot_h(&spins[4 * s], h);"),
-    "heis_phi_from_first_word": ("const float phi = 6.28318530717958647692f * unit_uniform(w1);",
-                                 "const float phi = 6.28318530717958647692f * unit_uniform(w0);"),
+    "heis_phi_from_first_word": ("const float t = 8.0f * unit_uniform(w1);", "const float t = 8.0f * unit_uniform(w0);"),
+    "heis_odd_octant_not_reflected": ("const float a = (o & 1) ? 1.0f - r : r;", "const float a = r;"),
+    "heis_third_quadrant_sign": ("case 2: cx = -c; sy = -sn; break;", "case 2: cx = c; sy = -sn; break;"),
+    "heis_cos_series_short": ("pc = fmaf(pc, x2, 1.0f / 40320.0f);", "pc = fmaf(pc, x2, 0.0f);"),
+    "heis_exp_ln2_tail_dropped": ("r = fmaf(-k, 1.428606765330187045e-06f, r);", "r = fmaf(-k, 0.0f, r);"),
+    "heis_exp_series_short": ("p = fmaf(p, r, 1.0f / 720.0f);", "p = fmaf(p, r, 0.0f);"),
+    "heis_exp_cutoff_early": ("if (!(y > -87.0f)) return 0;", "if (!(y > -60.0f)) return 0;"),
+    "heis_zero_dE_rejected": ("if (dE <= 0.0f || accept_exp(", "if (dE < 0.0f || accept_exp("),
     "heis_drop_upper_neighbour": ("for (int k = 0; k < 3; ++k) h[k] = h[k] + spins[4 * up + k];", "(void)up;"),
     "heis_update_counter_colour": ("uint32_t ctr[4] = {(uint32_t)s, t, replica, 10u + (uint32_t)colour};",
                                    "uint32_t ctr[4] = {(uint32_t)s, t, replica, 10u};"),
@@ -208,6 +214,26 @@ def _quick_pins(lib, rocrand_philox):
                 S[s] = old
     lib.heis_sweeps(L, d, sp, hs, rep, 0, 1, beta)
     np.testing.assert_allclose(sp[:, :3], S, atol=2e-5)
+    # the float direction and acceptance steps against cos, sin and exp in double precision
+    hw = np.random.default_rng(9).integers(0, 1 << 32, size=(600, 2), dtype=np.uint64).tolist()
+    for a, b in hw + [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [1 << 31, 1 << 29], [1 << 31, 3 << 29]]:
+        z1, p1 = 2 * ((a >> 8) * 2.0 ** -24) - 1, 2 * math.pi * ((b >> 8) * 2.0 ** -24)
+        r1 = math.sqrt(1 - z1 * z1)
+        np.testing.assert_allclose(lib.heis_direction(a, b), [r1 * math.cos(p1), r1 * math.sin(p1), z1], atol=3e-7)
+    for y in np.linspace(-86.9, -1e-4, 300).astype(np.float32).tolist():
+        e = math.exp(y)
+        assert lib.heis_accept(e * (1 - 1e-6), y) and not lib.heis_accept(e * (1 + 1e-6), y), y
+    # dE = 0 at beta = inf is accepted: colour-1 spins (0, 0, s(x) s(y)), s = (+, +, -, -), cancel
+    # around every colour-0 site of the L = 4 square lattice
+    sp = lib.heis_init(4, 2, hs, 0)
+    for s in range(16):
+        if (s % 4 + s // 4) & 1:
+            sp[s] = [0.0, 0.0, (1.0 if s % 4 < 2 else -1.0) * (1.0 if s // 4 < 2 else -1.0), 0.0]
+    lib.heis_sweeps(4, 2, sp, hs, 0, 0, 1, math.inf)
+    for s in range(16):
+        if (s % 4 + s // 4) & 1 == 0:
+            ww = rocrand_philox([(s, 0, 0, 10)], (hs, 0))[0]
+            np.testing.assert_array_equal(sp[s, :3], lib.heis_direction(int(ww[0]), int(ww[1])))
 
 
 def test_unmodified_oracle_passes_quick_pins(oracle_mod, rocrand_philox):
