@@ -31,10 +31,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit lane op per lane per clock
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic 32-bit lane operations per spin-flip attempt: Philox4x32-10 gives 4 words per
-# 10 rounds of (2 32x32->64 multiplies + 2 three-input XORs) = 10 per attempt; the update of an
-# 8-site group (4 attempts) takes 4 byte alignments, 2d mask-XORs, 2d-2 byte adds... for 2D:
-# 4 + 8 + 4 sums + 4 x (extract, compare, select) + 2 flip XORs + 1 counter = 31 -> 7.75.
-ALG_OPS_PER_ATTEMPT = {2: 10.0 + 31 / 4.0, 3: 10.0 + (4 + 12 + 8 + 12 + 2 + 1) / 4.0}
+# 10 rounds of (2 32x32->64 multiplies + 2 three-input XORs) = 10 per attempt.  The update of an
+# 8-site group (4 attempts of one colour) with the active sites packed into one dword: gathers
+# (active bytes, other-colour bytes, the shifted side, 2d - 2 row/plane neighbours), 2d mask-XORs,
+# the sums of 2d terms (2 in 2D, 3 in 3D), 4 x (extract, compare, select), 2 flip XORs and 1
+# counter: 2D 5 + 4 + 2 + 12 + 2 + 1 = 26 -> 6.5; 3D 7 + 6 + 3 + 12 + 2 + 1 = 31 -> 7.75.
+ALG_OPS_PER_ATTEMPT = {2: 10.0 + 26 / 4.0, 3: 10.0 + 31 / 4.0}
 BYTES_PER_ATTEMPT = 2.0  # int8 spin read once and written once per sweep (Ising)
 # LDS: 256 CUs x 128 bytes per clock x 2.4 GHz.  Algorithmic LDS bytes of the streaming kernels per
 # 8-site group and sweep: the row (2D) or plane-slice row (3D) stored once (8 B); per colour unit the
@@ -75,8 +77,8 @@ def parse():
 
 # Source files that define each profiled kernel (its counters are valid while they are unchanged).
 KERNEL_SOURCES = {
-    "k_stream2d": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h"),
-    "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h"),
+    "k_stream2d": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
+    "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_msc_stream": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),

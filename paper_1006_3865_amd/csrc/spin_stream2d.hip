@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "spin_device.h"
+#include "spin_packed.h"
 #include "spin_phase.h"
 
 namespace spin {
@@ -14,7 +15,8 @@ namespace spin {
 // rows in LDS (row k of the strip, k = y - (y0-2), lives in slot k & 7; a
 // row's bytes sit at [16, 16+L) with x = L-16..L-1 copied to [0,16) and
 // x = 0..15 to [16+L, 32+L)).  Step i (i = 0..H+2), with a = y0-1+i:
-//   load row a+2 into registers (stored to LDS at the end of the step);
+//   load row a+2 into registers (stored to LDS at the end of the step; the
+//     last two steps reload row y0+H+1 into slots no longer read);
 //   colour 0 on row a (i <= H+1): reads rows a-1..a+1, writes row a in LDS;
 //   colour 1 on row a-2 (i >= 3): reads rows a-3..a-1, writes dst;
 //   barrier.
@@ -60,9 +62,13 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
   constexpr uint32_t L = C::L, GPR = C::GPR, RBS = C::RBS;
   const uint32_t H = c.H, y0 = c.y0, t = c.t;
   if (i >= H + 3) return;
+  // Row k = i + 3 of the strip for steps i <= H; the two steps after that
+  // fetch row H + 3 again (an L2 hit) into ring slots no step reads any more
+  // (slot (i + 3) & 7 holds row i - 5; colour 1 reads rows i - 2 .. i and the
+  // closing count reads row H + 1), so that the load and its LDS store are
+  // unconditional and the load never waits on the previous step's stores.
   uint2 nxt[G];
-  const bool do_load = (i <= H);
-  if (do_load) c.get_row(wrap_row(y0 + i + 3, 2u, L), nxt);
+  c.get_row(wrap_row(y0 + (i <= H ? i : H) + 3, 2u, L), nxt);
   if (i <= H + 1) {
     // colour 0 on row a = y0 - 1 + i (strip row k = i + 1); parity of a is (i+1) & 1
     const uint32_t y = wrap_row(y0 + i + 1, 2u, L);
@@ -80,22 +86,24 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
       uint32_t rnd[4];
       philox_lane(y * GPR + g, c.U0, *c.keys, rnd);
       const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
-      uint32_t S0, S1;
-      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      const uint32_t Sp = unsat_packed<2>((S + 1) & 1, cc.x, cc.y, lw, rw, o0, o1);
       uint32_t c0 = cc.x, c1 = cc.y;
-      apply_group_p<(S + 1) & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
+      apply_packed<NEVER>((S + 1) & 1, c0, c1, Sp, rnd, c.bound, c.never4);
       *reinterpret_cast<uint2*>(row + 8 * g) = make_uint2(c0, c1);
       if (g >= GPR - 2) *reinterpret_cast<uint2*>(row - 16 + 8 * (g - (GPR - 2))) = make_uint2(c0, c1);
       if (g < 2) *reinterpret_cast<uint2*>(row + L + 8 * g) = make_uint2(c0, c1);
     }
   }
-  if (i >= 3) {
-    // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1
+  // colour 1 on row b = y0 + i - 3 (strip row k = i - 1); parity of (1 + b) is i & 1.
+  // Its results go to dst after the LDS store of the loaded row below, so that
+  // the wait for that load does not include these stores.
+  uint2 res[G];
+  const bool col1 = (i >= 3);
+  if (col1) {
     const uint32_t y = y0 + i - 3u;
     int8_t* row = c.ring + ((S + 7) & 7) * RBS + 16;
     const int8_t* up = c.ring + ((S + 6) & 7) * RBS + 16;
     const int8_t* dn = c.ring + (S & 7) * RBS + 16;
-    int8_t* out = c.dst + (uint64_t)y * L;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const uint32_t g = t + NT * j;
@@ -107,11 +115,10 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
       uint32_t rnd[4];
       philox_lane(y * GPR + g, c.U1, *c.keys, rnd);
       const uint32_t o0[2] = {u2.x, d2.x}, o1[2] = {u2.y, d2.y};
-      uint32_t S0, S1;
-      unsat_ising<2>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+      const uint32_t Sp = unsat_packed<2>(S & 1, cc.x, cc.y, lw, rw, o0, o1);
       uint32_t c0 = cc.x, c1 = cc.y;
-      apply_group_p<S & 1, NEVER>(c0, c1, S0, S1, rnd, c.bound, c.never4);
-      *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(c0, c1);
+      apply_packed<NEVER>(S & 1, c0, c1, Sp, rnd, c.bound, c.never4);
+      res[j] = make_uint2(c0, c1);
       if (MEAS) {
         // E and M of the swept lattice, counted on final values:
         //  - row b's negative spins;
@@ -139,7 +146,12 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
       }
     }
   }
-  if (do_load) c.put_row((S + 3) & 7, nxt);
+  c.put_row((S + 3) & 7, nxt);
+  if (col1) {
+    int8_t* out = c.dst + (uint64_t)(y0 + i - 3u) * L;
+#pragma unroll
+    for (int j = 0; j < G; ++j) *reinterpret_cast<uint2*>(out + 8 * (t + NT * j)) = res[j];
+  }
   __syncthreads();
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "spin_device.h"
+#include "spin_packed.h"
 #include "spin_phase.h"
 
 namespace spin {
@@ -92,10 +93,10 @@ __device__ __forceinline__ void stream3_group(const Stream3Ctx<TY, W, G>& c, uin
   const uint32_t cbase = (uint32_t)((((uint64_t)z * L + y) * L) >> 3);
   philox_lane(cbase + g, C ? c.U1 : c.U0, *c.keys, rnd);
   const uint32_t o0[4] = {ym.x, yp.x, a2.x, b2.x}, o1[4] = {ym.y, yp.y, a2.y, b2.y};
-  uint32_t S0, S1;
-  unsat_ising<4>(cc.x, cc.y, lw, rw, o0, o1, S0, S1);
+  const uint32_t P = (C + y + z) & 1u;
+  const uint32_t Sp = unsat_packed<4>(P, cc.x, cc.y, lw, rw, o0, o1);
   uint32_t c0 = cc.x, c1 = cc.y;
-  apply_group<NEVER>(c0, c1, S0, S1, (C + y + z) & 1u, rnd, c.bound, c.never4);
+  apply_packed<NEVER>(P, c0, c1, Sp, rnd, c.bound, c.never4);
   o_lo = c0;
   o_hi = c1;
 }
