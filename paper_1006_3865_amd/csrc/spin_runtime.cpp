@@ -236,7 +236,7 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
   if (kernel == SPIN_KERNEL_FUSED) {
     if (h->d == 3) return Tile{L, 8, 64, 640};
     if (L == 8192) return Tile{8192, 16, 0, 1024};
-    if (L == 4096) return Tile{4096, 16, 0, 512};
+    if (L == 4096) return Tile{4096, 8, 0, 512};
     if (L % 512 == 0 && L >= 1024) return Tile{512, 16, 0, 256};
     if (L % 256 == 0) return Tile{256, 32, 0, 256};
     if (L % 128 == 0) return Tile{128, 16, 0, 256};

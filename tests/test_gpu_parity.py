@@ -252,7 +252,7 @@ def test_torch_allocator(oracle_mod, gpu):
 
 
 @pytest.mark.parametrize("tile,L", [
-    ((4096, 16, 0, 512), 4096), ((4096, 64, 0, 512), 4096), ((4096, 8, 0, 256), 4096),
+    ((4096, 16, 0, 512), 4096), ((4096, 8, 0, 512), 4096), ((4096, 64, 0, 512), 4096), ((4096, 8, 0, 256), 4096),
     ((8192, 32, 0, 1024), 8192), ((8192, 16, 0, 512), 8192),
 ])
 def test_ising2d_streaming_rows(oracle_mod, tile, L):
