@@ -173,9 +173,11 @@ __global__ __launch_bounds__(NT) void k_measure_sites(const int8_t* __restrict__
 }
 
 // Row-structured version (L % 16 == 0): each workgroup takes RPB lattice rows
-// (a row = L sites along x at fixed y, z); a thread takes 16 sites of a row,
-// counts negative spins and unsatisfied +x/+y/+z bonds from sign bits, with
-// 32-bit index arithmetic (rows < 2^32, bytes per row < 2^17).
+// (a row = L sites along x at fixed y, z), cut into 16-site chunks that its
+// threads take in turn across rows (so short rows still occupy every
+// thread); a thread counts negative spins and unsatisfied +x/+y/+z bonds of
+// its chunk from sign bits, with 32-bit index arithmetic (rows < 2^32, bytes
+// per row < 2^17, chunks per workgroup < 2^32).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ sp,
                                                      const int8_t* __restrict__ J, uint32_t L,
@@ -185,15 +187,20 @@ __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ 
   const uint32_t msb = 0x80808080u;
   const uint32_t cpr = L / 16;
   int64_t unsat = 0, neg = 0;
-  const uint32_t row_end = min(nrows, (blockIdx.x + 1) * rpb);
-  for (uint32_t row = blockIdx.x * rpb; row < row_end; ++row) {
+  const uint32_t row0 = blockIdx.x * rpb;
+  const uint32_t row_end = min(nrows, row0 + rpb);
+  const uint32_t chunks = (row_end - row0) * cpr;
+  for (uint32_t k = threadIdx.x; k < chunks; k += NT) {
+    const uint32_t rk = k / cpr;
+    const uint32_t row = row0 + rk;
+    const uint32_t cx = k - rk * cpr;
     const uint32_t y = row % L;
     const uint32_t z = row / L;  // 0 in 2D
     const uint64_t base = (uint64_t)row * L;
     const uint64_t below = base + ((y + 1 == L) ? -(int64_t)(L - 1) * L : (int64_t)L);
     const uint64_t plane = (uint64_t)L * L;
     const uint64_t behind = (d == 3) ? (base + ((z + 1 == L) ? -(int64_t)(L - 1) * plane : (int64_t)plane)) : 0;
-    for (uint32_t cx = threadIdx.x; cx < cpr; cx += NT) {
+    {
       const uint32_t x = 16 * cx;
       const uint4 c = *reinterpret_cast<const uint4*>(sp + base + x);
       const uint32_t nx = *reinterpret_cast<const uint32_t*>(sp + base + ((x + 16 == L) ? 0 : x + 16));
@@ -214,11 +221,11 @@ __global__ __launch_bounds__(NT) void k_measure_rows(const int8_t* __restrict__ 
       if (d == 3) dz = *reinterpret_cast<const uint4*>(sp + behind + x);
       const uint32_t zw[4] = {dz.x, dz.y, dz.z, dz.w};
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        neg += __popc(cw[k] & msb);
-        unsat += __popc(xor3(cw[k], rw[k], jxw[k]) & msb);
-        unsat += __popc(xor3(cw[k], yw[k], jyw[k]) & msb);
-        if (d == 3) unsat += __popc(xor3(cw[k], zw[k], jzw[k]) & msb);
+      for (int w = 0; w < 4; ++w) {
+        neg += __popc(cw[w] & msb);
+        unsat += __popc(xor3(cw[w], rw[w], jxw[w]) & msb);
+        unsat += __popc(xor3(cw[w], yw[w], jyw[w]) & msb);
+        if (d == 3) unsat += __popc(xor3(cw[w], zw[w], jzw[w]) & msb);
       }
     }
   }
