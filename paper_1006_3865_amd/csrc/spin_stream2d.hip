@@ -25,13 +25,19 @@ namespace spin {
 // colour-0 bytes finished one or more steps earlier.  The step loop is
 // unrolled over the ring period so that ring slots and row parities (y0 is
 // even) are compile-time constants.
+// Rows move between HBM and registers by buffer instructions: a descriptor
+// over the lattice's L*L bytes (third word 0x00020000, the raw-buffer format
+// of the gfx9 family), the row offset y*L as a scalar operand and the
+// thread's byte offset 8*(t + NT*j) as the vector operand, so no per-lane
+// 64-bit address arithmetic remains.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <int NT, int G>
 struct StreamCtx {
   static constexpr uint32_t L = 8u * NT * G;
   static constexpr uint32_t GPR = L / 8;
   static constexpr uint32_t RBS = L + 32;
-  const int8_t* __restrict__ src;
-  int8_t* __restrict__ dst;
+  __amdgpu_buffer_rsrc_t rsrc, rdst;
   int8_t* ring;
   const uint32_t* bound;
   const RoundKeys* keys;
@@ -39,9 +45,18 @@ struct StreamCtx {
   uint32_t never4, y0, H, t;
 
   __device__ __forceinline__ void get_row(uint32_t y, uint2 (&v)[G]) const {
-    const int8_t* rowp = src + (uint64_t)y * L;
 #pragma unroll
-    for (int j = 0; j < G; ++j) v[j] = *reinterpret_cast<const uint2*>(rowp + 8 * (t + NT * j));
+    for (int j = 0; j < G; ++j) {
+      const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, 8u * (t + NT * j), y * L, 0);
+      v[j] = make_uint2(w.x, w.y);
+    }
+  }
+  __device__ __forceinline__ void put_out(uint32_t y, const uint2 (&v)[G]) const {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const u32x2 w = {v[j].x, v[j].y};
+      __builtin_amdgcn_raw_buffer_store_b64(w, rdst, 8u * (t + NT * j), y * L, 0);
+    }
   }
   __device__ __forceinline__ void put_row(uint32_t slot, const uint2 (&v)[G]) const {
     int8_t* row = ring + slot * RBS;
@@ -147,11 +162,7 @@ __device__ __forceinline__ void stream_step(const StreamCtx<NT, G>& c, uint32_t 
     }
   }
   c.put_row((S + 3) & 7, nxt);
-  if (col1) {
-    int8_t* out = c.dst + (uint64_t)(y0 + i - 3u) * L;
-#pragma unroll
-    for (int j = 0; j < G; ++j) *reinterpret_cast<uint2*>(out + 8 * (t + NT * j)) = res[j];
-  }
+  if (col1) c.put_out(y0 + i - 3u, res);
   __syncthreads();
 }
 
@@ -164,8 +175,8 @@ __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
   // then the 8-row ring
   __shared__ __align__(16) int8_t lds[32 + 8 * C::RBS];
   C c;
-  c.src = src;
-  c.dst = dst;
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(C::L * C::L), 0x00020000);
+  c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(C::L * C::L), 0x00020000);
   c.ring = lds + 32;
   c.bound = reinterpret_cast<const uint32_t*>(lds);
   c.keys = &a.keys;
