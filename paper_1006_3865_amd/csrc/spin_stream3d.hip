@@ -25,6 +25,13 @@ namespace spin {
 // The 2TY+2 row-units of a step are dealt to the waves round-robin.  The
 // step loop is unrolled over the ring period (slots compile-time; with z0
 // even the plane parities are too).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Rows move between HBM and registers by buffer instructions over the
+// lattice's L^3 bytes (at most 2^30; third descriptor word 0x00020000, the
+// raw-buffer format of the gfx9 family): the row offset (z L + y) L is a
+// scalar operand and the thread's byte offset 8 (lane + 64 j) the vector
+// operand, so no per-lane 64-bit address arithmetic remains.
 template <int TY, int W, int G>
 struct Stream3Ctx {
   static constexpr uint32_t L = 512u * G;
@@ -34,8 +41,7 @@ struct Stream3Ctx {
   static constexpr uint32_t PB = RP * RB;
   static constexpr int NT = 64 * W;
   static constexpr int RPW = (RP + W - 1) / W;  // plane rows loaded per wave
-  const int8_t* __restrict__ src;
-  int8_t* __restrict__ dst;
+  __amdgpu_buffer_rsrc_t rsrc, rdst;
   int8_t* ring;
   const uint32_t* bound;
   const RoundKeys* keys;
@@ -48,9 +54,12 @@ struct Stream3Ctx {
       const uint32_t rr = wave + W * q;
       if (rr < RP) {
         const uint32_t y = wrap_row(y0 + rr, 2u, L);
-        const int8_t* rowp = src + ((uint64_t)z * L + y) * L;
+        const uint32_t roff = (z * L + y) * L;
 #pragma unroll
-        for (int j = 0; j < G; ++j) v[q][j] = *reinterpret_cast<const uint2*>(rowp + 8 * (lane + 64 * j));
+        for (int j = 0; j < G; ++j) {
+          const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rsrc, 8u * (lane + 64 * j), roff, 0);
+          v[q][j] = make_uint2(w.x, w.y);
+        }
       }
     }
   }
@@ -78,7 +87,7 @@ __device__ __forceinline__ void stream3_group(const Stream3Ctx<TY, W, G>& c, uin
                                               uint32_t z, uint32_t g, uint32_t& o_lo,
                                               uint32_t& o_hi) {
   using X = Stream3Ctx<TY, W, G>;
-  constexpr uint32_t L = X::L, RB = X::RB, PB = X::PB;
+  constexpr uint32_t L = X::L, GPR = X::GPR, RB = X::RB, PB = X::PB;
   const int8_t* row = c.ring + PC * PB + r * RB + 16;
   const int8_t* zm = c.ring + PM * PB + r * RB + 16;
   const int8_t* zp = c.ring + PP * PB + r * RB + 16;
@@ -90,7 +99,7 @@ __device__ __forceinline__ void stream3_group(const Stream3Ctx<TY, W, G>& c, uin
   const uint32_t lw = *reinterpret_cast<const uint32_t*>(row + 8 * g - 4);
   const uint32_t rw = *reinterpret_cast<const uint32_t*>(row + 8 * g + 8);
   uint32_t rnd[4];
-  const uint32_t cbase = (uint32_t)((((uint64_t)z * L + y) * L) >> 3);
+  const uint32_t cbase = (z * L + y) * GPR;  // < 2^27 for L <= 1024
   philox_lane(cbase + g, C ? c.U1 : c.U0, *c.keys, rnd);
   const uint32_t o0[4] = {ym.x, yp.x, a2.x, b2.x}, o1[4] = {ym.y, yp.y, a2.y, b2.y};
   const uint32_t P = (C + y + z) & 1u;
@@ -161,11 +170,11 @@ __device__ __forceinline__ void stream3_step(const Stream3Ctx<TY, W, G>& c, uint
 #pragma unroll
     for (int q = 0; q < N1; ++q) {
       if (2u + c.wave + W * q > TY + 1u) break;
-      int8_t* out = c.dst + ((uint64_t)zb * L + y1v[q]) * L;
+      const uint32_t roff = (zb * L + y1v[q]) * L;
 #pragma unroll
       for (int j = 0; j < G; ++j) {
-        const uint32_t g = c.lane + 64 * j;
-        *reinterpret_cast<uint2*>(out + 8 * g) = make_uint2(v1[q][j][0], v1[q][j][1]);
+        const u32x2 w = {v1[q][j][0], v1[q][j][1]};
+        __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * (c.lane + 64 * j), roff, 0);
       }
     }
   }
@@ -180,8 +189,8 @@ __global__ __launch_bounds__(64 * W) void k_stream3d(const int8_t* __restrict__ 
   using X = Stream3Ctx<TY, W, G>;
   __shared__ __align__(16) int8_t lds[32 + 6 * X::PB];
   X c;
-  c.src = src;
-  c.dst = dst;
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(X::L * X::L * X::L), 0x00020000);
+  c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(X::L * X::L * X::L), 0x00020000);
   c.ring = lds + 32;
   c.bound = reinterpret_cast<const uint32_t*>(lds);
   c.keys = &a.keys;
