@@ -262,6 +262,16 @@ def test_ising2d_streaming_rows(oracle_mod, tile, L):
                  tag="stream")
 
 
+@pytest.mark.parametrize("model,L,d", [(0, 96, 3), (1, 96, 3), (0, 4112, 2), (1, 48, 3)])
+def test_measure_ragged_row_ranges(oracle_mod, model, L, d):
+    """E/M counting when the rows do not divide evenly among the counting workgroups (3D L = 96:
+    5 rows per workgroup and 1 in the last; 2D L = 4112: 257 chunks per row, more than the 256
+    threads, 3 rows per workgroup and 2 in the last), Ising and +-J."""
+    sched = [(2, 0.3, 1), (1, 0.7, 0), (2, 1.2, 2)]
+    compare_runs(oracle_mod, model, L, d, workloads.seed(0x70 + L + model), sched, replica=1,
+                 cseed=workloads.seed(0x71) if model else None, tag="measure-ragged")
+
+
 # ------------------------------------------------------ full-size configs
 
 @pytest.mark.parametrize("beta", workloads.BETA_2D)
