@@ -26,9 +26,10 @@ __device__ __forceinline__ uint32_t gather_bytes(uint32_t lo, uint32_t hi, uint3
   return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-// 4u per active site, packed (u = unsatisfied bonds among the 2 + NO neighbours).
+// Selector of the bytes of parity P of an 8-byte group.
 __device__ __forceinline__ uint32_t sel_active(uint32_t P) { return P ? 0x07050301u : 0x06040200u; }
 
+// 4u per active site, packed (u = unsatisfied bonds among the 2 + NO neighbours).
 template <int NO>
 __device__ __forceinline__ uint32_t unsat_packed(uint32_t P, uint32_t c0, uint32_t c1, uint32_t lw, uint32_t rw,
                                                  const uint32_t (&o0)[NO], const uint32_t (&o1)[NO]) {
@@ -53,13 +54,15 @@ __device__ __forceinline__ uint32_t flip_mask(uint32_t i4, uint32_t r, uint32_t 
 }
 
 // Apply the four decisions of a packed 4u dword to the group (word r[m] for
-// packed byte m, i.e. site 8g + P + 2m).
+// packed byte m, i.e. site 8g + P + 2m).  Byte 1 is extracted by v_perm_b32
+// (selector 0x0C gives a zero byte), one operation where a shift and a mask
+// would take two.
 template <bool NEVER>
 __device__ __forceinline__ void apply_packed(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S,
                                              const uint32_t r[4], const uint32_t* bound_lds, uint32_t never4) {
   const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
   const uint32_t f0 = flip_mask<NEVER>(S & 0xFFu, r[0], ma, bound_lds, never4);
-  const uint32_t f1 = flip_mask<NEVER>(__builtin_amdgcn_ubfe(S, 8u, 8u), r[1], mb, bound_lds, never4);
+  const uint32_t f1 = flip_mask<NEVER>(__builtin_amdgcn_perm(0u, S, 0x0C0C0C01u), r[1], mb, bound_lds, never4);
   const uint32_t f2 = flip_mask<NEVER>(__builtin_amdgcn_ubfe(S, 16u, 8u), r[2], ma, bound_lds, never4);
   const uint32_t f3 = flip_mask<NEVER>(S >> 24, r[3], mb, bound_lds, never4);
   c0 = xor3(c0, f0, f1);
