@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "tiled", "generic", "resident"])
     ap.add_argument("--tile", default="", help="x,y,z,threads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3D Ising L=512 leg")
+    ap.add_argument("--c3-steps", type=int, default=100, help="steps of 10 sweeps of the 3D leg (100: whole job)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2D L=16384 sensitivity row")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the probe kernels")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D EA workload")
@@ -115,26 +119,89 @@ def profiled_traffic(kernel_tag, L):
     return None
 
 
+def host_cpu():
+    """CPU model, logical CPUs of the host and CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
+
+
 def cpu_baseline(cfg, seconds_hint):
-    """The C oracle, single-threaded, on a bounded sample of the workload."""
+    """The C oracle, single-threaded, on a bounded sample of the workload: each lattice is built (hot
+    start) before its timed window, which covers the sweeps (with their E/M records) only."""
     import oracle
     L, d = cfg["L"], cfg["d"]
     n_sweeps = 2 if L ** d >= 1 << 26 else (20 if L ** d >= 1 << 20 else 200)
     attempts = 0
     used = 0
-    t0 = time.perf_counter()
+    busy = 0.0
     for b in cfg["betas"]:
         ch = oracle.Chain(L, d, cfg["seed"])
+        t0 = time.perf_counter()
         ch.sweep(n_sweeps, b, every=max(1, min(cfg["every"], n_sweeps)))
+        busy += time.perf_counter() - t0
         attempts += n_sweeps * L ** d
         used += 1
-        if time.perf_counter() - t0 > seconds_hint:
+        if busy > seconds_hint:
             break
-    dt = time.perf_counter() - t0
-    return {"value": round(attempts / (dt * 1e9), 5), "unit": "spin-flip attempts/ns", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d sweeps (E/M recorded) of the L=%d d=%d lattice from the hot start at each of %d "
-                      "beta(s); %.1f s on one host core" % (n_sweeps, L, d, used, dt)}
+    cpu = host_cpu()
+    return {"value": round(attempts / (busy * 1e9), 5), "unit": "spin-flip attempts/ns", "cores": 1,
+            "kind": "oracle", "cpu_model": cpu["model"], "nproc": cpu["nproc"], "usable_cpus": cpu["usable"],
+            "sample": "%d sweeps (E/M recorded) of the L=%d d=%d lattice at each of %d beta(s) from the hot "
+                      "start (built outside the timed window); %.1f s of sweeps on one host core"
+                      % (n_sweeps, L, d, used, busy)}
+
+
+def _oracle_worker(args):
+    """One oracle process: build its lattice untimed, then time `sweeps` sweeps."""
+    import oracle
+    L, d, seed, replica, cseed, realisation, beta, sweeps = args
+    J = oracle.couplings(L, d, cseed, realisation) if cseed is not None else None
+    ch = oracle.Chain(L, d, seed, replica, J=J)
+    t0 = time.perf_counter()
+    ch.sweep(sweeps, beta)
+    return sweeps * L ** d, time.perf_counter() - t0
+
+
+def cpu_aggregate(workloads, kind, procs, seconds=5.0, oracle_rate=0.015):
+    """Labelled aggregate of P independent single-threaded oracle processes, one lattice each, run at
+    the same time (P = the CPUs this process may use, at most 16): the ±J batch's lattices (kind
+    "ea3d_batch") or the served trace's jobs ("serve_trace"), each for about `seconds` of sweeps
+    (sweep counts from an assumed `oracle_rate` attempts/ns).  Aggregate = summed attempts / the
+    longest process's sweep time."""
+    import multiprocessing as mp
+    work = []
+    if kind == "ea3d_batch":
+        descs = workloads.ea_batch()
+        step = max(1, len(descs) // procs)
+        for d in descs[::step][:procs]:
+            n = max(1, int(seconds * oracle_rate * 1e9 / d["L"] ** 3))
+            work.append((d["L"], 3, d["seed"], d["replica"], d["coupling_seed"], d["realisation"], d["beta"], n))
+    else:
+        for j in workloads.serve_trace(jobs=procs):
+            n = max(1, min(j["sweeps"], int(seconds * oracle_rate * 1e9 / j["L"] ** j["d"])))
+            work.append((j["L"], j["d"], j["seed"], 0, j["coupling_seed"] if j["model"] == 1 else None, 0,
+                         j["beta"], n))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(work)) as pool:
+        res = pool.map(_oracle_worker, work)
+    att = sum(a for a, _ in res)
+    span = max(t for _, t in res)
+    return {"value": round(att / (span * 1e9), 4), "unit": "spin-flip attempts/ns", "cores": len(work),
+            "kind": "oracle aggregate", "workload": kind,
+            "sample": "%d independent single-threaded oracle processes at once, one lattice each (%s), "
+                      "%.1f s longest" % (len(work), "first lattices of the batch, evenly spaced" if
+                                          kind == "ea3d_batch" else "the trace's first jobs, sweeps capped", span)}
 
 
 def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
@@ -369,10 +436,21 @@ def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (409
     return {"workload": "ea multi-spin-coded (32 realisations per word)", "beta": beta, "rates": out}
 
 
+def serve_class(job, lds_resident):
+    """Size class of a served job: 'lds' (swept by the pool's persistent kernel), 'mid' (below 4 M
+    sites, on the single-lattice kernels), 'big' (4 M sites and more: fills the GPU on its own)."""
+    N = job["L"] ** job["d"]
+    if lds_resident(job["L"], job["d"]):
+        return "lds"
+    return "mid" if N < (1 << 22) else "big"
+
+
 def bench_serving(torch, serve, workloads, jobs):
-    """Serving workload: Poisson job stream at 0.8 x the saturated capacity of the served path,
-    1 GiB pool budget, 512 slots; p50/p99 latency served vs plain FIFO (one job at a time on
-    lone handles, same trace, latencies by the FIFO recurrence over measured service times)."""
+    """Serving workload (a9).  Capacity: the served loop with every job submitted at t = 0 against the
+    plain path's capacity (the same jobs one at a time on lone handles: total work / summed service
+    times), overall and per size class (each class served alone at t = 0).  Latency: a Poisson stream at
+    0.8 x the served capacity, 1 GiB pool budget, 512 slots; p50/p99 served vs plain FIFO (latencies by
+    the FIFO recurrence over the measured service times)."""
     unit = workloads.serve_trace(jobs=jobs, rate_per_s=1.0)
     work = sum(j["L"] ** j["d"] * j["sweeps"] for j in unit)
     stream = torch.cuda.Stream()
@@ -390,11 +468,35 @@ def bench_serving(torch, serve, workloads, jobs):
     trace = [dict(j, arrival=j["arrival"] / lam) for j in unit]
     served, ticks = run(trace)
     plain = serve.plain_fifo(trace, serve.lone_service)
+    plain_busy = sum(r["service"] for r in plain.values())
+    plain_cap = work / plain_busy
     s_sum = serve.summarize(served, trace)
     p_sum = serve.summarize(plain, trace)
     same = all((served[k]["E"], served[k]["M"]) == (plain[k]["E"], plain[k]["M"]) for k in served)
+    classes = {}
+    for c in ("lds", "mid", "big"):
+        sub = [j for j in unit if serve_class(j, serve.lds_resident) == c]
+        if not sub:
+            continue
+        w = sum(j["L"] ** j["d"] * j["sweeps"] for j in sub)
+        res_c, _ = run([dict(j, arrival=0.0) for j in sub])
+        served_s = max(r["finished"] for r in res_c.values())
+        plain_s = sum(plain[j["job"]]["service"] for j in sub)
+        classes[c] = {"jobs": len(sub), "work_share": round(w / work, 4),
+                      "served_attempts_per_ns": round(w / served_s / 1e9, 2),
+                      "plain_attempts_per_ns": round(w / plain_s / 1e9, 2),
+                      "ratio": round(plain_s / served_s, 2), "served_s": round(served_s, 4),
+                      "plain_s": round(plain_s, 4)}
+    # classes served one after another: the ratio a served run can reach on this trace without running
+    # classes concurrently, from the per-class capacities
+    seq_served = sum(v["served_s"] for v in classes.values())
     return {"workload": "serve_trace", "jobs": jobs, "mean_attempts_per_job": work / len(unit),
-            "saturated_attempts_per_ns": round(cap / 1e9, 2), "arrival_rate_per_s": round(lam, 2),
+            "saturated_attempts_per_ns": round(cap / 1e9, 2),
+            "plain_saturated_attempts_per_ns": round(plain_cap / 1e9, 2),
+            "saturated_ratio": round(cap / plain_cap, 2),
+            "classes": classes,
+            "class_sequential_ratio": round(plain_busy / seq_served, 2) if seq_served > 0 else None,
+            "arrival_rate_per_s": round(lam, 2),
             "budget_bytes": 1 << 30, "max_slots": 512, "ticks": ticks,
             "served": {k: round(v, 5) for k, v in s_sum.items()},
             "plain_fifo": {k: round(v, 5) for k, v in p_sum.items()},
@@ -403,25 +505,15 @@ def bench_serving(torch, serve, workloads, jobs):
             "results_identical": bool(same)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1006_3865_amd import spin, workloads
-
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
-    spin.load()
-    cfg = workloads.CONFIGS[args.workload]
+def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0, 0, 0), so_sweeps=200):
+    """One single-lattice workload: `steps` steps of 10 sweeps with the workload's E/M records, on
+    lattices created and initialised before the timed region; then `so_sweeps` back-to-back sweeps
+    without records (the sweep-only rate, HIP events on the lattice's stream) and the roofline of the
+    dominant kernel from them."""
+    cfg = workloads.CONFIGS[name]
     L, d, every = cfg["L"], cfg["d"], cfg["every"]
     N = L ** d
     sweeps_per_step = 10  # one record interval of the L=8192 / L=512 workloads
-    kern = {"auto": 0, "generic": 1, "resident": 2, "tiled": 3, "fused": 4}[args.kernel]
-    tile = [int(v) for v in args.tile.split(",")] if args.tile else [0, 0, 0, 0]
-
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     lats = []
@@ -432,7 +524,7 @@ def main():
         lats.append((lat, b))
     kname = spin.KERNEL_NAMES[lats[0][0].kernel]
     recs_per_step = sweeps_per_step // every
-    nrec = args.steps * recs_per_step
+    nrec = steps * recs_per_step
     Erec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
     Mrec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
     stream.wait_stream(torch.cuda.current_stream())
@@ -440,14 +532,14 @@ def main():
         lat.synchronize()
 
     # warmup (advances the same chains; the kernels' cost does not depend on the state)
-    for i in range(args.warmup):
+    for i in range(warmup):
         for lat, b in lats:
             lat.sweep(sweeps_per_step, b)
     torch.cuda.synchronize()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         for j, (lat, b) in enumerate(lats):
             lat.sweep_record_device(sweeps_per_step, b, every, Erec[j][i * recs_per_step:],
                                     Mrec[j][i * recs_per_step:])
@@ -455,7 +547,6 @@ def main():
     wall = time.perf_counter() - t0
 
     # sweep-only segment (measurement excluded): the same kernel, HIP events on its stream
-    so_sweeps = 200
     ev_a = torch.cuda.Event(enable_timing=True)
     ev_b = torch.cuda.Event(enable_timing=True)
     lat0, b0 = lats[1] if len(lats) > 1 else lats[0]
@@ -464,12 +555,24 @@ def main():
     ev_b.record(stream)
     torch.cuda.synchronize()
     so_ms = ev_a.elapsed_time(ev_b)
+    for lat, _ in lats:
+        lat.close()
+    res = {"workload": name, "kernel": kname, "lattices": len(lats), "steps": steps, "warmup": warmup,
+           "sweeps_per_step": sweeps_per_step, "record_every": every,
+           "value": round(steps * sweeps_per_step * N * len(lats) / (wall * 1e9), 2),
+           "ms_per_step": round(wall * 1e3 / max(1, steps), 4)}
+    res.update(roofline_of(kname, L, d, N, so_sweeps, so_ms))
+    return res
+
+
+def roofline_of(kname, L, d, N, so_sweeps, so_ms):
+    """Sweep-only rate and the roofline of the dominant kernel from so_sweeps back-to-back sweeps that
+    took so_ms (HIP events on the lattice's stream)."""
     launches_per_sweep = {"fused": 1, "tiled": 2, "generic": 2}.get(kname, 0)
     launches = so_sweeps * launches_per_sweep if launches_per_sweep else 1
     kernel_avg_us = so_ms * 1e3 / launches
     attempts_per_launch = so_sweeps * N / launches
     sweep_only_rate = so_sweeps * N / (so_ms * 1e6)  # attempts per ns
-
     alg_ops = ALG_OPS_PER_ATTEMPT[d]
     alu_tops = alg_ops * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e12
     hbm_gbs = BYTES_PER_ATTEMPT * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
@@ -488,6 +591,101 @@ def main():
         roof["lds"] = {"achieved": round(lds_gbs, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
                        "frac": round(lds_gbs / LDS_PEAK_GBS, 4),
                        "alg_bytes_per_launch": int(LDS_BYTES_PER_ATTEMPT[d] * attempts_per_launch)}
+    return {"sweep_only_attempts_per_ns": round(sweep_only_rate, 2),
+            "hbm_frac_sweep_only": round(hbm_gbs / HBM_PEAK_GBS, 4), "roofline": roof}
+
+
+def bench_large2d(torch, spin, workloads, L=16384, sweeps=100):
+    """Sensitivity row above the 256 MB Infinity Cache: 2D Ising L = 16384 (256 MiB of spins, 512 MiB
+    with the second buffer), sweep-only rate on the row-streaming kernel (not one of the workloads)."""
+    stream = torch.cuda.Stream()
+    lat = spin.Lattice(0, L, 2, workloads.seed(2), stream=stream)
+    lat.sweep(2, workloads.BETA_2D_CRIT)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    lat.sweep(sweeps, workloads.BETA_2D_CRIT)
+    b.record(stream)
+    lat.synchronize()
+    kname = spin.KERNEL_NAMES[lat.kernel]
+    lat.close()
+    out = {"workload": "ising2d_L%d (sensitivity, not a workload)" % L, "beta": workloads.BETA_2D_CRIT,
+           "kernel": kname, "sweeps": sweeps, "ping_pong_bytes": 2 * L * L}
+    out.update(roofline_of(kname, L, 2, L * L, sweeps, a.elapsed_time(b)))
+    return out
+
+
+def bench_ceilings(torch, spin):
+    """What bounds the sweep on this GPU, from the probe kernels in the library (include/spin_probe.h):
+    Philox4x32-10 blocks evaluated by the sweep kernels' own code (words/ns), the issue rate of the
+    32x32 -> 64-bit multiply-add the generator is built from and of a plain 32-bit operation (VALU
+    lane-instructions per second against 256 CUs x 64 lanes x 2.4 GHz), and a device copy (GB/s of
+    bytes read + written) of a buffer above the 256 MB Infinity Cache and of one inside it."""
+    lib = spin.load()
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    blocks = 256 * 16
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    threads = blocks * 256
+
+    def timed(fn, reps=3):
+        fn()
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            stream.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    res = {}
+    it = 1024
+    ms = timed(lambda: spin._check(lib.spin_probe_alu(spin.SPIN_PROBE_PHILOX, out.data_ptr(), blocks, it, 7, sp)))
+    words = 4.0 * it * threads
+    res["philox_words_per_ns"] = round(words / (ms * 1e6), 1)
+    res["philox_blocks_per_ns"] = round(words / 4 / (ms * 1e6), 1)
+    it = 512
+    ms = timed(lambda: spin._check(lib.spin_probe_alu(spin.SPIN_PROBE_MAD64, out.data_ptr(), blocks, it, 7, sp)))
+    mad_ops = 64.0 * it * threads
+    res["mad64_probe_lane_instr_per_s"] = round(mad_ops / (ms * 1e-3), -9)
+    res["mad64_probe_frac_of_valu_peak"] = round(mad_ops / (ms * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4)
+    ms = timed(lambda: spin._check(lib.spin_probe_alu(spin.SPIN_PROBE_ALU32, out.data_ptr(), blocks, it, 7, sp)))
+    alu_ops = 32.0 * it * threads
+    res["alu32_probe_lane_instr_per_s"] = round(alu_ops / (ms * 1e-3), -9)
+    res["alu32_probe_frac_of_valu_peak"] = round(alu_ops / (ms * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4)
+    res["valu_peak_lane_instr_per_s"] = VALU_PEAK_TOPS * 1e12
+    for mib in (1024, 64):
+        nb = mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        ms = timed(lambda: spin._check(lib.spin_probe_copy(src.data_ptr(), dst.data_ptr(), nb, 256 * 64, sp)))
+        res["copy_%dMiB_GBps" % mib] = round(2.0 * nb / (ms * 1e6), 1)
+        del src, dst
+    # the canonical chain's ceiling if the generator ran alone at the measured rate and the update
+    # cost nothing: one word per attempt
+    res["note"] = ("philox words/ns bounds attempts/ns from the generator alone; the sweep adds the "
+                   "update's VALU work on top")
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1006_3865_amd import spin, workloads
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    spin.load()
+    kern = {"auto": 0, "generic": 1, "resident": 2, "tiled": 3, "fused": 4}[args.kernel]
+    tile = [int(v) for v in args.tile.split(",")] if args.tile else [0, 0, 0, 0]
+    head = lattice_job(torch, spin, workloads, args.workload, args.steps, args.warmup, kern, tile)
+    cfg = workloads.CONFIGS[args.workload]
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -495,28 +693,33 @@ def main():
         bb = torch.empty_like(a)
         bb.copy_(a)
         torch.cuda.synchronize()
+        del a, bb
 
-    total_attempts = args.steps * sweeps_per_step * N * len(lats)
-    value = total_attempts / (wall * 1e9)
     out = {
         "metric": "spin-flip attempts/ns + % HBM roofline; batched vs plain flips/ns; p50/p99 job latency",
-        "value": round(value, 2),
+        "value": head["value"],
         "unit": "spin-flip attempts/ns",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / max(1, args.steps), 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int8", "data": "synthetic",
-        "config": {"workload": args.workload, "model": "ising", "L": L, "d": d,
-                   "betas": [float(b) for b in cfg["betas"]], "sweeps_per_step": sweeps_per_step,
-                   "record_every": every, "lattices": len(lats), "kernel": kname,
+        "config": {"workload": args.workload, "model": "ising", "L": cfg["L"], "d": cfg["d"],
+                   "betas": [float(b) for b in cfg["betas"]], "sweeps_per_step": head["sweeps_per_step"],
+                   "record_every": cfg["every"], "lattices": head["lattices"], "kernel": head["kernel"],
                    "parallelism": "single GPU"},
-        "sweep_only_attempts_per_ns": round(sweep_only_rate, 2),
-        "hbm_frac_sweep_only": round(hbm_gbs / HBM_PEAK_GBS, 4),
-        "roofline": roof,
+        "sweep_only_attempts_per_ns": head["sweep_only_attempts_per_ns"],
+        "hbm_frac_sweep_only": head["hbm_frac_sweep_only"],
+        "roofline": head["roofline"],
     }
-    for lat, _ in lats:
-        lat.close()
-    del Erec, Mrec
+    if not args.no_c3 and args.workload != "ising3d_L512":
+        # the 3D workload as its own leg: the whole 1000-sweep job (100 steps of 10 sweeps, E/M every 10)
+        out["ising3d_L512"] = lattice_job(torch, spin, workloads, "ising3d_L512", args.c3_steps, 2)
+        print("ising3d_L512:", json.dumps(out["ising3d_L512"]), file=sys.stderr, flush=True)
+    if not args.no_large:
+        out["large2d_L16384"] = bench_large2d(torch, spin, workloads)
+    if not args.no_ceilings:
+        out["ceilings"] = bench_ceilings(torch, spin)
+        print("ceilings:", json.dumps(out["ceilings"]), file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps)
         print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
@@ -544,6 +747,10 @@ def main():
         print("serving:", json.dumps(out["serving"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, 25.0)
+        procs = min(16, host_cpu()["usable"])
+        out["cpu_baseline_aggregates"] = {
+            "ea3d_batch": cpu_aggregate(workloads, "ea3d_batch", procs),
+            "serve_trace": cpu_aggregate(workloads, "serve_trace", procs)}
     print(json.dumps(out), flush=True)
 
 

@@ -3,6 +3,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -12,7 +13,7 @@ LIB = os.path.join(PKG, "libspin.so")
 
 SOURCES = ["spin_kernels.hip", "spin_stream2d.hip", "spin_stream3d.hip", "spin_stream_kernels.hip",
            "spin_coarse_kernels.hip", "spin_batch_kernels.hip", "spin_msc_kernels.hip", "spin_lcg_kernels.hip",
-           "spin_heis_kernels.hip", "spin_runtime.cpp", "spin_batch.cpp", "spin_msc.cpp", "spin_heis.cpp"]
+           "spin_heis_kernels.hip", "spin_probe_kernels.hip", "spin_runtime.cpp", "spin_batch.cpp", "spin_msc.cpp", "spin_heis.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -29,19 +30,34 @@ def hipcc():
     return exe
 
 
+def _jobs():
+    try:
+        n = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(16, n or os.cpu_count() or 1))
+
+
 def build(verbose=False):
-    """Compile every source and link libspin.so next to this file (always rebuilds)."""
-    objs = []
+    """Compile every source (in parallel) and link libspin.so next to this file (always rebuilds)."""
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + HIP_FLAGS + ["-I", INCLUDE, "-I", CSRC] + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc()] + HIP_FLAGS + ["-I", INCLUDE, "-I", CSRC] + lang +
+                    ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as pool:
+        for f in [pool.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -795,6 +795,7 @@ static hipError_t gofused(const Lat& lat, const int8_t* src, int8_t* dst, const 
 uint32_t fused_record_parts(const Lat& lat, const Tile& tile) {
   if (!fused_supported(lat, tile)) return 0;
   if (lat.d == 2 && (uint32_t)tile.x == lat.L && tile.x >= 4096) return lat.L / (uint32_t)tile.y;
+  if (lat.d == 3) return stream3d_record_parts(lat, tile);
   return 0;
 }
 
@@ -806,7 +807,7 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
   if (!fused_supported(lat, tile)) return hipErrorInvalidValue;
   const PhaseArgs a = phase_args(lat, t, 0u, acc);
   const bool never = acc.never_level > 0;
-  if (lat.d == 3) return launch_stream3d(lat, src, dst, a, never, tile, stream);
+  if (lat.d == 3) return launch_stream3d(lat, src, dst, a, never, tile, rec, measured, stream);
   if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
     int G = 0;
     stream2d_shape(lat.L, tile.threads, &G);

@@ -69,4 +69,27 @@ __device__ __forceinline__ void apply_packed(uint32_t P, uint32_t& c0, uint32_t&
   c1 = xor3(c1, f2, f3);
 }
 
+// apply_packed that also adds to acc four times the number of unsatisfied
+// bonds of the four active sites after the update (D: lattice dimension).
+// S holds 4u per site before it; a flipped site has 2D - u unsatisfied bonds
+// afterwards (every one of its bonds changes), so its byte becomes 8D - S_m
+// (no byte borrows: S_m <= 8D).  One v_sad_u8 against zero sums the bytes.
+template <bool NEVER, int D>
+__device__ __forceinline__ void apply_packed_count(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S,
+                                                   const uint32_t r[4], const uint32_t* bound_lds, uint32_t never4,
+                                                   uint32_t& acc) {
+  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
+  const uint32_t f0 = flip_mask<NEVER>(S & 0xFFu, r[0], ma, bound_lds, never4);
+  const uint32_t f1 = flip_mask<NEVER>(__builtin_amdgcn_perm(0u, S, 0x0C0C0C01u), r[1], mb, bound_lds, never4);
+  const uint32_t f2 = flip_mask<NEVER>(__builtin_amdgcn_ubfe(S, 16u, 8u), r[2], ma, bound_lds, never4);
+  const uint32_t f3 = flip_mask<NEVER>(S >> 24, r[3], mb, bound_lds, never4);
+  const uint32_t d0 = f0 ^ f1, d1 = f2 ^ f3;
+  c0 ^= d0;
+  c1 ^= d1;
+  const uint32_t F = gather_bytes(d0, d1, sel_active(P));  // 0xFE at the packed sites that flipped
+  constexpr uint32_t K = 0x01010101u * (8u * (uint32_t)D);
+  const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
+  acc = __builtin_amdgcn_sad_u8(Sf, 0u, acc);
+}
+
 }  // namespace spin

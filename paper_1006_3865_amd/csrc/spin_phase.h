@@ -50,10 +50,14 @@ bool stream2d_shape(uint32_t L, int threads, int* G);
 hipError_t launch_stream2d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
                            uint32_t H, const Record* rec, int threads, int G, hipStream_t stream);
 
-// 3D Ising streaming sweep (k_stream3d): tile.x == L in {512, 1024}, tile.y =
-// rows per workgroup, tile.z = planes per strip, tile.threads = 64 * waves.
+// 3D Ising streaming sweep: tile.x == L, tile.y = rows per workgroup, tile.z =
+// planes per strip, tile.threads = 64 * waves.  L = 512 with (16, 576) or
+// (8, 320) runs the register-column kernel (k_stream3r), which can also count
+// E/M of its result into rec (*measured = true); the other shapes (L = 512 or
+// 1024) run k_stream3d.
 bool stream3d_shape(const Lat& lat, const Tile& tile);
+uint32_t stream3d_record_parts(const Lat& lat, const Tile& tile);  // 0: the kernel cannot count
 hipError_t launch_stream3d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
-                           const Tile& tile, hipStream_t stream);
+                           const Tile& tile, const Record* rec, bool* measured, hipStream_t stream);
 
 }  // namespace spin

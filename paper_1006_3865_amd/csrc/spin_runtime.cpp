@@ -234,8 +234,9 @@ static Tile default_tile(const spin_lattice* h, int kernel) {
   }
   if (t.x && t.y && t.threads && (h->d == 2 || t.z)) return t;
   if (kernel == SPIN_KERNEL_FUSED) {
-    if (h->d == 3) return Tile{L, 8, 64, 640};
+    if (h->d == 3) return L == 512 ? Tile{512, 16, 32, 576} : Tile{L, 8, 64, 640};
     if (L == 8192) return Tile{8192, 16, 0, 1024};
+    if (L == 16384) return Tile{16384, 16, 0, 1024};
     if (L == 4096) return Tile{4096, 8, 0, 512};
     if (L % 512 == 0 && L >= 1024) return Tile{512, 16, 0, 256};
     if (L % 256 == 0) return Tile{256, 32, 0, 256};
@@ -532,7 +533,7 @@ static std::vector<Tuned> tune_candidates(const spin_lattice* h) {
   } else {
     const int f3[5][2] = {{8, 640}, {8, 320}, {16, 576}, {16, 384}, {32, 704}};
     for (auto& f : f3)
-      for (int H : {8, 16, 32}) c.push_back({SPIN_KERNEL_FUSED, Tile{L, f[0], H, f[1]}});
+      for (int H : {8, 16, 32, 64}) c.push_back({SPIN_KERNEL_FUSED, Tile{L, f[0], H, f[1]}});
     const int t3[4][4] = {{64, 8, 8, 256}, {32, 8, 4, 128}, {128, 8, 4, 256}, {16, 4, 4, 64}};
     for (auto& f : t3) c.push_back({SPIN_KERNEL_TILED, Tile{f[0], f[1], f[2], f[3]}});
     for (int th : {256, 512})

@@ -220,8 +220,286 @@ __global__ __launch_bounds__(64 * W) void k_stream3d(const int8_t* __restrict__ 
   }
 }
 
-// 3D streaming shapes: tile.x == L == 512*G, tile.y = TY, tile.z = H, threads = 64*W.
+// ---------------------------------------------------------------------------
+// 3D Ising, L = 512, one whole sweep per launch, streamed over planes with
+// each row's z column held in registers (k_stream3r).
+//
+// A workgroup owns the TY rows [y0, y0+TY) of the planes [z0, z0+H) and has
+// W = TY/2 + 1 waves.  Rows of the slab are numbered r = 0..TY+3 (y = y0-2+r):
+// wave w keeps rows r = 2w+1 and 2w+2 for the whole launch, so rows 2..TY+1
+// are the owned rows, 1 and TY+2 a one-row ring whose colour 0 is recomputed
+// here (colour 1 of the owned edge rows needs it), and 0 and TY+3 (loaded by
+// the first and last wave) the halo that colour 0 of the ring reads.  Lane l
+// holds the 8-site group x = 8l of each of its rows (a row is 512 bytes).
+// Step i = 0..H+1, a = z0-1+i:
+//   load plane a+2 of the wave's rows into registers;
+//   colour 0 on plane a: z neighbours from the registers (plane a-1 after
+//     its colour 0 -- whose colour-1 bytes are the old ones -- and plane
+//     a+1 as loaded), y neighbours from the wave's other row (registers)
+//     and from LDS, x neighbours across the group edge by a wavefront
+//     rotate (DPP), so no row needs wrap bytes;
+//   colour 1 on plane a-1 (i >= 2, owned rows only): z neighbours a-2 and a
+//     after colour 0 (registers), y neighbours as above from the LDS copy
+//     of plane a-1 after colour 0; the result goes to dst;
+//   barrier.
+// LDS holds three plane slices of TY+4 rows in a ring by step: slot i%3
+// gets plane a as loaded at the end of step i-1, is read for colour 0 in
+// step i and overwritten in place with the colour-0 results (only colour-0
+// bytes change, and colour 0 reads only colour-1 bytes of its neighbours,
+// so the concurrent reads of other waves see the same values either way);
+// step i+1 reads it for colour 1; step i+2 overwrites it with plane a+3.
+// Every cross-wave read therefore happens one step after its write.
+// With MEAS the launch also counts E and M of its result: every bond joins a
+// colour-0 and a colour-1 site, so the unsatisfied bonds are the sum over
+// the owned colour-1 sites of their count after the update -- the count the
+// update computed against final colour-0 neighbours, or 2d minus it where
+// the site flipped -- and M from the owned sites' final bytes.
+typedef uint32_t u32x2r __attribute__((ext_vector_type(2)));
+
+template <int TY>
+struct Col3Ctx {
+  static constexpr uint32_t L = 512;
+  static constexpr uint32_t RP = TY + 4;         // rows of a slice
+  static constexpr uint32_t PB = RP * L;         // bytes of a slice
+  static constexpr int W = TY / 2 + 1;
+  __amdgpu_buffer_rsrc_t rsrc, rdst;
+  int8_t* ring;
+  const uint32_t* bound;
+  const RoundKeys* keys;
+  PhiloxUniform U0, U1;
+  uint32_t never4, y0, z0, H, lane, wave;
+  uint32_t yrow[2];   // y of the wave's two rows
+  uint32_t yhalo;     // y of the halo row the edge wave loads
+};
+
+// x neighbour dword of a group for active parity P: P = 0 needs the high
+// dword of the group to the left (lane - 1), P = 1 the low dword of the group
+// to the right (lane + 1); a row is one wavefront, so the rotates wrap x
+// periodically.
+template <uint32_t P>
+__device__ __forceinline__ uint32_t xnb(uint2 c) {
+  if (P == 0) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.y, 0x13C, 0xF, 0xF, false);  // wave_ror:1
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.x, 0x134, 0xF, 0xF, false);             // wave_rol:1
+}
+
+// One colour unit of a group with active parity P: centre c, y neighbours
+// ym, yp, z neighbours zm, zp; Philox counter base c0.  Returns the new group;
+// with MEAS adds 4 x the unsatisfied bonds of the active sites after the
+// update to acc.
+template <uint32_t P, bool NEVER, bool MEAS>
+__device__ __forceinline__ uint2 col3_unit(uint2 c, uint2 ym, uint2 yp, uint2 zm, uint2 zp, uint32_t c0,
+                                           const PhiloxUniform& U, const RoundKeys& K, const uint32_t* bound,
+                                           uint32_t never4, uint32_t& acc) {
+  uint32_t rnd[4];
+  philox_lane(c0, U, K, rnd);
+  const uint32_t nb = xnb<P>(c);
+  const uint32_t o0[4] = {ym.x, yp.x, zm.x, zp.x}, o1[4] = {ym.y, yp.y, zm.y, zp.y};
+  const uint32_t Sp = unsat_packed<4>(P, c.x, c.y, nb, nb, o0, o1);
+  uint32_t c0n = c.x, c1n = c.y;
+  if (MEAS) {
+    apply_packed_count<NEVER, 3>(P, c0n, c1n, Sp, rnd, bound, never4, acc);
+  } else {
+    apply_packed<NEVER>(P, c0n, c1n, Sp, rnd, bound, never4);
+  }
+  return make_uint2(c0n, c1n);
+}
+
+// Register state of one wave: its two rows' z columns and, on the edge
+// waves, the halo row's.
+struct Col3Regs {
+  uint2 xa[2];    // plane a as loaded (colour-0 centre)
+  uint2 xa1[2];   // plane a+1 as loaded
+  uint2 ya1[2];   // plane a-1 after colour 0
+  uint2 ya2[2];   // plane a-2 after colour 0
+  uint2 xh1;      // halo row, plane a+1 as loaded
+  uint32_t sA, sB, sN;  // ring slots of planes a, a-1, a+1
+};
+
+template <int TY>
+__device__ __forceinline__ uint2 col3_load(const Col3Ctx<TY>& c, uint32_t z, uint32_t y) {
+  constexpr uint32_t L = Col3Ctx<TY>::L;
+  const u32x2r v = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * c.lane, (z * L + y) * L, 0);
+  return make_uint2(v.x, v.y);
+}
+
+// Step i of the pipeline (Q = i & 1; C1: colour 1 runs, i.e. i >= 2).  Row j
+// of the wave has y parity (1 + j) & 1 and plane a = z0-1+i parity (i+1) & 1
+// (z0 is even), so the active parity of row j is (Q + j) & 1 in both colours.
+template <int TY, int EDGE, bool NEVER, bool MEAS, uint32_t Q, bool C1>
+__device__ __forceinline__ void col3_step(const Col3Ctx<TY>& c, Col3Regs& R, uint32_t i, int8_t* base,
+                                          uint32_t& unsat4, uint32_t& neg) {
+  using X = Col3Ctx<TY>;
+  constexpr uint32_t L = X::L, PB = X::PB;
+  constexpr bool OWN0 = EDGE != 1, OWN1 = EDGE != 2;  // row j is owned (not the ring)
+  constexpr uint32_t P0 = Q, P1 = Q ^ 1u;             // active parity of rows 0 and 1
+  // load plane a+2 (the last step reloads plane z0+H+1, which nothing reads, so that the load is
+  // unconditional)
+  const uint32_t zl = wrap_row(c.z0 + 1u + (i <= c.H ? i : c.H), 0u, L);
+  uint2 xa2[2], xh2 = make_uint2(0, 0);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) xa2[j] = col3_load(c, zl, c.yrow[j]);
+  if (EDGE) xh2 = col3_load(c, zl, c.yhalo);
+  const uint32_t a = wrap_row(c.z0 + i, 1u, L);
+  int8_t* pA = base + R.sA * PB;
+  int8_t* pB = base + R.sB * PB;
+  int8_t* pN = base + R.sN * PB;
+  uint32_t none = 0;
+  // colour 0 on plane a: y neighbours rows 2w (LDS) and 2w+3 (LDS), the wave's other row (registers)
+  const uint2 up0 = *reinterpret_cast<const uint2*>(pA);
+  const uint2 dn1 = *reinterpret_cast<const uint2*>(pA + 3 * L);
+  uint2 ya0[2];
+  ya0[0] = col3_unit<P0, NEVER, false>(R.xa[0], up0, R.xa[1], R.ya1[0], R.xa1[0], (a * L + c.yrow[0]) * 64u + c.lane,
+                                       c.U0, *c.keys, c.bound, c.never4, none);
+  ya0[1] = col3_unit<P1, NEVER, false>(R.xa[1], R.xa[0], dn1, R.ya1[1], R.xa1[1], (a * L + c.yrow[1]) * 64u + c.lane,
+                                       c.U0, *c.keys, c.bound, c.never4, none);
+  *reinterpret_cast<uint2*>(pA + L) = ya0[0];
+  *reinterpret_cast<uint2*>(pA + 2 * L) = ya0[1];
+  // colour 1 on plane b = a-1 (owned rows)
+  uint2 fin[2];
+  const uint32_t b = wrap_row(a, 1u, L);
+  if (C1) {
+    const uint2 upB = *reinterpret_cast<const uint2*>(pB);
+    const uint2 dnB = *reinterpret_cast<const uint2*>(pB + 3 * L);
+    uint32_t add = 0;
+    if (OWN0)
+      fin[0] = col3_unit<P0, NEVER, MEAS>(R.ya1[0], upB, R.ya1[1], R.ya2[0], ya0[0],
+                                          (b * L + c.yrow[0]) * 64u + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+    if (OWN1)
+      fin[1] = col3_unit<P1, NEVER, MEAS>(R.ya1[1], R.ya1[0], dnB, R.ya2[1], ya0[1],
+                                          (b * L + c.yrow[1]) * 64u + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+    if (MEAS) {
+      unsat4 += add;
+      if (OWN0) neg += __popc(fin[0].x & 0x80808080u) + __popc(fin[0].y & 0x80808080u);
+      if (OWN1) neg += __popc(fin[1].x & 0x80808080u) + __popc(fin[1].y & 0x80808080u);
+    }
+  }
+  // plane a+1 as loaded, for colour 0 of the next step
+  *reinterpret_cast<uint2*>(pN + L) = R.xa1[0];
+  *reinterpret_cast<uint2*>(pN + 2 * L) = R.xa1[1];
+  if (EDGE == 1) *reinterpret_cast<uint2*>(pN) = R.xh1;
+  if (EDGE == 2) *reinterpret_cast<uint2*>(pN + 3 * L) = R.xh1;
+  if (C1) {
+    if (OWN0) {
+      const u32x2r w = {fin[0].x, fin[0].y};
+      __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * c.lane, (b * L + c.yrow[0]) * L, 0);
+    }
+    if (OWN1) {
+      const u32x2r w = {fin[1].x, fin[1].y};
+      __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * c.lane, (b * L + c.yrow[1]) * L, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    R.ya2[j] = R.ya1[j];
+    R.ya1[j] = ya0[j];
+    R.xa[j] = R.xa1[j];
+    R.xa1[j] = xa2[j];
+  }
+  R.xh1 = xh2;
+  const uint32_t t = R.sB;
+  R.sB = R.sA;
+  R.sA = R.sN;
+  R.sN = t;
+  __syncthreads();
+}
+
+template <int TY, int EDGE, bool NEVER, bool MEAS>
+__device__ __forceinline__ void col3_run(const Col3Ctx<TY>& c, uint32_t& unsat4, uint32_t& neg) {
+  using X = Col3Ctx<TY>;
+  constexpr uint32_t L = X::L;
+  // LDS address of (slot 0, row 2w, this lane's group); rows 2w .. 2w+3 of a slot sit at +0 .. +3L
+  int8_t* base = c.ring + 2u * c.wave * L + 8u * c.lane;
+  Col3Regs R;
+  // prologue: planes z0-2 (its colour-1 bytes are the z-1 neighbours of step 0), z0-1 and z0
+  const uint32_t zm2 = wrap_row(c.z0, 2u, L), zm1 = wrap_row(c.z0, 1u, L);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    R.ya1[j] = col3_load(c, zm2, c.yrow[j]);
+    R.xa[j] = col3_load(c, zm1, c.yrow[j]);
+    R.xa1[j] = col3_load(c, c.z0, c.yrow[j]);
+    R.ya2[j] = make_uint2(0, 0);
+  }
+  uint2 xh = make_uint2(0, 0);
+  R.xh1 = make_uint2(0, 0);
+  if (EDGE) {
+    xh = col3_load(c, zm1, c.yhalo);
+    R.xh1 = col3_load(c, c.z0, c.yhalo);
+  }
+  *reinterpret_cast<uint2*>(base + L) = R.xa[0];
+  *reinterpret_cast<uint2*>(base + 2 * L) = R.xa[1];
+  if (EDGE == 1) *reinterpret_cast<uint2*>(base) = xh;
+  if (EDGE == 2) *reinterpret_cast<uint2*>(base + 3 * L) = xh;
+  R.sA = 0;
+  R.sB = 2;
+  R.sN = 1;
+  __syncthreads();
+  // steps 0 and 1 (planes z0-1 and z0 for colour 0; no owned plane for colour 1 yet), then pairs
+  col3_step<TY, EDGE, NEVER, MEAS, 0, false>(c, R, 0u, base, unsat4, neg);
+  col3_step<TY, EDGE, NEVER, MEAS, 1, false>(c, R, 1u, base, unsat4, neg);
+  const uint32_t steps = c.H + 2;
+  for (uint32_t i0 = 2; i0 < steps; i0 += 2) {
+    col3_step<TY, EDGE, NEVER, MEAS, 0, true>(c, R, i0, base, unsat4, neg);
+    col3_step<TY, EDGE, NEVER, MEAS, 1, true>(c, R, i0 + 1u, base, unsat4, neg);
+  }
+}
+
+template <int TY, bool NEVER, bool MEAS>
+__global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __restrict__ src,
+                                                                int8_t* __restrict__ dst, PhaseArgs a,
+                                                                uint32_t H, Record rec) {
+  using X = Col3Ctx<TY>;
+  constexpr uint32_t L = X::L;
+  constexpr int W = X::W;
+  __shared__ __align__(16) int8_t lds[32 + 3 * X::PB];
+  X c;
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(L * L * L), 0x00020000);
+  c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(L * L * L), 0x00020000);
+  c.ring = lds + 32;
+  c.bound = reinterpret_cast<const uint32_t*>(lds);
+  c.keys = &a.keys;
+  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
+  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
+  c.never4 = a.never4;
+  // workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles (all slabs
+  // of its strips), so that the halo rows of neighbouring slabs are read from the same L2
+  const uint32_t nslab = L / TY;
+  const uint32_t nblk = gridDim.x;
+  const uint32_t b = blockIdx.x;
+  const uint32_t tile = (nblk % 8u == 0u) ? (b % 8u) * (nblk / 8u) + b / 8u : b;
+  c.y0 = (tile % nslab) * TY;
+  c.z0 = (tile / nslab) * H;
+  c.H = H;
+  c.lane = threadIdx.x & 63;
+  c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) c.yrow[j] = wrap_row(c.y0 + 2u * c.wave + 1u + j, 2u, L);
+  c.yhalo = (c.wave == 0) ? wrap_row(c.y0, 2u, L) : wrap_row(c.y0 + TY + 3u, 2u, L);
+  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
+  uint32_t unsat4 = 0, neg = 0;
+  if (c.wave == 0)
+    col3_run<TY, 1, NEVER, MEAS>(c, unsat4, neg);
+  else if (c.wave == (uint32_t)(W - 1))
+    col3_run<TY, 2, NEVER, MEAS>(c, unsat4, neg);
+  else
+    col3_run<TY, 0, NEVER, MEAS>(c, unsat4, neg);
+  if (MEAS) {
+    __shared__ int64_t red[W];
+    record_block<64 * W>((int64_t)(unsat4 >> 2), (int64_t)neg, rec, red);
+  }
+}
+
+// Register-column kernel (k_stream3r): L = 512, tile.y = TY in {8, 16} with
+// TY/2 + 1 waves (320 or 576 threads), tile.z = H even.
+static bool col3_shape(const Lat& lat, const Tile& tile) {
+  if (lat.J != nullptr || lat.d != 3 || lat.L != 512 || (uint32_t)tile.x != lat.L) return false;
+  const bool ok = (tile.y == 16 && tile.threads == 576) || (tile.y == 8 && tile.threads == 320);
+  return ok && tile.z >= 2 && tile.z % 2 == 0 && lat.L % (uint32_t)tile.z == 0;
+}
+
+// 3D streaming shapes: tile.x == L == 512*G, tile.y = TY, tile.z = H, threads = 64*W
+// (k_stream3d), or the register-column shapes above.
 bool stream3d_shape(const Lat& lat, const Tile& tile) {
+  if (col3_shape(lat, tile)) return true;
   if (lat.J != nullptr || lat.d != 3) return false;
   if ((uint32_t)tile.x != lat.L || (lat.L != 512 && lat.L != 1024)) return false;
   const bool ok_shape = (tile.y == 8 && (tile.threads == 640 || tile.threads == 320)) ||
@@ -229,6 +507,31 @@ bool stream3d_shape(const Lat& lat, const Tile& tile) {
                         (tile.y == 32 && tile.threads == 704 && lat.L == 512);
   return ok_shape && lat.L % (uint32_t)tile.y == 0 && tile.z >= 4 && tile.z % 2 == 0 &&
          lat.L % (uint32_t)tile.z == 0;
+}
+
+uint32_t stream3d_record_parts(const Lat& lat, const Tile& tile) {
+  if (!col3_shape(lat, tile)) return 0;
+  return (lat.L / (uint32_t)tile.y) * (lat.L / (uint32_t)tile.z);
+}
+
+template <int TY>
+static hipError_t gocol3(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
+                         uint32_t H, const Record* rec, hipStream_t stream) {
+  dim3 grid((lat.L / TY) * (lat.L / H));
+  dim3 block(64 * (TY / 2 + 1));
+  const Record r = rec ? *rec : Record{nullptr};
+  if (rec) {
+    if (never)
+      hipLaunchKernelGGL((k_stream3r<TY, true, true>), grid, block, 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream3r<TY, false, true>), grid, block, 0, stream, src, dst, a, H, r);
+  } else {
+    if (never)
+      hipLaunchKernelGGL((k_stream3r<TY, true, false>), grid, block, 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream3r<TY, false, false>), grid, block, 0, stream, src, dst, a, H, r);
+  }
+  return hipGetLastError();
 }
 
 template <int TY, int W, int G>
@@ -243,13 +546,17 @@ static hipError_t gostream3(const Lat& lat, const int8_t* src, int8_t* dst, cons
 }
 
 hipError_t launch_stream3d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
-                           const Tile& tile, hipStream_t stream) {
+                           const Tile& tile, const Record* rec, bool* measured, hipStream_t stream) {
+  if (measured) *measured = false;
   if (!stream3d_shape(lat, tile)) return hipErrorInvalidValue;
   const uint32_t H = (uint32_t)tile.z;
+  if (col3_shape(lat, tile)) {
+    if (measured) *measured = (rec != nullptr);
+    if (tile.y == 16) return gocol3<16>(lat, src, dst, a, never, H, rec, stream);
+    return gocol3<8>(lat, src, dst, a, never, H, rec, stream);
+  }
   if (lat.L == 512) {
     if (tile.y == 8 && tile.threads == 640) return gostream3<8, 10, 1>(lat, src, dst, a, never, H, stream);
-    if (tile.y == 8) return gostream3<8, 5, 1>(lat, src, dst, a, never, H, stream);
-    if (tile.y == 16 && tile.threads == 576) return gostream3<16, 9, 1>(lat, src, dst, a, never, H, stream);
     if (tile.y == 16) return gostream3<16, 6, 1>(lat, src, dst, a, never, H, stream);
     return gostream3<32, 11, 1>(lat, src, dst, a, never, H, stream);
   }

@@ -110,6 +110,13 @@ SIGNATURES = {
     "spin_batch_synchronize": (_c.c_int, [_P]),
 }
 
+# The ceiling probes of include/spin_probe.h (measurement only).
+PROBE_SIGNATURES = {
+    "spin_probe_alu": (_c.c_int, [_c.c_int, _c.c_void_p, _c.c_uint32, _c.c_uint32, _c.c_uint64, _c.c_void_p]),
+    "spin_probe_copy": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_uint64, _c.c_uint32, _c.c_void_p]),
+}
+SPIN_PROBE_PHILOX, SPIN_PROBE_MAD64, SPIN_PROBE_ALU32 = 0, 1, 2
+
 _lib = None
 
 
@@ -121,7 +128,7 @@ def load():
             raise RuntimeError("libspin.so is not built (run __graft_entry__.build()); "
                                "there is no fallback path")
         lib = _c.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
+        for name, (res, args) in list(SIGNATURES.items()) + list(PROBE_SIGNATURES.items()):
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
@@ -144,6 +151,26 @@ def _check(rc):
 
 def _i8(a):
     return a.ctypes.data_as(_i8p)
+
+
+def check_record_tensors(E, M, need):
+    """Validate device record arrays before their pointers reach the C ABI: torch int64 tensors on a
+    GPU, contiguous, with at least `need` elements each.  A wrong dtype, host memory or a short
+    tensor would make the record kernels write outside the allocation, so they raise ValueError."""
+    if need <= 0:
+        return
+    for name, t in (("E", E), ("M", M)):
+        if t is None:
+            raise ValueError("%s: a device int64 tensor of >= %d elements is required" % (name, need))
+        dtype = getattr(t, "dtype", None)
+        if dtype is None or str(dtype) != "torch.int64":
+            raise ValueError("%s must be a torch.int64 tensor (got %s)" % (name, dtype))
+        if not getattr(t, "is_cuda", False):
+            raise ValueError("%s must live in GPU memory (got device %s)" % (name, getattr(t, "device", "?")))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if t.numel() < need:
+            raise ValueError("%s holds %d elements, the call writes %d" % (name, t.numel(), need))
 
 
 # --------------------------------------------------------------- C names
@@ -318,7 +345,11 @@ class Lattice:
 
     def sweep_record_device(self, n, beta, every, E, M):
         """E, M: torch int64 CUDA tensors with >= n//every elements."""
-        spin_sweep_record_device(self.h, n, beta, every, E.data_ptr(), M.data_ptr())
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        check_record_tensors(E, M, n // every if n > 0 else 0)
+        spin_sweep_record_device(self.h, n, beta, every, E.data_ptr() if E is not None else None,
+                                 M.data_ptr() if M is not None else None)
 
     def measure(self):
         return spin_measure(self.h)
@@ -485,6 +516,8 @@ class Batch:
     def sweep_device(self, n, beta, every, E, M):
         """E, M: torch int64 CUDA tensors holding record_counts(n, every).sum() values."""
         n, b = self._args(n, beta)
+        if every > 0:
+            check_record_tensors(E, M, int(self.record_counts(n, every).sum()))
         self._hold = (n, b)
         _check(load().spin_batch_sweep_device(self.h, n.ctypes.data_as(_ip), b.ctypes.data_as(_dp), every,
                                               E.data_ptr() if E is not None else None,

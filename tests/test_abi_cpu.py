@@ -14,8 +14,8 @@ from paper_1006_3865_amd import spin
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    text = open(os.path.join(ROOT, "include", "spin.h")).read()
+def declared_functions(header="spin.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(spin_[a-z_]+)\s*\(", text)
     return sorted(set(names))
@@ -34,6 +34,16 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(spin.SIGNATURES), "binding and header disagree"
+
+
+def test_probe_symbols_are_exported(lib):
+    names = declared_functions("spin_probe.h")
+    assert names == sorted(spin.PROBE_SIGNATURES)
+    for n in names:
+        assert hasattr(lib, n), n
+    # argument errors come back before any launch
+    assert lib.spin_probe_alu(7, None, 1, 1, 0, None) == spin.SPIN_EINVAL
+    assert lib.spin_probe_copy(None, None, 16, 1, None) == spin.SPIN_EINVAL
 
 
 def test_version(lib):
@@ -76,3 +86,34 @@ def test_null_handle_and_bad_beta(lib):
     assert lib.spin_threshold_table(-0.1, 2, T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) == spin.SPIN_EINVAL
     assert lib.spin_threshold_table(0.5, 4, T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) == spin.SPIN_EINVAL
     lib.spin_free(None)  # NULL-safe
+
+
+def test_record_tensors_rejected_before_the_abi():
+    """Device record arrays are checked in the binding: a wrong dtype, host memory, a strided view or
+    too few elements raise ValueError, so no bad pointer reaches a record kernel."""
+    import torch
+    ok64 = torch.zeros(8, dtype=torch.int64)
+    with pytest.raises(ValueError, match="int64"):
+        spin.check_record_tensors(torch.zeros(8, dtype=torch.int32), ok64, 4)
+    with pytest.raises(ValueError, match="GPU"):
+        spin.check_record_tensors(ok64, ok64, 4)          # host tensors
+    with pytest.raises(ValueError, match="required"):
+        spin.check_record_tensors(None, ok64, 1)
+    spin.check_record_tensors(None, None, 0)              # nothing recorded: nothing checked
+
+    class FakeCuda:
+        """Stands for a device tensor (no GPU here): dtype, device flag, layout and size."""
+        def __init__(self, n, contiguous=True, dtype=torch.int64):
+            self.dtype, self.is_cuda, self._n, self._c = dtype, True, n, contiguous
+
+        def is_contiguous(self):
+            return self._c
+
+        def numel(self):
+            return self._n
+
+    spin.check_record_tensors(FakeCuda(4), FakeCuda(5), 4)
+    with pytest.raises(ValueError, match="contiguous"):
+        spin.check_record_tensors(FakeCuda(8, contiguous=False), FakeCuda(8), 4)
+    with pytest.raises(ValueError, match="writes 6"):
+        spin.check_record_tensors(FakeCuda(6), FakeCuda(5), 6)

@@ -310,6 +310,26 @@ def test_ising3d_L512_first_sweep(oracle_mod):
     lat.close()
 
 
+def test_ising3d_L512_register_column_shapes(oracle_mod):
+    """The register-column plane-streaming kernel (the 3D L = 512 default) at every slab height and at
+    strip heights from 2 planes to the whole lattice (one strip: the z wrap inside one workgroup's
+    pipeline), continuing one chain across shapes and temperatures: a typical beta, beta = 3 (classes
+    with T = 0), beta = 0 (every spin flips) and a zero-temperature quench; E/M counted in the sweep."""
+    s = workloads.seed(0xB3)
+    lat = make(0, 512, 3, s, 5)
+    ch = oracle_mod.Chain(512, 3, s, 5)
+    for tile, beta in [((512, 16, 32, 576), B_3D), ((512, 16, 2, 576), 3.0), ((512, 8, 4, 320), 0.0),
+                       ((512, 16, 512, 576), math.inf), ((512, 8, 64, 320), 0.5), ((512, 16, 8, 576), B_3D)]:
+        lat.set_kernel(FUS, *tile)
+        note("register-column", tile, beta)
+        E, M = lat.sweep_record(1, beta, 1)
+        Eo, Mo = ch.sweep(1, beta, every=1)
+        np.testing.assert_array_equal(E, Eo)
+        np.testing.assert_array_equal(M, Mo)
+        np.testing.assert_array_equal(lat.spins(), ch.spins)
+    lat.close()
+
+
 @pytest.mark.parametrize("model,L,d", [(0, 256, 3), (1, 96, 3), (0, 2048, 2), (1, 48, 3)])
 def test_autotune_keeps_chain_and_parity(oracle_mod, model, L, d):
     """spin_autotune leaves the handle's chain untouched, and the family it picks (also taken by new
@@ -364,15 +384,22 @@ def check_sweep_sampled(oracle_mod, old, new, L, d, J, seed, replica, t, beta, n
         assert int(new[s]) == (-int(old[s]) if flip else int(old[s])), ("site", s, "colour", c)
 
 
-@pytest.mark.parametrize("model,L,d,beta", [(0, 16384, 2, B_CRIT), (0, 1024, 3, B_3D), (1, 512, 3, 1.0)])
-def test_largest_sizes_sampled(oracle_mod, model, L, d, beta):
-    """The largest lattices the specialised kernels take (2D L = 16384: two 8-site groups per thread of
-    the row-streaming kernel; 3D L = 1024) and a 3D +-J lattice of the benchmark's size: the second
-    sweep checked site by site on a sample."""
+@pytest.mark.parametrize("model,L,d,beta,tile", [
+    (0, 16384, 2, B_CRIT, (16384, 16, 0, 1024)),   # row-streaming kernel, two 8-site groups per thread
+    (0, 16384, 2, B_CRIT, (512, 16, 0, 256)),      # tiled fused kernel on the same lattice
+    (0, 1024, 3, B_3D, None),
+    (1, 512, 3, 1.0, None)])
+def test_largest_sizes_sampled(oracle_mod, model, L, d, beta, tile):
+    """The largest lattices the specialised kernels take (2D L = 16384 on the row-streaming kernel,
+    whose buffer descriptor spans 2^28 bytes, and on the tiled fused kernel; 3D L = 1024) and a 3D
+    +-J lattice of the benchmark's size: the second sweep checked site by site on a sample."""
     seed, rep = workloads.seed(0xA0 + d), 1
     cs = workloads.seed(0x11) if model else None
     lat = make(model, L, d, seed, rep, None, cs)
-    note("largest", model, L, d, "kernel", spin.KERNEL_NAMES[lat.kernel])
+    if tile is not None:
+        lat.set_kernel(spin.SPIN_KERNEL_FUSED, *tile)
+        assert lat.kernel == spin.SPIN_KERNEL_FUSED
+    note("largest", model, L, d, "kernel", spin.KERNEL_NAMES[lat.kernel], "tile", tile)
     lat.sweep(1, beta)
     old = lat.spins()
     t = lat.t
