@@ -205,6 +205,12 @@ __global__ __launch_bounds__(NT) void k_batch(BatchLattice* lats, const BatchCal
   __shared__ uint32_t task;
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* sp = lds;
+  // Termination: the queue fetch (thread 0's atomic), both barriers, the
+  // readfirstlane of the task index and the exit test sit at this one loop
+  // level and nothing before the exit test branches on per-lane data, so
+  // every wave reads the same k and leaves on the same iteration.  Moving the
+  // fetch or a barrier into a nested loop or a lane-dependent branch breaks
+  // that: a wave can then re-read a stale index and never reach k >= ntasks.
   for (;;) {
     if (threadIdx.x == 0) task = atomicAdd(next, 1u);
     __syncthreads();
