@@ -214,22 +214,61 @@ def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
     betas = np.array([d["beta"] for d in descs])
     N = np.array([d["L"] ** 3 for d in descs], dtype=np.float64)
     stream = torch.cuda.Stream()
+    attempts = float(N.sum()) * sweeps
+
+    def one_call(tag):
+        """The whole workload as one pool call on a fresh pool: (wall s, GPU ms)."""
+        b = spin.Batch(descs, stream=stream)
+        nrec = int(b.record_counts(sweeps, every).sum())
+        E = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
+        M = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
+        b.sweep(2, betas, 0)          # warm-up: module load, LDS attributes
+        b.synchronize()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        b.sweep_device(sweeps, betas, every, E, M)
+        ev1.record(stream)
+        b.synchronize()
+        wall = time.perf_counter() - t0
+        print("bench: batched %s %.1f ms" % (tag, wall * 1e3), file=sys.stderr, flush=True)
+        h = [int(E[-1]), int(M[-1])]
+        b.close()
+        return wall, ev0.elapsed_time(ev1), h
+
+    wall_static, ms_static, h_static = one_call("static plan")
+    # the project's autotuner picks each lattice shape's launch plan by timing (outside the timed region)
     b = spin.Batch(descs, stream=stream)
-    nrec = int(b.record_counts(sweeps, every).sum())
+    t0 = time.perf_counter()
+    ntuned = b.autotune(float(np.median(betas)), 20)
+    tune_s = time.perf_counter() - t0
+    b.close()
+    plans = {"L%d" % L: spin.batch_plan(3, 1, L) for L in sorted({d["L"] for d in descs})}
+    wall, gpu_ms, h_tuned = one_call("tuned plan")
+    # the same workload as replays of one captured 100-sweep call (hipGraph)
+    g_sweeps = 100
+    reps = sweeps // g_sweeps
+    b = spin.Batch(descs, stream=stream)
+    nrec = int(b.record_counts(g_sweeps, every).sum())
     E = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
     M = torch.zeros(max(nrec, 1), dtype=torch.int64, device="cuda")
-    b.sweep(2, betas, 0)          # warm-up: module load, LDS attributes
+    b.sweep(2, betas, 0)                           # the same 2 warm-up sweeps as one_call
+    b.sweep_device(g_sweeps, betas, every, E, M)   # uploads the call's tables (uncaptured)
     b.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.sweep_device(g_sweeps, betas, every, E, M)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    b.sweep_device(sweeps, betas, every, E, M)
-    ev1.record(stream)
-    b.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    attempts = float(N.sum()) * sweeps
+    for _ in range(reps - 1):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_wall = time.perf_counter() - t0
+    h_graph = [int(E[-1]), int(M[-1])]
+    del g
     b.close()
+    graph_att = float(N.sum()) * g_sweeps * (reps - 1)
     rates = {}
     for L in sorted({d["L"] for d in descs}):
         sel = [d for d in descs if d["L"] == L][:2]
@@ -255,6 +294,12 @@ def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
     return {"workload": "ea3d_batch", "lattices": len(descs), "realisations": len(descs) // 16,
             "sizes": sorted(rates), "sweeps": sweeps, "record_every": every, "attempts": attempts,
             "batched_attempts_per_ns": round(batched, 2), "batched_gpu_ms": round(gpu_ms, 2),
+            "plan": "autotuned (%d shapes in %.1f s): %s" % (ntuned, tune_s, plans),
+            "static_plan_attempts_per_ns": round(attempts / (wall_static * 1e9), 2),
+            "static_plan_gpu_ms": round(ms_static, 2),
+            "graph": {"captured_sweeps": g_sweeps, "replays_timed": reps - 1,
+                      "attempts_per_ns": round(graph_att / (graph_wall * 1e9), 2)},
+            "final_record_identical": {"tuned_vs_static": h_static == h_tuned, "graph_vs_static": h_static == h_graph},
             "plain_attempts_per_ns": round(plain, 3), "ratio": round(batched / plain, 2),
             "plain_rate_by_L": {str(L): {"attempts_per_ns": round(r, 3), "kernel": k} for L, (r, k) in rates.items()},
             "plain_method": "lone handles, %d sweeps on 2 lattices per L, summed over the workload" % plain_sweeps}
@@ -672,6 +717,9 @@ def bench_ceilings(torch, spin):
 
 def main():
     args = parse()
+    # tuning records are neither read nor written unless the caller names a cache file: the
+    # benchmark runs its own autotuner where it uses one
+    os.environ.setdefault("SPIN_TUNE_CACHE", "")
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % args.gpus,
               file=sys.stderr)

@@ -220,8 +220,24 @@ int spin_threshold_table(double beta, int d, uint64_t* T);
  * release(ptr, ctx) frees it.  Affects handles created afterwards. */
 void spin_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx);
 
+/* Test hooks for the out-of-memory paths (no passage of the paper; for
+ * tests that force allocation failures).  spin_debug_fault_alloc(k) with
+ * k >= 0: the library's next k device allocations succeed and the one after
+ * them fails as if the device were out of memory (SPIN_ENOMEM from the call
+ * that made it), after which injection is off again; k = -1 turns it off.
+ * The environment variable SPIN_FAULT_ALLOC=k sets the same at the first
+ * allocation of the process.  spin_debug_live_allocations: device blocks
+ * the library holds now (lattices, pools and their buffers), for leak
+ * checks. */
+int spin_debug_fault_alloc(int64_t after);
+int64_t spin_debug_live_allocations(void);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* spin_last_error(void);
+
+/* Status code (spin_status) of that call: what a constructor that returned
+ * NULL failed with. */
+int spin_last_status(void);
 
 /* Library version string. */
 const char* spin_version(void);
@@ -283,9 +299,9 @@ int  spin_batch_is_member(const spin_batch* b, int i);
 
 /* Device bytes that slot i's lattice may hold: spins (twice L^d for a
  * lattice beyond the LDS-sized kind: the streaming kernels' second buffer)
- * plus its couplings (d*L^d/2 packed for the LDS-sized kind, d*L^d
- * otherwise), counted in full even when shared with other members; 0 for a
- * free slot.  An upper bound for admission control. */
+ * plus its couplings (d*L^d/2 packed for the LDS-sized kind, 3*d*L^d/2 --
+ * int8 and packed -- otherwise), counted in full even when shared with
+ * other members; 0 for a free slot.  An upper bound for admission control. */
 uint64_t spin_batch_footprint(const spin_batch* b, int i);
 
 /* Advance slot i by n[i] >= 0 sweeps at beta[i] (host arrays of
@@ -295,7 +311,35 @@ uint64_t spin_batch_footprint(const spin_batch* b, int i);
  * sum_{j<i} of the earlier slots' counts (free slots count 0).  Synchronises. */
 int spin_batch_sweep(spin_batch* b, const int* n, const double* beta, int every, int64_t* E, int64_t* M);
 
-/* As spin_batch_sweep with DEVICE record arrays; asynchronous. */
+/* Sec. 4 (tile sizes chosen by experiment), for the persistent launch: for
+ * every lattice shape (d, model, L) among the pool's LDS-held members, time
+ * each launch shape -- workgroups of 256, 512 or 1024 threads, 1 .. as many
+ * workgroups per CU as threads and LDS allow -- on scratch lattices of that
+ * shape (as many as the pool holds, at most four per CU), `sweeps` sweeps at
+ * beta each; check that every candidate leaves identical spins (else
+ * SPIN_EDEVICE); keep the fastest as the shape's plan for every pool of the
+ * process, and append it to the tuning cache file (SPIN_TUNE_CACHE, default
+ * $HOME/.cache/spin-gfx950/tune.txt; records "batch <arch> d model L threads
+ * workgroups_per_cu ns_per_sweep", read back at the first pool call of a
+ * later process).  The pool's own lattices are not touched.  Returns the
+ * number of shapes tuned or a negative status.  Synchronises. */
+int spin_batch_autotune(spin_batch* b, double beta, int sweeps);
+
+/* The plan of shape (d, model, L): 1 and its threads and workgroups per CU,
+ * or 0 (outputs 0) when the shape has none and the static rule applies. */
+int spin_batch_plan(int d, int model, int L, int* threads, int* workgroups_per_cu);
+
+/* As spin_batch_sweep with DEVICE record arrays; asynchronous.
+ * Graph capture: a call made while the pool's stream (a non-null stream
+ * given at creation) is being captured enqueues only kernel launches -- the
+ * queue counters are cleared by a kernel, and the per-slot tables must
+ * already be on the device, so its arguments (n, beta, every, E, M) must
+ * repeat those of the pool's previous, uncaptured call, and only members
+ * held in LDS may sweep or record (else SPIN_ESTATE, nothing enqueued).
+ * Every replay of the graph advances those members by n[i] sweeps from
+ * where the previous replay left them and rewrites the same record slots;
+ * spin_batch_sweeps_done and the next uncaptured call read the advanced
+ * counters back from the device. */
 int spin_batch_sweep_device(spin_batch* b, const int* n, const double* beta, int every, int64_t* E,
                             int64_t* M);
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <tuple>
@@ -41,13 +42,8 @@ namespace {
 
 template <class T>
 bool dmalloc(T** p, size_t bytes) {
-  *p = nullptr;
-  if (hipMalloc((void**)p, bytes ? bytes : 16) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return false;
-  }
-  return true;
+  *p = (T*)device_alloc(bytes);
+  return *p != nullptr;
 }
 
 // Device memory of the members: 256-byte blocks carved from 32 MiB chunks,
@@ -90,7 +86,7 @@ class Slab {
     if (!p) return;
     auto it = direct_.find(p);
     if (it != direct_.end()) {
-      (void)hipFree(p);
+      device_free(p);
       direct_.erase(it);
       return;
     }
@@ -100,8 +96,8 @@ class Slab {
   }
 
   void release() {
-    for (char* c : chunks_) (void)hipFree(c);
-    for (void* p : direct_) (void)hipFree(p);
+    for (char* c : chunks_) device_free(c);
+    for (void* p : direct_) device_free(p);
     chunks_.clear();
     direct_.clear();
     free_.clear();
@@ -144,9 +140,49 @@ struct Class {
   uint32_t nt;                   // threads per workgroup
   size_t lds;                    // dynamic LDS of the launch (largest member of the class)
   std::vector<uint32_t> members;
+  uint32_t per_cu;               // planned workgroups per CU (smallest over the planned members), 0: none
+  bool unplanned;                // some member has no plan
 };
 
 size_t rec_count(int n, int every) { return every > 0 ? (n > 0 ? (size_t)(n / every) : 1) : 0; }
+
+// Launch plan of the persistent kernel for one lattice shape (d, model, L):
+// workgroup size and workgroups per CU, chosen by spin_batch_autotune (or
+// read back from the tuning cache).  Shapes without a plan use the static
+// rule: threads by lattice size (batch_threads_for), workgroups per CU as
+// many as threads and LDS allow.
+struct Plan {
+  uint32_t nt;
+  uint32_t per_cu;
+};
+std::mutex g_plan_mu;
+std::map<std::tuple<int, int, int>, Plan> g_plan;
+bool g_plan_loaded = false;
+
+// Records "batch <arch> d model L threads per_cu ns_per_sweep".
+void load_plans_locked() {
+  if (g_plan_loaded) return;
+  g_plan_loaded = true;
+  for (const auto& v : tune_cache_read("batch"))
+    if (v.size() >= 5 && (v[3] == 256 || v[3] == 512 || v[3] == 1024) && v[4] >= 1 && v[4] <= 8)
+      g_plan[std::make_tuple((int)v[0], (int)v[1], (int)v[2])] = Plan{(uint32_t)v[3], (uint32_t)v[4]};
+}
+
+bool plan_for(int d, int model, int L, Plan* out) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  load_plans_locked();
+  auto it = g_plan.find(std::make_tuple(d, model, L));
+  if (it == g_plan.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// Workgroups of nt threads with `lds` bytes of dynamic LDS that one CU holds.
+uint32_t max_per_cu(uint32_t nt, size_t lds) {
+  const uint32_t by_threads = 2048u / nt;
+  const uint32_t by_lds = (uint32_t)((160 * 1024 - 256) / std::max<size_t>(lds, 1));
+  return std::max<uint32_t>(1, std::min(by_threads, by_lds));
+}
 
 }  // namespace
 
@@ -177,7 +213,43 @@ struct spin_batch {
   int next_aux = 0;
   int num_cu = 256;
   int wgs_override = 0;               // 0: by occupancy
+  uint32_t force_nt = 0;              // autotuner's scratch pools: this launch shape for every class
+  uint32_t force_per_cu = 0;
+  // The tables of the last upload (a call that repeats them uploads nothing, which is what lets
+  // a call be captured into a graph) and whether a call has been captured: then any replay may
+  // have advanced the resident members' device sweep counters, and the host mirrors are read
+  // back from the device whenever they are needed.
+  std::vector<BatchCall> last_calls;
+  std::vector<uint32_t> last_order;
+  bool t_stale = false;
 };
+
+// Whether work enqueued on the pool's stream is being captured into a graph.
+static bool capturing(const spin_batch* b) {
+  if (!b->stream) return false;  // the null stream is never captured here
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(b->stream, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st == hipStreamCaptureStatusActive;
+}
+
+// Bring the host mirrors of the resident members' sweep counters up to the
+// device copies (a pool with a captured call: graph replays advance them
+// without the host's knowledge).  Synchronises.
+static int refresh_counters(spin_batch* b) {
+  if (!b->t_stale) return SPIN_OK;
+  const size_t S = b->m.size();
+  std::vector<BatchLattice> tmp(S);
+  hipError_t e = S ? hipMemcpyAsync(tmp.data(), b->d_lats, sizeof(BatchLattice) * S, hipMemcpyDeviceToHost, b->stream)
+                   : hipSuccess;
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hfail(e, "batch counter refresh");
+  for (size_t i = 0; i < S; ++i)
+    if (b->m[i].active && b->m[i].resident) b->m[i].t = tmp[i].t;
+  return SPIN_OK;
+}
 
 static void free_member(spin_batch* b, Member& mb) {
   if (mb.big) spin_free(mb.big);
@@ -203,11 +275,11 @@ static void batch_destroy(spin_batch* b) {
   for (Member& mb : b->m)
     if (mb.active || mb.big) free_member(b, mb);
   b->slab.release();
-  (void)hipFree(b->d_lats);
-  (void)hipFree(b->d_calls);
-  (void)hipFree(b->d_order);
-  (void)hipFree(b->d_counters);
-  (void)hipFree(b->d_rec);
+  device_free(b->d_lats);
+  device_free(b->d_calls);
+  device_free(b->d_order);
+  device_free(b->d_counters);
+  device_free(b->d_rec);
   if (b->h_lats) (void)hipHostFree(b->h_lats);
   if (b->h_calls) (void)hipHostFree(b->h_calls);
   if (b->h_order) (void)hipHostFree(b->h_order);
@@ -247,17 +319,17 @@ static int ensure_capacity(spin_batch* b, size_t n) {
   }
   if (!ok) {
     (void)hipGetLastError();
-    (void)hipFree(d_lats);
-    (void)hipFree(d_calls);
-    (void)hipFree(d_order);
+    device_free(d_lats);
+    device_free(d_calls);
+    device_free(d_order);
     if (h_lats) (void)hipHostFree(h_lats);
     if (h_calls) (void)hipHostFree(h_calls);
     if (h_order) (void)hipHostFree(h_order);
     return bfail(SPIN_ENOMEM, "batch slot arrays (%zu slots)", cap);
   }
-  (void)hipFree(b->d_lats);
-  (void)hipFree(b->d_calls);
-  (void)hipFree(b->d_order);
+  device_free(b->d_lats);
+  device_free(b->d_calls);
+  device_free(b->d_order);
   if (b->h_lats) (void)hipHostFree(b->h_lats);
   if (b->h_calls) (void)hipHostFree(b->h_calls);
   if (b->h_order) (void)hipHostFree(b->h_order);
@@ -268,6 +340,8 @@ static int ensure_capacity(spin_batch* b, size_t n) {
   b->h_calls = h_calls;
   b->h_order = h_order;
   b->cap = cap;
+  b->last_calls.clear();  // the new device tables hold nothing yet
+  b->last_order.clear();
   return SPIN_OK;
 }
 
@@ -312,7 +386,7 @@ static int init_member(spin_batch* b, int slot, const spin_desc& s, bool upload)
     b->next_aux = (b->next_aux + 1) % spin_batch::kAux;
     c.stream = b->aux[mb.aux];
     mb.big = spin_create_config(&c);
-    if (!mb.big) return SPIN_EINVAL;  // message set by spin_create_config
+    if (!mb.big) return spin_last_status();  // status and message set by spin_create_config
     mb.active = true;
     return SPIN_OK;
   }
@@ -362,7 +436,7 @@ static int init_member(spin_batch* b, int slot, const spin_desc& s, bool upload)
       e = hipMemcpyAsync(tmp, s.couplings, nbytes, hipMemcpyHostToDevice, b->stream);
       if (e == hipSuccess) e = launch_pack_nibbles(tmp, mb.jn, nbytes, b->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-      (void)hipFree(tmp);
+      device_free(tmp);
       if (e != hipSuccess) return hfail(e, "coupling upload");
     }
     bl.Jn = mb.jn;
@@ -425,21 +499,29 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
   if (!n || !beta) return bfail(SPIN_EINVAL, "NULL n or beta array");
   if (every < 0) return bfail(SPIN_EINVAL, "every must be >= 0");
   const int S = (int)b->m.size();
+  const bool cap = capturing(b);
+  if (!cap)
+    if (int rc = refresh_counters(b)) return rc;
   for (int i = 0; i < S; ++i) {
     const Member& mb = b->m[i];
     if (!mb.active) {
       if (n[i] != 0) return bfail(SPIN_EINVAL, "slot %d holds no lattice but n[%d] = %d", i, i, n[i]);
       continue;
     }
+    if (cap && !mb.resident && (n[i] > 0 || rec_count(n[i], every)))
+      return bfail(SPIN_ESTATE, "slot %d: a captured pool call can sweep only members held in LDS", i);
     if (n[i] < 0) return bfail(SPIN_EINVAL, "slot %d: n must be >= 0", i);
     if (std::isnan(beta[i]) || beta[i] < 0) return bfail(SPIN_EINVAL, "slot %d: bad beta %g", i, beta[i]);
     const uint64_t t = mb.big ? spin_sweeps_done(mb.big) : mb.t;
     if (t + (uint64_t)n[i] > ((uint64_t)1 << 32)) return bfail(SPIN_EINVAL, "slot %d: sweep index past 2^32", i);
     if (rec_count(n[i], every) && (!dE || !dM)) return bfail(SPIN_EINVAL, "NULL record arrays");
   }
-  // the previous call's uploads must have been read before the host buffers change
-  hipError_t e = hipEventSynchronize(b->uploaded);
+  // the previous call's uploads must have been read before the host buffers change (a captured
+  // call uploads nothing and changes nothing the previous upload reads)
+  hipError_t e = cap ? hipSuccess : hipEventSynchronize(b->uploaded);
   if (e != hipSuccess) return hfail(e, "batch upload wait");
+  std::vector<BatchCall> saved;
+  if (cap) saved.assign(b->h_calls, b->h_calls + S);
   size_t rec = 0;
   std::map<std::tuple<int, int, uint32_t>, size_t> cls_index;
   std::vector<Class> classes;
@@ -463,16 +545,23 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     c.M = nr ? dM + rec : nullptr;
     rec += nr;
     if (c.n == 0 && c.every == 0) continue;
-    const uint32_t nt = batch_threads_for(mb.N / 8);
+    Plan pl{0, 0};
+    const bool planned = b->force_nt ? (pl = Plan{b->force_nt, b->force_per_cu}, true)
+                                     : plan_for(mb.d, mb.model, mb.L, &pl);
+    const uint32_t nt = planned ? pl.nt : batch_threads_for(mb.N / 8);
     const auto key = std::make_tuple(mb.d, mb.model, nt);
     auto it = cls_index.find(key);
     if (it == cls_index.end()) {
       it = cls_index.emplace(key, classes.size()).first;
-      classes.push_back(Class{(uint32_t)mb.d, mb.model == SPIN_EA_PMJ, nt, 0, {}});
+      classes.push_back(Class{(uint32_t)mb.d, mb.model == SPIN_EA_PMJ, nt, 0, {}, 0, false});
     }
     Class& cl = classes[it->second];
     cl.members.push_back((uint32_t)i);
     cl.lds = std::max(cl.lds, batch_lds_bytes((uint32_t)mb.L, (uint32_t)mb.d));
+    if (planned)
+      cl.per_cu = cl.per_cu ? std::min(cl.per_cu, pl.per_cu) : pl.per_cu;
+    else
+      cl.unplanned = true;
   }
   // members too large for one workgroup: the single-lattice kernels on their own streams, forked
   // before the persistent launches so that both run at once
@@ -513,22 +602,41 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     for (uint32_t i : cl.members) b->h_order[norder++] = i;
     ranges.push_back({start, (uint32_t)cl.members.size()});
   }
-  if (norder) {
+  // upload the tables unless the device already holds them (same calls for the resident members,
+  // same task order)
+  bool same = norder && norder == b->last_order.size() && b->last_calls.size() == (size_t)S &&
+              std::memcmp(b->last_order.data(), b->h_order, sizeof(uint32_t) * norder) == 0;
+  for (int i = 0; same && i < S; ++i)
+    if (b->m[i].active && b->m[i].resident)
+      same = std::memcmp(&b->last_calls[i], &b->h_calls[i], sizeof(BatchCall)) == 0;
+  if (norder && !same && cap) {
+    std::copy(saved.begin(), saved.end(), b->h_calls);
+    return bfail(SPIN_ESTATE,
+                 "a captured pool call must repeat the arguments of the pool's previous call (make that call "
+                 "once uncaptured first)");
+  }
+  if (norder && !same) {
     e = hipMemcpyAsync(b->d_calls, b->h_calls, sizeof(BatchCall) * S, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->d_order, b->h_order, sizeof(uint32_t) * norder, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, b->stream);
     if (e != hipSuccess) {
+      b->last_calls.clear();
+      b->last_order.clear();
       join_aux(b, used);
       return hfail(e, "batch upload");
     }
+    b->last_calls.assign(b->h_calls, b->h_calls + S);
+    b->last_order.assign(b->h_order, b->h_order + norder);
   }
   for (size_t k = 0; k < classes.size(); ++k) {
     const Class& cl = classes[k];
     const uint32_t ntasks = ranges[k].second;
-    uint32_t per_cu = std::min<uint32_t>(2048u / cl.nt, (uint32_t)((160 * 1024 - 256) / cl.lds));
+    // workgroups per CU: the override, else the plan when every member has one (never more than
+    // the class's LDS allows), else as many as threads and LDS allow
+    uint32_t per_cu = max_per_cu(cl.nt, cl.lds);
+    if (cl.per_cu && !cl.unplanned) per_cu = std::min(per_cu, cl.per_cu);
     if (b->wgs_override > 0) per_cu = (uint32_t)b->wgs_override;
-    if (per_cu < 1) per_cu = 1;
     const uint32_t grid = std::min<uint32_t>(ntasks, per_cu * (uint32_t)b->num_cu);
     e = launch_batch(cl.d, cl.ea, cl.nt, b->d_lats, b->d_calls, b->d_order + ranges[k].first, ntasks,
                      b->d_counters + k, cl.lds, grid, b->stream);
@@ -539,8 +647,12 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
   }
   // join: later work on the pool's stream waits for the larger members
   if (int rc = join_aux(b, used)) return rc;
-  for (int i = 0; i < S; ++i)
-    if (b->m[i].active && b->m[i].resident) b->m[i].t += (uint64_t)n[i];
+  if (cap) {
+    b->t_stale = true;  // every replay advances the device counters
+  } else {
+    for (int i = 0; i < S; ++i)
+      if (b->m[i].active && b->m[i].resident) b->m[i].t += (uint64_t)n[i];
+  }
   return SPIN_OK;
 }
 
@@ -624,7 +736,8 @@ int spin_batch_is_member(const spin_batch* b, int i) { return slot_ok(b, i) ? 1 
 uint64_t spin_batch_footprint(const spin_batch* b, int i) {
   if (!slot_ok(b, i)) return 0;
   const Member& mb = b->m[i];
-  if (mb.big) return mb.N * (mb.model == SPIN_EA_PMJ ? 2 + mb.d : 2);  // spins, ping-pong copy, int8 couplings
+  // spins, ping-pong copy, and for the glass the int8 couplings and their nibble-packed copy
+  if (mb.big) return mb.N * 2 + (mb.model == SPIN_EA_PMJ ? (uint64_t)mb.d * mb.N + (uint64_t)mb.d * mb.N / 2 : 0);
   return mb.N + (mb.model == SPIN_EA_PMJ ? (uint64_t)mb.d * mb.N / 2 : 0);
 }
 
@@ -640,7 +753,7 @@ int spin_batch_sweep(spin_batch* b, const int* n, const double* beta, int every,
   if (nr && (!E || !M)) return bfail(SPIN_EINVAL, "NULL record arrays");
   if (nr > b->rec_cap) {
     (void)hipStreamSynchronize(b->stream);
-    (void)hipFree(b->d_rec);
+    device_free(b->d_rec);
     if (!dmalloc(&b->d_rec, 2 * nr * sizeof(int64_t))) {
       b->rec_cap = 0;
       return bfail(SPIN_ENOMEM, "record buffer allocation failed");
@@ -706,6 +819,7 @@ int spin_batch_set_spins(spin_batch* b, int i, const int8_t* in, size_t n) {
 
 uint64_t spin_batch_sweeps_done(const spin_batch* b, int i) {
   if (!slot_ok(b, i)) return 0;
+  if (b->t_stale && !capturing(b) && refresh_counters(const_cast<spin_batch*>(b)) != SPIN_OK) return 0;
   return b->m[i].big ? spin_sweeps_done(b->m[i].big) : b->m[i].t;
 }
 
@@ -714,6 +828,115 @@ int spin_batch_set_workgroups_per_cu(spin_batch* b, int wgs) {
   if (wgs < 0 || wgs > 8) return bfail(SPIN_EINVAL, "workgroups per CU must be in 0..8");
   b->wgs_override = wgs;
   return SPIN_OK;
+}
+
+int spin_batch_autotune(spin_batch* b, double beta, int sweeps) {
+  if (!b) return bfail(SPIN_EINVAL, "NULL batch");
+  if (std::isnan(beta) || beta < 0) return bfail(SPIN_EINVAL, "bad beta %g", beta);
+  if (sweeps < 1 || sweeps > 1000) return bfail(SPIN_EINVAL, "sweeps must be in 1..1000");
+  if (int rc = refresh_counters(b)) return rc;
+  std::map<std::tuple<int, int, int>, int> shapes;  // (d, model, L) -> members of the pool
+  for (const Member& mb : b->m)
+    if (mb.active && mb.resident) ++shapes[std::make_tuple(mb.d, mb.model, mb.L)];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hfail(hipGetLastError(), "autotune events");
+  }
+  int tuned = 0, rc = SPIN_OK;
+  for (const auto& sh : shapes) {
+    const int d = std::get<0>(sh.first), model = std::get<1>(sh.first), L = std::get<2>(sh.first);
+    // scratch lattices of this shape, as many as the pool holds (at most four per CU): the launch
+    // sees the same number of tasks per CU as the pool's own calls
+    const int K = std::min(sh.second, 4 * b->num_cu);
+    std::vector<spin_desc> descs(K);
+    for (int r = 0; r < K; ++r) {
+      descs[r].model = model;
+      descs[r].L = L;
+      descs[r].d = d;
+      descs[r].couplings = nullptr;
+      descs[r].coupling_seed = 0x5EED00000001ull;
+      descs[r].realisation = (uint32_t)(r % 64);
+      descs[r].seed = 0x5EED00000000ull;
+      descs[r].replica = (uint32_t)r;
+    }
+    const size_t lds = batch_lds_bytes((uint32_t)L, (uint32_t)d);
+    struct Cand {
+      uint32_t nt, per_cu;
+      float ms;
+      uint64_t hash;
+    };
+    std::vector<Cand> cands;
+    for (uint32_t nt : {256u, 512u, 1024u}) {
+      if ((uint32_t)L / 8 > nt) continue;
+      for (uint32_t pc = 1; pc <= max_per_cu(nt, lds); ++pc) cands.push_back(Cand{nt, pc, 0.f, 0});
+    }
+    for (Cand& c : cands) {
+      spin_batch* t = spin_batch_create(K, descs.data(), b->stream);
+      if (!t) {
+        rc = spin_last_status();
+        break;
+      }
+      t->force_nt = c.nt;
+      t->force_per_cu = c.per_cu;
+      std::vector<int> n(K, 1);
+      std::vector<double> bt(K, beta);
+      rc = batch_run(t, n.data(), bt.data(), 0, nullptr, nullptr);  // warm-up sweep
+      std::fill(n.begin(), n.end(), sweeps);
+      hipError_t e = rc == SPIN_OK ? hipEventRecord(e0, b->stream) : hipSuccess;
+      if (rc == SPIN_OK && e == hipSuccess) rc = batch_run(t, n.data(), bt.data(), 0, nullptr, nullptr);
+      if (rc == SPIN_OK && e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (rc == SPIN_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      if (rc == SPIN_OK && e == hipSuccess) e = hipEventElapsedTime(&c.ms, e0, e1);
+      if (rc == SPIN_OK && e != hipSuccess) rc = hfail(e, "autotune timing");
+      // FNV-1a over the final spins of three members: every candidate must give the same bits
+      uint64_t h = 1469598103934665603ull;
+      std::vector<int8_t> sp;
+      for (int i : {0, K / 2, K - 1}) {
+        if (rc != SPIN_OK) break;
+        sp.resize(t->m[i].N);
+        rc = spin_batch_get_spins(t, i, sp.data(), sp.size());
+        for (int8_t v : sp) h = (h ^ (uint8_t)v) * 1099511628211ull;
+      }
+      c.hash = h;
+      spin_batch_free(t);
+      if (rc != SPIN_OK) break;
+    }
+    if (rc != SPIN_OK) break;
+    const Cand* best = nullptr;
+    for (const Cand& c : cands) {
+      if (c.hash != cands[0].hash) {
+        rc = bfail(SPIN_EDEVICE, "autotune: launch shapes (%u, %u) and (%u, %u) gave different spins for L=%d d=%d",
+                   c.nt, c.per_cu, cands[0].nt, cands[0].per_cu, L, d);
+        break;
+      }
+      if (!best || c.ms < best->ms) best = &c;
+    }
+    if (rc != SPIN_OK || !best) break;
+    {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
+      load_plans_locked();
+      g_plan[sh.first] = Plan{best->nt, best->per_cu};
+    }
+    const double ns_per_sweep = 1e6 * best->ms / sweeps;
+    tune_cache_append("batch", {d, model, L, (long long)best->nt, (long long)best->per_cu, (long long)ns_per_sweep});
+    ++tuned;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc == SPIN_OK ? tuned : rc;
+}
+
+int spin_batch_plan(int d, int model, int L, int* threads, int* workgroups_per_cu) {
+  if (!threads || !workgroups_per_cu) return bfail(SPIN_EINVAL, "NULL output");
+  Plan pl{0, 0};
+  if (!plan_for(d, model, L, &pl)) {
+    *threads = *workgroups_per_cu = 0;
+    return 0;
+  }
+  *threads = (int)pl.nt;
+  *workgroups_per_cu = (int)pl.per_cu;
+  return 1;
 }
 
 int spin_batch_synchronize(spin_batch* b) {

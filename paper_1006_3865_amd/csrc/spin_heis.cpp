@@ -37,21 +37,20 @@ struct spin_heis {
 static void heis_destroy(spin_heis* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(h->S);
-  (void)hipFree(h->part);
+  device_free(h->S);
+  device_free(h->part);
   delete h;
 }
 
 static int reserve(spin_heis* h, size_t nrec) {
   if (nrec <= h->rec_cap) return SPIN_OK;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(h->part);
+  device_free(h->part);
   h->part = nullptr;
   h->rec_cap = 0;
   const size_t bytes = nrec * heis_measure_blocks(h->N) * 4 * sizeof(double);
-  if (hipMalloc((void**)&h->part, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    h->part = nullptr;
+  h->part = (double*)device_alloc(bytes);
+  if (!h->part) {
     return hfail(SPIN_ENOMEM, "Heisenberg record buffer (%zu bytes)", bytes);
   }
   h->rec_cap = nrec;
@@ -132,9 +131,8 @@ spin_heis* spin_heis_create(int L, int d, uint64_t seed, uint32_t replica, void*
   h->part = nullptr;
   h->rec_cap = 0;
   h->stream = (hipStream_t)stream;
-  if (hipMalloc((void**)&h->S, N * sizeof(float4)) != hipSuccess) {
-    (void)hipGetLastError();
-    h->S = nullptr;
+  h->S = (float4*)device_alloc(N * sizeof(float4));
+  if (!h->S) {
     hfail(SPIN_ENOMEM, "Heisenberg spins (%llu sites)", (unsigned long long)N);
     heis_destroy(h);
     return nullptr;

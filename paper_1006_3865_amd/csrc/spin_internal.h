@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace spin {
 
 // Philox4x32-10 round keys: key (k0, k1) plus i times the Weyl constants
@@ -32,6 +34,22 @@ struct Lat {
   uint32_t replica;
   RoundKeys keys;
 };
+
+// Every device allocation of the library goes through these two: the hook
+// (torch's caching allocator, spin_set_allocator) when given, else
+// hipMalloc / hipFree.  They keep the count of live blocks and apply the
+// injected allocation failure of spin_debug_fault_alloc (or the environment
+// variable SPIN_FAULT_ALLOC), so that out-of-memory paths can be forced.
+void* device_alloc(size_t bytes, void* (*hook)(size_t, void*) = nullptr, void* ctx = nullptr);
+void device_free(void* p, void (*hook)(void*, void*) = nullptr, void* ctx = nullptr);
+
+// Persisted tuning records (spin_autotune, spin_batch_autotune): one line per
+// record, "<kind> <arch> <fields...>", in the file named by SPIN_TUNE_CACHE
+// (default $HOME/.cache/spin-gfx950/tune.txt; empty: not persisted).  Records
+// of other GPU architectures are ignored; for a key the last record wins.
+const char* device_arch();  // "gfx950": the current device's architecture
+std::vector<std::vector<long long>> tune_cache_read(const char* kind);  // fields after <arch>
+void tune_cache_append(const char* kind, const std::vector<long long>& fields);
 
 RoundKeys make_round_keys(uint64_t seed);
 Accept make_accept(double beta, int d);
@@ -108,4 +126,13 @@ struct spin_lattice;
 namespace spin {
 // E, M of a handle's current state into device int64s (asynchronous).
 int record_device(spin_lattice* h, int64_t* E, int64_t* M);
+
+// Device scratch of one sweep call supplied by the caller instead of the
+// handle's own buffers: record partials (part_slots int64) and the one-task
+// block of the LDS-resident path (single_bytes() bytes).
+struct CallScratch {
+  int64_t* part;
+  size_t part_slots;
+  void* single;
+};
 }  // namespace spin

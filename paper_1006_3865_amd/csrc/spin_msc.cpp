@@ -45,23 +45,19 @@ struct spin_msc {
 static void msc_destroy(spin_msc* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(h->S);
-  (void)hipFree(h->S2);
-  (void)hipFree(h->J);
-  (void)hipFree(h->J6);
-  (void)hipFree(h->part);
-  (void)hipFree(h->rec);
+  device_free(h->S);
+  device_free(h->S2);
+  device_free(h->J);
+  device_free(h->J6);
+  device_free(h->part);
+  device_free(h->rec);
   delete h;
 }
 
 template <class T>
 static bool dalloc(T** p, size_t bytes) {
-  if (hipMalloc((void**)p, bytes ? bytes : 16) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return false;
-  }
-  return true;
+  *p = (T*)device_alloc(bytes);
+  return *p != nullptr;
 }
 
 static MscArgs msc_args(const spin_msc* h, double beta) {
@@ -117,7 +113,7 @@ static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int6
 static int ensure_rec(spin_msc* h, size_t nrec) {
   if (nrec <= h->rec_cap) return SPIN_OK;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(h->rec);
+  device_free(h->rec);
   h->rec_cap = 0;
   if (!dalloc(&h->rec, 2 * 32 * nrec * sizeof(int64_t))) return mfail(SPIN_ENOMEM, "record buffer allocation failed");
   h->rec_cap = nrec;

@@ -3,6 +3,11 @@
 // and the per-sweep launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
+#include <atomic>
+#include <cstdlib>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -65,6 +70,7 @@ using namespace spin;
 // ------------------------------------------------------------------ errors
 
 static thread_local std::string g_error;
+static thread_local int g_status = SPIN_OK;
 
 static int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -73,11 +79,13 @@ static int fail(int code, const char* fmt, ...) {
   std::vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
   g_error = buf;
+  g_status = code;
   return code;
 }
 
 int spin::set_error(int code, const char* msg) {
   g_error = msg;
+  g_status = code;
   return code;
 }
 
@@ -91,28 +99,138 @@ static void* (*g_alloc)(size_t, void*) = nullptr;
 static void (*g_release)(void*, void*) = nullptr;
 static void* g_ctx = nullptr;
 
+// Injected allocation failure: -2 = the environment not read yet, -1 = off,
+// k >= 0 = k more allocations succeed, the next one fails (then off).
+static std::atomic<int64_t> g_fault_after{-2};
+static std::atomic<int64_t> g_live_blocks{0};
+
+static bool injected_failure() {
+  int64_t v = g_fault_after.load();
+  if (v == -2) {
+    const char* env = std::getenv("SPIN_FAULT_ALLOC");
+    int64_t k = -1;
+    if (env && *env) {
+      char* end = nullptr;
+      const long long x = std::strtoll(env, &end, 10);
+      if (end && *end == 0 && x >= 0) k = (int64_t)x;
+    }
+    g_fault_after.compare_exchange_strong(v, k);
+    v = g_fault_after.load();
+  }
+  while (v >= 0) {
+    if (g_fault_after.compare_exchange_weak(v, v == 0 ? -1 : v - 1)) return v == 0;
+  }
+  return false;
+}
+
+void* spin::device_alloc(size_t bytes, void* (*hook)(size_t, void*), void* ctx) {
+  if (bytes == 0) bytes = 16;
+  if (injected_failure()) return nullptr;
+  void* p = nullptr;
+  if (hook) {
+    p = hook(bytes, ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) ++g_live_blocks;
+  return p;
+}
+
+void spin::device_free(void* p, void (*hook)(void*, void*), void* ctx) {
+  if (!p) return;
+  if (hook)
+    hook(p, ctx);
+  else
+    (void)hipFree(p);
+  --g_live_blocks;
+}
+
+// --------------------------------------------------------------- tuning cache
+
+static std::mutex g_cache_mu;
+
+static std::string tune_cache_path() {
+  const char* env = std::getenv("SPIN_TUNE_CACHE");
+  if (env) return std::string(env);
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return std::string();
+  return std::string(home) + "/.cache/spin-gfx950/tune.txt";
+}
+
+const char* spin::device_arch() {
+  static thread_local char arch[64] = {0};
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    std::snprintf(arch, sizeof(arch), "unknown");
+    return arch;
+  }
+  size_t k = 0;
+  while (k + 1 < sizeof(arch) && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
+    arch[k] = prop.gcnArchName[k];
+    ++k;
+  }
+  arch[k] = 0;
+  return arch;
+}
+
+std::vector<std::vector<long long>> spin::tune_cache_read(const char* kind) {
+  std::vector<std::vector<long long>> out;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return out;
+  const std::string arch = device_arch();
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[32], a[64];
+    int used = 0;
+    if (std::sscanf(line, "%31s %63s%n", k, a, &used) != 2) continue;
+    if (std::strcmp(k, kind) != 0 || arch != a) continue;
+    std::vector<long long> v;
+    const char* p = line + used;
+    long long x;
+    int m = 0;
+    while (std::sscanf(p, "%lld%n", &x, &m) == 1) {
+      v.push_back(x);
+      p += m;
+    }
+    out.push_back(v);
+  }
+  std::fclose(f);
+  return out;
+}
+
+void spin::tune_cache_append(const char* kind, const std::vector<long long>& fields) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const std::string arch = device_arch();
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    // create the directory chain (best effort)
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s %s", kind, arch.c_str());
+  for (long long x : fields) std::fprintf(f, " %lld", x);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
 struct Allocator {
   void* (*alloc)(size_t, void*);
   void (*release)(void*, void*);
   void* ctx;
 
-  void* get(size_t bytes) const {
-    if (bytes == 0) bytes = 16;
-    if (alloc) return alloc(bytes, ctx);
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
-    return p;
-  }
-  void put(void* p) const {
-    if (!p) return;
-    if (release)
-      release(p, ctx);
-    else
-      (void)hipFree(p);
-  }
+  void* get(size_t bytes) const { return device_alloc(bytes, alloc, ctx); }
+  void put(void* p) const { device_free(p, release, ctx); }
 };
 
 // ------------------------------------------------------------------ handle
@@ -204,8 +322,21 @@ struct Tuned {
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, Tuned> g_tuned;
 
+static bool g_tuned_loaded = false;
+
+// Records "lattice <arch> model L d kernel x y z threads": the persisted choices of spin_autotune.
+static void load_tuned_locked() {
+  if (g_tuned_loaded) return;
+  g_tuned_loaded = true;
+  for (const auto& v : tune_cache_read("lattice"))
+    if (v.size() >= 8)
+      g_tuned[std::make_tuple((int)v[0], (int)v[1], (int)v[2])] =
+          Tuned{(int)v[3], Tile{(int)v[4], (int)v[5], (int)v[6], (int)v[7]}};
+}
+
 static bool tuned_choice(const spin_lattice* h, Tuned* out) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tuned_locked();
   auto it = g_tuned.find(std::make_tuple(h->model, h->L, h->d));
   if (it == g_tuned.end()) return false;
   *out = it->second;
@@ -314,6 +445,27 @@ static int reserve_parts(spin_lattice* h, uint32_t nrec, uint32_t parts) {
   return SPIN_OK;
 }
 
+// Partial-count slots for nrec records of `parts` slots each: the caller's fixed
+// scratch (no allocation; too small is an error) or the handle's own buffer.
+static int take_parts(spin_lattice* h, const CallScratch* fx, uint32_t nrec, uint32_t parts, int64_t** out) {
+  *out = nullptr;
+  if (nrec == 0) return SPIN_OK;
+  if (fx) {
+    const size_t need = (size_t)nrec * parts * 2;
+    if (need > fx->part_slots)
+      return fail(SPIN_EINVAL,
+                  "%u records of this lattice need %llu bytes of record scratch, more than the %llu bytes "
+                  "the allocation-free call has (record fewer per call)",
+                  nrec, (unsigned long long)(need * sizeof(int64_t)),
+                  (unsigned long long)(fx->part_slots * sizeof(int64_t)));
+    *out = fx->part;
+    return SPIN_OK;
+  }
+  if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  *out = h->part;
+  return SPIN_OK;
+}
+
 static int64_t e_offset(const spin_lattice* h) { return -(int64_t)h->d * (int64_t)h->N; }
 
 static int check_beta(double beta) {
@@ -322,8 +474,9 @@ static int check_beta(double beta) {
 }
 
 // Nibble-packed couplings (EA) for the kernels that read them, packed on first use.
-static int ensure_jn(spin_lattice* h) {
+static int ensure_jn(spin_lattice* h, const CallScratch* fx = nullptr) {
   if (h->model != SPIN_EA_PMJ || h->jn) return SPIN_OK;
+  if (fx) return fail(SPIN_ESTATE, "the packed couplings of this lattice are not allocated yet");
   const uint64_t nbytes = (uint64_t)h->d * h->N;
   h->jn = (uint32_t*)h->mem.get(nbytes / 2);
   if (!h->jn) return fail(SPIN_ENOMEM, "allocation of the packed couplings failed");
@@ -335,12 +488,13 @@ static int ensure_jn(spin_lattice* h) {
 // n sweeps of the whole lattice in one workgroup's LDS (the batch kernel with
 // one task); records (every > 0) go straight to dE, dM.
 static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM,
-                      uint32_t nt) {
-  if (!h->single) {
+                      uint32_t nt, const CallScratch* fx) {
+  if (!fx && !h->single) {
     h->single = (BatchSingle*)h->mem.get(sizeof(BatchSingle));
     if (!h->single) return fail(SPIN_ENOMEM, "allocation of the one-task block failed");
   }
-  if (int rc = ensure_jn(h)) return rc;
+  BatchSingle* blk = fx ? (BatchSingle*)fx->single : h->single;
+  if (int rc = ensure_jn(h, fx)) return rc;
   BatchLattice bl;
   bl.spins = h->buf[h->cur];
   bl.Jn = h->jn;
@@ -356,21 +510,22 @@ static int run_single(spin_lattice* h, int n, const Accept& acc, int every, int6
   for (int k = 0; k < 8; ++k) c.bound[k] = acc.bound[k];
   c.E = c.every ? dE : nullptr;
   c.M = c.every ? dM : nullptr;
-  hipError_t e = launch_batch_single(h->single, bl, c, nt, h->stream);
+  hipError_t e = launch_batch_single(blk, bl, c, nt, h->stream);
   if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
   return SPIN_OK;
 }
 
 // n sweeps of the coarse-tile schedule (two launches each, one per tile
 // parity), records by the measurement kernel.
-static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM) {
+static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM,
+                      const CallScratch* fx) {
   if ((h->t + (uint64_t)n) * (uint64_t)h->hits > kMaxSweepIndex)
     return fail(SPIN_EINVAL, "sweep index times hits would exceed 2^32");
-  if (int rc = ensure_jn(h)) return rc;
+  if (int rc = ensure_jn(h, fx)) return rc;
   const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
   const uint32_t parts = measure_parts(lat_of(h));
-  if (nrec > 0)
-    if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  int64_t* part = nullptr;
+  if (int rc = take_parts(h, fx, nrec, parts, &part)) return rc;
   hipError_t e = hipSuccess;
   uint32_t rec = 0;
   for (int i = 0; i < n; ++i) {
@@ -380,13 +535,13 @@ static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int6
       e = launch_coarse_phase(l, h->jn, t, (uint32_t)h->hits, q, acc, h->coarse_tile, h->stream);
     if (e != hipSuccess) return hip_fail(e, "coarse phase launch");
     if (every > 0 && (i + 1) % every == 0) {
-      e = launch_measure(l, Record{h->part + (size_t)rec * parts * 2}, h->stream);
+      e = launch_measure(l, Record{part + (size_t)rec * parts * 2}, h->stream);
       if (e != hipSuccess) return hip_fail(e, "measure launch");
       ++rec;
     }
   }
   if (nrec > 0) {
-    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    e = launch_finalize(part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
     if (e != hipSuccess) return hip_fail(e, "record finalize launch");
   }
   h->t += (uint64_t)n;
@@ -395,11 +550,12 @@ static int run_coarse(spin_lattice* h, int n, const Accept& acc, int every, int6
 
 // The canonical chain with LCG draws (spin_set_rng): two colour phases per sweep, records as for the
 // coarse mode.
-static int run_lcg(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM) {
+static int run_lcg(spin_lattice* h, int n, const Accept& acc, int every, int64_t* dE, int64_t* dM,
+                   const CallScratch* fx) {
   const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
   const uint32_t parts = measure_parts(lat_of(h));
-  if (nrec > 0)
-    if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  int64_t* part = nullptr;
+  if (int rc = take_parts(h, fx, nrec, parts, &part)) return rc;
   LcgArgs a;
   for (int i = 0; i < 8; ++i) a.T[i] = acc.T[i];
   a.N = h->N;
@@ -414,13 +570,13 @@ static int run_lcg(spin_lattice* h, int n, const Accept& acc, int every, int64_t
     }
     if (e != hipSuccess) return hip_fail(e, "LCG phase launch");
     if (every > 0 && (i + 1) % every == 0) {
-      e = launch_measure(lat_of(h), Record{h->part + (size_t)rec * parts * 2}, h->stream);
+      e = launch_measure(lat_of(h), Record{part + (size_t)rec * parts * 2}, h->stream);
       if (e != hipSuccess) return hip_fail(e, "measure launch");
       ++rec;
     }
   }
   if (nrec > 0) {
-    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    e = launch_finalize(part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
     if (e != hipSuccess) return hip_fail(e, "record finalize launch");
   }
   h->t += (uint64_t)n;
@@ -428,20 +584,21 @@ static int run_lcg(spin_lattice* h, int n, const Accept& acc, int every, int64_t
 }
 
 // Enqueue n sweeps; if every > 0 write records into device arrays dE, dM.
-static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM) {
+static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* dE, int64_t* dM,
+                      const CallScratch* fx = nullptr) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
   if (n < 0) return fail(SPIN_EINVAL, "n must be >= 0");
   if (int rc = check_beta(beta)) return rc;
   if (h->t + (uint64_t)n > kMaxSweepIndex) return fail(SPIN_EINVAL, "sweep index would exceed 2^32");
   if (n == 0) return SPIN_OK;
   const Accept acc = make_accept(beta, h->d);
-  if (h->rng != SPIN_RNG_PHILOX) return run_lcg(h, n, acc, every, dE, dM);
-  if (h->schedule == SPIN_SCHEDULE_COARSE) return run_coarse(h, n, acc, every, dE, dM);
+  if (h->rng != SPIN_RNG_PHILOX) return run_lcg(h, n, acc, every, dE, dM, fx);
+  if (h->schedule == SPIN_SCHEDULE_COARSE) return run_coarse(h, n, acc, every, dE, dM, fx);
   Tile tile;
   const int kernel = resolve(h, &tile);
   hipError_t e = hipSuccess;
   if (kernel == SPIN_KERNEL_RESIDENT && single_threads(h, tile)) {
-    if (int rc = run_single(h, n, acc, every, dE, dM, single_threads(h, tile))) return rc;
+    if (int rc = run_single(h, n, acc, every, dE, dM, single_threads(h, tile), fx)) return rc;
     h->t += (uint64_t)n;
     return SPIN_OK;
   }
@@ -453,8 +610,9 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
     return SPIN_OK;
   }
   if (kernel == SPIN_KERNEL_STREAM)
-    if (int rc = ensure_jn(h)) return rc;
+    if (int rc = ensure_jn(h, fx)) return rc;
   if ((kernel == SPIN_KERNEL_FUSED || kernel == SPIN_KERNEL_STREAM) && !h->buf[1]) {
+    if (fx) return fail(SPIN_ESTATE, "the second spin buffer of this lattice is not allocated yet");
     h->buf[1] = (int8_t*)h->mem.get(h->N);
     if (!h->buf[1]) return fail(SPIN_ENOMEM, "allocation of the second spin buffer failed");
   }
@@ -462,14 +620,14 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   const uint32_t nrec = every > 0 ? (uint32_t)(n / every) : 0;
   const uint32_t fparts = (kernel == SPIN_KERNEL_FUSED) ? fused_record_parts(lat_of(h), tile) : 0;
   const uint32_t parts = fparts ? fparts : measure_parts(lat_of(h));
-  if (nrec > 0)
-    if (int rc = reserve_parts(h, nrec, parts)) return rc;
+  int64_t* part = nullptr;
+  if (int rc = take_parts(h, fx, nrec, parts, &part)) return rc;
   int rec = 0;
   for (int i = 0; i < n; ++i) {
     const uint32_t t = (uint32_t)(h->t + (uint64_t)i);
     Lat l = lat_of(h);
     const bool record_now = every > 0 && (i + 1) % every == 0;
-    const Record r = Record{record_now ? h->part + (size_t)rec * parts * 2 : nullptr};
+    const Record r = Record{record_now ? part + (size_t)rec * parts * 2 : nullptr};
     bool measured = false;
     if (kernel == SPIN_KERNEL_FUSED) {
       e = launch_fused_sweep(l, h->buf[h->cur], h->buf[1 - h->cur], t, acc, tile,
@@ -496,10 +654,27 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
     }
   }
   if (nrec > 0) {
-    e = launch_finalize(h->part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
+    e = launch_finalize(part, parts, parts, nrec, dE, dM, e_offset(h), (int64_t)h->N, h->stream);
     if (e != hipSuccess) return hip_fail(e, "record finalize launch");
   }
   h->t += (uint64_t)n;
+  return SPIN_OK;
+}
+
+// Allocate what the handle's next sweep needs (the second spin buffer of the
+// ping-pong kernels, the packed couplings), so that sweeping later allocates
+// nothing.
+static int prepare_buffers(spin_lattice* h) {
+  if (h->rng != SPIN_RNG_PHILOX) return SPIN_OK;
+  if (h->schedule == SPIN_SCHEDULE_COARSE) return ensure_jn(h);
+  Tile tile;
+  const int kernel = resolve(h, &tile);
+  if ((kernel == SPIN_KERNEL_RESIDENT && single_threads(h, tile)) || kernel == SPIN_KERNEL_STREAM)
+    if (int rc = ensure_jn(h)) return rc;
+  if ((kernel == SPIN_KERNEL_FUSED || kernel == SPIN_KERNEL_STREAM) && !h->buf[1]) {
+    h->buf[1] = (int8_t*)h->mem.get(h->N);
+    if (!h->buf[1]) return fail(SPIN_ENOMEM, "allocation of the second spin buffer failed");
+  }
   return SPIN_OK;
 }
 
@@ -550,7 +725,17 @@ extern "C" {
 
 const char* spin_last_error(void) { return g_error.c_str(); }
 
+int spin_last_status(void) { return g_status; }
+
 const char* spin_version(void) { return "spin-gfx950 0.1"; }
+
+int spin_debug_fault_alloc(int64_t after) {
+  if (after < -1) return fail(SPIN_EINVAL, "after must be >= -1");
+  g_fault_after.store(after);
+  return SPIN_OK;
+}
+
+int64_t spin_debug_live_allocations(void) { return g_live_blocks.load(); }
 
 void spin_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
   g_alloc = alloc;
@@ -642,6 +827,10 @@ spin_lattice* spin_create_config(const spin_config* cfg) {
   e = launch_init_spins(lat_of(h), h->stream);
   if (e != hipSuccess) {
     hip_fail(e, "hot start");
+    destroy(h);
+    return nullptr;
+  }
+  if (prepare_buffers(h) != SPIN_OK) {
     destroy(h);
     return nullptr;
   }
@@ -778,7 +967,7 @@ int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int til
                   kernel, t.x, t.y, t.z, t.threads, h->L, h->d, h->model);
     }
   }
-  return SPIN_OK;
+  return prepare_buffers(h);
 }
 
 int spin_autotune(spin_lattice* h, double beta, int sweeps) {
@@ -830,12 +1019,17 @@ int spin_autotune(spin_lattice* h, double beta, int sweeps) {
   (void)hipEventDestroy(e1);
   destroy(s);
   g_error.clear();
+  g_status = SPIN_OK;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tuned_locked();
     g_tuned[std::make_tuple(h->model, h->L, h->d)] = best;
   }
+  tune_cache_append("lattice", {h->model, h->L, h->d, best.kernel, best.tile.x, best.tile.y, best.tile.z,
+                                best.tile.threads});
   h->kernel = best.kernel;
   h->tile = best.tile;
+  if (int rc = prepare_buffers(h)) return rc;
   return best.kernel;
 }
 
@@ -857,7 +1051,7 @@ int spin_set_schedule(spin_lattice* h, int schedule, int tile, int hits) {
   h->schedule = schedule;
   h->coarse_tile = tile;
   h->hits = hits;
-  return SPIN_OK;
+  return prepare_buffers(h);
 }
 
 int spin_set_rng(spin_lattice* h, int rng) {

@@ -41,11 +41,12 @@ def lds_resident(L, d):
 
 def footprint(job):
     """Device bytes of a job in the pool: spins (a second buffer for the streaming kernels of
-    larger lattices) plus its couplings (nibble-packed in the persistent kernel's layout)."""
+    larger lattices) plus its couplings (nibble-packed in the persistent kernel's layout; int8 and
+    nibble-packed for the larger lattices)."""
     N = job["L"] ** job["d"]
     if lds_resident(job["L"], job["d"]):
         return N + (job["d"] * N // 2 if job["model"] == 1 else 0)
-    return 2 * N + (job["d"] * N if job["model"] == 1 else 0)
+    return 2 * N + (job["d"] * N + job["d"] * N // 2 if job["model"] == 1 else 0)
 
 
 def percentile(values, q):
@@ -126,8 +127,24 @@ class Server:
             q = self.tick_s * rate / (N * share)
         return int(min(job["left"], max(1, math.floor(q))))
 
-    def serve(self, trace):
-        """Run every job of the trace; returns dict job -> result (E, M, latency, ...)."""
+    def _cancelled(self, j, now, cancel):
+        """Why job j is to be cancelled at trace time now, or None."""
+        at = cancel.get(j["job"]) if cancel else None
+        if at is not None and at <= now:
+            return "cancelled"
+        dl = j.get("deadline_s")
+        if dl is not None and now - j["arrival"] > dl:
+            return "deadline"
+        return None
+
+    def serve(self, trace, cancel=None):
+        """Run every job of the trace; returns dict job -> result (E, M, latency, ...).
+
+        cancel: optional dict job -> trace time of a cancellation request.  A job with a
+        "deadline_s" field is cancelled by the watchdog once its age (now - arrival) exceeds it.
+        Both take effect at the next tick boundary: a waiting job is dropped, a resident one leaves
+        the pool and frees its slot and budget; its result is {cancelled: True, reason, sweeps_done,
+        arrival, finished, latency}.  The other jobs' results do not change."""
         jobs = sorted((dict(j) for j in trace), key=lambda j: (j["arrival"], j["job"]))
         for j in jobs:
             if footprint(j) > self.budget:
@@ -139,6 +156,20 @@ class Server:
         now = 0.0
         while waiting or resident:
             t0 = self.clock()
+            # cancellations and the watchdog
+            for j in [j for j in waiting if j["arrival"] <= now and self._cancelled(j, now, cancel)]:
+                waiting.remove(j)
+                results[j["job"]] = dict(cancelled=True, reason=self._cancelled(j, now, cancel), sweeps_done=0,
+                                         arrival=j["arrival"], finished=now, latency=now - j["arrival"])
+            for s in [s for s, j in resident.items() if self._cancelled(j, now, cancel)]:
+                j = resident.pop(s)
+                self.ex.remove(s)
+                used -= footprint(j)
+                results[j["job"]] = dict(cancelled=True, reason=self._cancelled(j, now, cancel),
+                                         sweeps_done=j["sweeps"] - j["left"], arrival=j["arrival"],
+                                         admitted=j["admitted"], finished=now, latency=now - j["arrival"])
+            if not waiting and not resident:
+                break
             # admission, first come first served
             while waiting and waiting[0]["arrival"] <= now:
                 j = waiting[0]
@@ -219,7 +250,7 @@ def lone_service(job, spins_out=None):
 
 
 def summarize(results, trace):
-    lat = [r["latency"] for r in results.values()]
+    lat = [r["latency"] for r in results.values() if not r.get("cancelled")]
     work = sum(j["L"] ** j["d"] * j["sweeps"] for j in trace)
     span = max(r["finished"] for r in results.values()) - min(j["arrival"] for j in trace)
     return dict(jobs=len(results), p50_s=percentile(lat, 50), p99_s=percentile(lat, 99),

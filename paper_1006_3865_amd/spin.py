@@ -91,7 +91,10 @@ SIGNATURES = {
     "spin_device_spins": (_c.c_void_p, [_P]),
     "spin_threshold_table": (_c.c_int, [_c.c_double, _c.c_int, _u64p]),
     "spin_set_allocator": (None, [ALLOC_FN, RELEASE_FN, _c.c_void_p]),
+    "spin_debug_fault_alloc": (_c.c_int, [_c.c_int64]),
+    "spin_debug_live_allocations": (_c.c_int64, []),
     "spin_last_error": (_c.c_char_p, []),
+    "spin_last_status": (_c.c_int, []),
     "spin_version": (_c.c_char_p, []),
     "spin_batch_create": (_P, [_c.c_int, _c.POINTER(spin_desc), _c.c_void_p]),
     "spin_batch_free": (None, [_P]),
@@ -100,6 +103,8 @@ SIGNATURES = {
     "spin_batch_remove": (_c.c_int, [_P, _c.c_int]),
     "spin_batch_is_member": (_c.c_int, [_P, _c.c_int]),
     "spin_batch_footprint": (_c.c_uint64, [_P, _c.c_int]),
+    "spin_batch_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
+    "spin_batch_plan": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
     "spin_batch_sweep": (_c.c_int, [_P, _ip, _dp, _c.c_int, _i64p, _i64p]),
     "spin_batch_sweep_device": (_c.c_int, [_P, _ip, _dp, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "spin_batch_measure": (_c.c_int, [_P, _i64p, _i64p]),
@@ -142,6 +147,12 @@ class SpinError(RuntimeError):
         self.code = code
 
 
+def _null_status():
+    """Status of the constructor call that just returned NULL (EINVAL if none was set)."""
+    rc = load().spin_last_status()
+    return rc if rc < 0 else SPIN_EINVAL
+
+
 def _check(rc):
     """Raise on a negative status; return rc (a slot index for spin_batch_add)."""
     if rc < 0:
@@ -180,7 +191,7 @@ def spin_create(model, L, d, couplings, seed):
     J = None if couplings is None else np.ascontiguousarray(couplings, dtype=np.int8)
     h = lib.spin_create(model, L, d, None if J is None else _i8(J), seed)
     if not h:
-        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+        raise SpinError(_null_status(), lib.spin_last_error().decode())
     return h
 
 
@@ -192,7 +203,7 @@ def spin_create_config(model, L, d, couplings=None, coupling_seed=0, realisation
                       stream)
     h = lib.spin_create_config(_c.byref(cfg))
     if not h:
-        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+        raise SpinError(_null_status(), lib.spin_last_error().decode())
     return h
 
 
@@ -305,6 +316,22 @@ def use_torch_allocator():
 
     _torch_hooks = (ALLOC_FN(_alloc), RELEASE_FN(_release))
     load().spin_set_allocator(_torch_hooks[0], _torch_hooks[1], None)
+
+
+def fault_alloc(after):
+    """Make the library's allocation after `after` more successful ones fail (-1: off)."""
+    _check(load().spin_debug_fault_alloc(int(after)))
+
+
+def live_allocations():
+    """Device blocks the library holds now."""
+    return int(load().spin_debug_live_allocations())
+
+
+def batch_plan(d, model, L):
+    """(threads, workgroups per CU) of the persistent kernel's plan for a shape, or None."""
+    t, w = _c.c_int(), _c.c_int()
+    return (t.value, w.value) if load().spin_batch_plan(d, model, L, _c.byref(t), _c.byref(w)) else None
 
 
 def use_hip_allocator():
@@ -425,7 +452,7 @@ def spin_batch_create(descs, stream=None):
         arr[i] = _desc(d, keep)
     h = lib.spin_batch_create(len(descs), arr, stream)
     if not h:
-        raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+        raise SpinError(_null_status(), lib.spin_last_error().decode())
     return h
 
 
@@ -542,6 +569,11 @@ class Batch:
     def t(self, i):
         return int(load().spin_batch_sweeps_done(self.h, i))
 
+    def autotune(self, beta, sweeps=20):
+        """Time the persistent kernel's launch shapes per lattice shape of the pool; returns the
+        number of shapes tuned (their plans apply to every pool and are persisted)."""
+        return _check(load().spin_batch_autotune(self.h, float(beta), int(sweeps)))
+
     def set_workgroups_per_cu(self, w):
         _check(load().spin_batch_set_workgroups_per_cu(self.h, w))
 
@@ -561,7 +593,7 @@ class Msc:
         lib = load()
         self.h = lib.spin_msc_create(L, d, coupling_seed, realisation0, seed, replica0, sp)
         if not self.h:
-            raise SpinError(SPIN_EINVAL, lib.spin_last_error().decode())
+            raise SpinError(_null_status(), lib.spin_last_error().decode())
         self.L, self.d, self.N = L, d, L ** d
 
     def close(self):
@@ -617,7 +649,7 @@ class Heis:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
         self.h = load().spin_heis_create(int(L), int(d), int(seed), int(replica), sp)
         if not self.h:
-            raise SpinError(SPIN_EINVAL, load().spin_last_error().decode())
+            raise SpinError(_null_status(), load().spin_last_error().decode())
         self.L, self.d, self.N = L, d, L ** d
 
     def close(self):

@@ -14,6 +14,10 @@ if HERE not in sys.path:
 
 
 def pytest_configure(config):
+    # tuning choices made by the tests (a few sweeps each) go to a file of this run only, never to the
+    # user's cache, where a later benchmark would pick them up
+    import tempfile
+    os.environ["SPIN_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="spin-tune-"), "tune.txt")
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long statistical run")
 

@@ -184,7 +184,7 @@ def test_footprint_rule():
     assert not serve.lds_resident(12, 2)
     assert serve.footprint(dict(model=1, L=16, d=3)) == 4096 + 3 * 4096 // 2
     assert serve.footprint(dict(model=0, L=1024, d=2)) == 2 * 1024 ** 2
-    assert serve.footprint(dict(model=1, L=72, d=3)) == 2 * 72 ** 3 + 3 * 72 ** 3
+    assert serve.footprint(dict(model=1, L=72, d=3)) == 2 * 72 ** 3 + 3 * 72 ** 3 + 3 * 72 ** 3 // 2
 
 
 class OracleExecutor:
@@ -255,6 +255,78 @@ def test_ticked_jobs_equal_one_shot_runs(oracle_mod):
     res = srv.serve(tr)
     assert srv.ticks > 10
     for j in tr:
+        d = serve.job_desc(j)
+        J = oracle_mod.couplings(d["L"], d["d"], d["coupling_seed"], 0) if j["model"] == 1 else None
+        ch = oracle_mod.Chain(d["L"], d["d"], d["seed"], 0, J=J)
+        ch.sweep(j["sweeps"], j["beta"])
+        np.testing.assert_array_equal(res[j["job"]]["spins"], ch.spins)
+        assert (res[j["job"]]["E"], res[j["job"]]["M"]) == ch.measure()
+
+
+def test_cancel_waiting_job_never_admitted():
+    """A job cancelled while it waits for budget is dropped without being admitted."""
+    clock = Clock()
+    budget = 3 << 20
+    tr = [dict(job=k, arrival=0.0, model=0, d=2, L=1024, beta=0.4, sweeps=2000, seed=k) for k in range(3)]
+    ex = FakeExecutor(clock, budget, 8)
+    srv = serve.Server(ex, budget_bytes=budget, max_slots=8, clock=clock)
+    res = srv.serve(tr, cancel={2: 0.0})
+    assert res[2]["cancelled"] and res[2]["reason"] == "cancelled" and res[2]["sweeps_done"] == 0
+    assert 2 not in ex.admit_order
+    for k in (0, 1):
+        assert not res[k].get("cancelled") and ex.done_sweeps[k] == 2000 and res[k]["M"] == 2000
+
+
+def test_cancel_resident_job_frees_slot_and_budget():
+    """Cancelling a running job frees its slot and budget for the job queued behind it."""
+    clock = Clock()
+    budget = 2 << 20                                 # one L = 1024 job (2 MiB) at a time
+    tr = [dict(job=0, arrival=0.0, model=0, d=2, L=1024, beta=0.4, sweeps=10 ** 6, seed=1),
+          dict(job=1, arrival=0.0, model=0, d=2, L=1024, beta=0.4, sweeps=300, seed=2)]
+    ex = FakeExecutor(clock, budget, 1)
+    srv = serve.Server(ex, budget_bytes=budget, max_slots=1, clock=clock)
+    res = srv.serve(tr, cancel={0: 0.05})
+    r0 = res[0]
+    assert r0["cancelled"] and 0 < r0["sweeps_done"] < 10 ** 6
+    assert r0["sweeps_done"] == ex.done_sweeps[0]
+    assert r0["finished"] >= 0.05
+    assert ex.admit_order == [0, 1]
+    assert not res[1].get("cancelled") and ex.done_sweeps[1] == 300
+    assert res[1]["admitted"] >= r0["finished"]
+    assert ex.peak_used <= budget
+
+
+def test_deadline_watchdog_cancels_overdue_jobs():
+    clock = Clock()
+    tr = [dict(job=0, arrival=0.0, model=0, d=2, L=2048, beta=0.4, sweeps=10 ** 6, seed=1, deadline_s=0.2),
+          dict(job=1, arrival=0.0, model=0, d=2, L=32, beta=0.4, sweeps=100, seed=2, deadline_s=100.0)]
+    ex = FakeExecutor(clock, 1 << 30, 8)
+    res = serve.Server(ex, clock=clock).serve(tr)
+    assert res[0]["cancelled"] and res[0]["reason"] == "deadline"
+    assert res[0]["latency"] > 0.2 and res[0]["sweeps_done"] < 10 ** 6   # stopped at the first tick past it
+    assert not res[1].get("cancelled") and ex.done_sweeps[1] == 100
+    s = serve.summarize(res, tr)
+    assert s["jobs"] == 2
+
+
+def test_cancellation_leaves_other_results_unchanged(oracle_mod):
+    """Jobs that share the pool with a cancelled one end in the same state as run alone."""
+    tr = [dict(job=k, arrival=0.0, model=k % 2, d=3 if k % 2 else 2, L=16 if k % 2 else 32,
+               beta=0.3 + 0.1 * k, sweeps=40, seed=workloads.seed(0x5000 + k),
+               coupling_seed=workloads.seed(0x6000 + k)) for k in range(5)]
+    clock = Clock()
+
+    def tick_clock():
+        clock.t += 1e-4
+        return clock.t
+
+    ex = OracleExecutor(oracle_mod)
+    srv = serve.Server(ex, tick_s=1e-4, rate_wg=4e6, rate_big=4e6, clock=tick_clock, keep_spins=True)
+    res = srv.serve(tr, cancel={2: 5e-4})
+    assert res[2]["cancelled"] and 0 < res[2]["sweeps_done"] < 40
+    for j in tr:
+        if j["job"] == 2:
+            continue
         d = serve.job_desc(j)
         J = oracle_mod.couplings(d["L"], d["d"], d["coupling_seed"], 0) if j["model"] == 1 else None
         ch = oracle_mod.Chain(d["L"], d["d"], d["seed"], 0, J=J)
