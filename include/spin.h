@@ -138,6 +138,24 @@ int spin_sweep_record(spin_lattice* h, int n, double beta, int every, int64_t* E
  * written asynchronously on the handle's stream. */
 int spin_sweep_record_device(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as spin_sweep_record_device -- same arguments, same bits, E and M
+ * DEVICE arrays of n/every int64 owned by the caller -- that calls no
+ * hipMalloc/hipFree (nor the allocator hook) and never synchronises.  Its
+ * scratch (the per-workgroup partial counts of the records, and the task
+ * block of the LDS-resident path) is one library-owned device array of
+ * SPIN_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.  A call
+ * whose records need more than that fails with SPIN_EINVAL before any work
+ * (record fewer sweeps per call); a handle whose buffers for its kernel are
+ * missing (possible only after another handle's spin_autotune changed the
+ * automatic choice) fails with SPIN_ESTATE -- spin_create, spin_set_kernel,
+ * spin_set_schedule and spin_autotune allocate them.  All calls on one GPU
+ * share the array and keep the last call's contents: calls that overlap on
+ * one GPU (two threads, or two streams running at once) race. */
+#define SPIN_NOALLOC_SCRATCH_BYTES ((size_t)2 << 20)
+int spin_sweep_record_noalloc(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M);
+
 /* Sec. 4 (the energy and magnetisation measured between sweeps): current
  * E and M into host int64s.  Synchronises. */
 int spin_measure(spin_lattice* h, int64_t* E, int64_t* M);

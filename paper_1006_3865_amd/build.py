@@ -13,7 +13,7 @@ LIB = os.path.join(PKG, "libspin.so")
 
 SOURCES = ["spin_kernels.hip", "spin_stream2d.hip", "spin_stream3d.hip", "spin_stream_kernels.hip",
            "spin_coarse_kernels.hip", "spin_batch_kernels.hip", "spin_msc_kernels.hip", "spin_lcg_kernels.hip",
-           "spin_heis_kernels.hip", "spin_probe_kernels.hip", "spin_runtime.cpp", "spin_batch.cpp", "spin_msc.cpp", "spin_heis.cpp"]
+           "spin_heis_kernels.hip", "spin_probe_kernels.hip", "spin_noalloc.hip", "spin_runtime.cpp", "spin_batch.cpp", "spin_msc.cpp", "spin_heis.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

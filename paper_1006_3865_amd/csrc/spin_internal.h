@@ -135,4 +135,9 @@ struct CallScratch {
   size_t part_slots;
   void* single;
 };
+size_t single_bytes();
+// spin_sweep_record_device on fixed scratch: allocates nothing, never
+// synchronises; buffers the handle lacks are an SPIN_ESTATE error.
+int sweep_record_fixed(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M,
+                       const CallScratch& fx);
 }  // namespace spin

@@ -661,6 +661,16 @@ static int run_sweeps(spin_lattice* h, int n, double beta, int every, int64_t* d
   return SPIN_OK;
 }
 
+size_t spin::single_bytes() { return sizeof(BatchSingle); }
+
+int spin::sweep_record_fixed(spin_lattice* h, int n, double beta, int every, int64_t* E, int64_t* M,
+                             const CallScratch& fx) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (every < 1) return fail(SPIN_EINVAL, "every must be >= 1");
+  if (n / every > 0 && (!E || !M)) return fail(SPIN_EINVAL, "NULL record arrays");
+  return run_sweeps(h, n, beta, every, E, M, &fx);
+}
+
 // Allocate what the handle's next sweep needs (the second spin buffer of the
 // ping-pong kernels, the packed couplings), so that sweeping later allocates
 // nothing.

@@ -55,6 +55,7 @@ SIGNATURES = {
     "spin_sweep": (_c.c_int, [_P, _c.c_int, _c.c_double]),
     "spin_sweep_record": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _i64p, _i64p]),
     "spin_sweep_record_device": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p]),
+    "spin_sweep_record_noalloc": (_c.c_int, [_P, _c.c_int, _c.c_double, _c.c_int, _c.c_void_p, _c.c_void_p]),
     "spin_measure": (_c.c_int, [_P, _i64p, _i64p]),
     "spin_get_spins": (_c.c_int, [_P, _i8p, _c.c_size_t]),
     "spin_set_spins": (_c.c_int, [_P, _i8p, _c.c_size_t]),
@@ -227,6 +228,14 @@ def spin_sweep_record_device(h, n, beta, every, E_ptr, M_ptr):
     return _check(load().spin_sweep_record_device(h, n, beta, every, E_ptr, M_ptr))
 
 
+def spin_sweep_record_noalloc(h, n, beta, every, E_ptr, M_ptr):
+    return _check(load().spin_sweep_record_noalloc(h, n, beta, every, E_ptr, M_ptr))
+
+
+# bytes of the device scratch array behind spin_sweep_record_noalloc (SPIN_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 2 << 20
+
+
 def spin_measure(h):
     E, M = _c.c_int64(), _c.c_int64()
     _check(load().spin_measure(h, _c.byref(E), _c.byref(M)))
@@ -377,6 +386,14 @@ class Lattice:
         check_record_tensors(E, M, n // every if n > 0 else 0)
         spin_sweep_record_device(self.h, n, beta, every, E.data_ptr() if E is not None else None,
                                  M.data_ptr() if M is not None else None)
+
+    def sweep_record_noalloc(self, n, beta, every, E, M):
+        """As sweep_record_device, on the library's fixed scratch array: no device allocation."""
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        check_record_tensors(E, M, n // every if n > 0 else 0)
+        spin_sweep_record_noalloc(self.h, n, beta, every, E.data_ptr() if E is not None else None,
+                                  M.data_ptr() if M is not None else None)
 
     def measure(self):
         return spin_measure(self.h)
