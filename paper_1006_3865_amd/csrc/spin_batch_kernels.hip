@@ -102,36 +102,141 @@ __device__ void batch_record(const BatchLattice& B, const BatchCall& Cl, const u
   }
 }
 
-// One task: lattice B, sweeps B.t .. B.t+n-1, all in LDS.  n == 0 with
-// every > 0 records the current state once.
-template <int D, bool EA, int NT>
-__device__ void batch_task(const BatchLattice& B, const BatchCall& Cl, uint32_t* sp, uint32_t* bound,
-                           int64_t* red) {
-  const uint32_t L = B.L;
-  const uint32_t LG = L / 8;                       // words per row
-  const uint32_t R = (D == 3) ? L * L : L;         // rows
-  const uint32_t NW = R * LG;                      // words
-  const uint32_t PS = L * LG;                      // words per plane (3D)
-  const uint32_t tid = threadIdx.x;
-  // pack the lattice into LDS
-  for (uint32_t w = tid; w < NW; w += NT) {
-    const uint2 b = reinterpret_cast<const uint2*>(B.spins)[w];
-    sp[w] = pack_nibbles(b.x, b.y);
+// Wavefront-uniform copies of a task's parameters.  The descriptors are read
+// from global memory by every lane; readfirstlane tells the compiler the
+// values are the same in all lanes, so they live in scalar registers and the
+// coupling loads below take a scalar base with 32-bit lane offsets.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  return (T*)(((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v));
+}
+
+__device__ __forceinline__ BatchLattice uniform_lattice(const BatchLattice& B) {
+  BatchLattice u;
+  u.spins = uni_ptr(B.spins);
+  u.Jn = uni_ptr(B.Jn);
+  u.L = uni(B.L);
+  u.d = uni(B.d);
+  u.replica = uni(B.replica);
+  u.t = uni(B.t);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    u.keys.k0[i] = uni(B.keys.k0[i]);
+    u.keys.k1[i] = uni(B.keys.k1[i]);
   }
-  if (tid < 8) bound[tid] = Cl.bound[tid];
-  __syncthreads();
-  // thread -> (word column xg, first row); rows advance by RI per iteration
-  const uint32_t RI = NT / LG;                      // rows per iteration (>= 1: L <= 8192)
-  const uint32_t NTa = RI * LG;                     // active threads
-  const bool active = tid < NTa;
-  const uint32_t xg = tid % LG;
-  const uint32_t r_first = tid / LG;
-  const uint32_t dz = RI / L, dy = RI % L;          // row step in (y, z)
-  gu32* Jx = as_global(B.Jn);
-  gu32* Jy = Jx + NW;
-  gu32* Jz = Jx + 2 * NW;
-  const uint32_t wl = xg ? 0u - 1u : LG - 1u;       // offset to the word on the left
-  const uint32_t wr = (xg + 1 < LG) ? 1u : 0u - (LG - 1u);
+  return u;
+}
+
+__device__ __forceinline__ BatchCall uniform_call(const BatchCall& C) {
+  BatchCall u;
+  u.n = uni(C.n);
+  u.every = uni(C.every);
+  u.never4 = uni(C.never4);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) u.bound[i] = uni(C.bound[i]);
+  u.E = uni_ptr(C.E);
+  u.M = uni_ptr(C.M);
+  return u;
+}
+
+// Per-thread geometry of a task: thread -> (word column xg, first row); rows
+// advance by RI = NT / LG per iteration.
+struct BatchGeo {
+  uint32_t L, LG, R, NW, PS, RI, xg, r_first, dy, dz, wl, wr, ym_wrap, zm_wrap;
+};
+
+// One colour phase over the thread's rows.  YFIX: RI is a multiple of L, so
+// every row the thread visits has the same y: its y-neighbour offsets are
+// fixed, and the parity of the active sites steps by dz per row.
+template <int D, bool EA, bool NEVER, bool YFIX>
+__device__ __forceinline__ void batch_colour(uint32_t* sp, const uint32_t* bound, __amdgpu_buffer_rsrc_t rj,
+                                             const BatchGeo& g, const PhiloxUniform& U, const RoundKeys& K,
+                                             uint32_t colour, uint32_t nev) {
+  const uint32_t L = g.L, LG = g.LG, PS = g.PS, NW = g.NW;
+  uint32_t y = g.r_first % L, z = g.r_first / L;
+  const uint32_t ymo = y ? 0u - LG : g.ym_wrap;               // used when YFIX
+  const uint32_t ypo = (y + 1 < L) ? LG : 0u - g.ym_wrap;
+  uint32_t p = (colour + y + z) & 1u;
+  const uint32_t pstep = g.dz & 1u;
+  const uint32_t wstep = g.RI * LG;
+  uint32_t w = g.r_first * LG + g.xg;
+  for (uint32_t row = g.r_first; row < g.R; row += g.RI, w += wstep) {
+    const uint32_t c = sp[w];
+    const uint32_t lw = sp[w + g.wl], rw = sp[w + g.wr];
+    const uint32_t wym = w + (YFIX ? ymo : (y ? 0u - LG : g.ym_wrap));
+    const uint32_t wyp = w + (YFIX ? ypo : ((y + 1 < L) ? LG : 0u - g.ym_wrap));
+    uint32_t nb[2 * D - 2];
+    uint32_t jn[2 * D];
+    nb[0] = sp[wym];
+    nb[1] = sp[wyp];
+    uint32_t wzm = 0;
+    if (D == 3) {
+      wzm = w + (z ? 0u - PS : g.zm_wrap);
+      const uint32_t wzp = w + ((z + 1 < L) ? PS : 0u - g.zm_wrap);
+      nb[2] = sp[wzm];
+      nb[3] = sp[wzp];
+    }
+    if (EA) {
+      const uint32_t jx = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * w, 0, 0);
+      const uint32_t jxl = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * (w + g.wl), 0, 0);
+      jn[0] = __builtin_amdgcn_alignbit(jx, jxl, 28);  // bond (x-1, x)
+      jn[1] = jx;                                      // bond (x, x+1)
+      jn[2] = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * wym, 4u * NW, 0);
+      jn[3] = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * w, 4u * NW, 0);
+      if (D == 3) {
+        jn[4] = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * wzm, 8u * NW, 0);
+        jn[5] = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * w, 8u * NW, 0);
+      }
+    }
+    const uint32_t S = nib_unsat<D, EA>(c, lw, rw, nb, jn);
+    uint32_t rnd[4];
+    philox_lane(w, U, K, rnd);
+    sp[w] = c ^ nib_flips<NEVER>(S, p, rnd, bound, nev);
+    if (YFIX) {
+      z += g.dz;
+      p ^= pstep;
+    } else {
+      y += g.dy;
+      z += g.dz;
+      if (y >= L) {
+        y -= L;
+        z += 1;
+      }
+      p = (colour + y + z) & 1u;
+    }
+  }
+}
+
+// n sweeps of lattice B (uniform parameters) in LDS, NEVER: the table has
+// classes with T == 0.
+template <int D, bool EA, int NT, bool NEVER>
+__device__ __forceinline__ void batch_sweeps(const BatchLattice& B, const BatchCall& Cl, uint32_t* sp,
+                                             const uint32_t* bound, int64_t* red) {
+  BatchGeo g;
+  g.L = B.L;
+  g.LG = g.L / 8;                                  // words per row
+  g.R = (D == 3) ? g.L * g.L : g.L;                // rows
+  g.NW = g.R * g.LG;                               // words
+  g.PS = g.L * g.LG;                               // words per plane (3D)
+  const uint32_t tid = threadIdx.x;
+  g.RI = NT / g.LG;                                // rows per iteration (>= 1: L <= 8192)
+  const bool active = tid < g.RI * g.LG;           // active threads
+  g.xg = tid % g.LG;
+  g.r_first = tid / g.LG;
+  g.dz = g.RI / g.L;                               // row step in (y, z)
+  g.dy = g.RI % g.L;
+  g.wl = g.xg ? 0u - 1u : g.LG - 1u;               // offset to the word on the left
+  g.wr = (g.xg + 1 < g.LG) ? 1u : 0u - (g.LG - 1u);
+  g.ym_wrap = (g.L - 1) * g.LG;
+  g.zm_wrap = (g.L - 1) * g.PS;
+  const bool yfix = g.dy == 0;
+  // couplings by buffer loads: one descriptor over the d arrays of NW words, byte offsets per lane
+  const __amdgpu_buffer_rsrc_t rj =
+      __builtin_amdgcn_make_buffer_rsrc((void*)B.Jn, 0, (int)(4u * D * g.NW), 0x00020000);
+  const uint32_t nev = NEVER ? Cl.never4 : 0u;
   uint32_t rec = 0;
   for (uint32_t i = 0; i < Cl.n; ++i) {
     const uint32_t t = B.t + i;
@@ -139,48 +244,10 @@ __device__ void batch_task(const BatchLattice& B, const BatchCall& Cl, uint32_t*
     for (uint32_t colour = 0; colour < 2; ++colour) {
       const PhiloxUniform U = philox_uniform(t, B.replica, colour, B.keys);
       if (active) {
-        uint32_t y = r_first % L, z = r_first / L;
-        for (uint32_t row = r_first; row < R; row += RI) {
-          const uint32_t w = row * LG + xg;
-          const uint32_t c = sp[w];
-          const uint32_t lw = sp[w + wl], rw = sp[w + wr];
-          const uint32_t wym = y ? w - LG : w + (L - 1) * LG;
-          const uint32_t wyp = (y + 1 < L) ? w + LG : w - (L - 1) * LG;
-          uint32_t nb[2 * D - 2];
-          uint32_t jn[2 * D];
-          nb[0] = sp[wym];
-          nb[1] = sp[wyp];
-          uint32_t wzm = 0;
-          if (D == 3) {
-            wzm = z ? w - PS : w + (L - 1) * PS;
-            const uint32_t wzp = (z + 1 < L) ? w + PS : w - (L - 1) * PS;
-            nb[2] = sp[wzm];
-            nb[3] = sp[wzp];
-          }
-          if (EA) {
-            jn[0] = __builtin_amdgcn_alignbit(Jx[w], Jx[w + wl], 28);  // bond (x-1, x)
-            jn[1] = Jx[w];                                              // bond (x, x+1)
-            jn[2] = Jy[wym];
-            jn[3] = Jy[w];
-            if (D == 3) {
-              jn[4] = Jz[wzm];
-              jn[5] = Jz[w];
-            }
-          }
-          const uint32_t S = nib_unsat<D, EA>(c, lw, rw, nb, jn);
-          uint32_t rnd[4];
-          philox_lane(w, U, B.keys, rnd);
-          const uint32_t p = (colour + y + z) & 1u;
-          const uint32_t f = Cl.never4 ? nib_flips<true>(S, p, rnd, bound, Cl.never4)
-                                       : nib_flips<false>(S, p, rnd, bound, 0);
-          sp[w] = c ^ f;
-          y += dy;
-          z += dz;
-          if (y >= L) {
-            y -= L;
-            z += 1;
-          }
-        }
+        if (yfix)
+          batch_colour<D, EA, NEVER, true>(sp, bound, rj, g, U, B.keys, colour, nev);
+        else
+          batch_colour<D, EA, NEVER, false>(sp, bound, rj, g, U, B.keys, colour, nev);
       }
       __syncthreads();
     }
@@ -189,6 +256,30 @@ __device__ void batch_task(const BatchLattice& B, const BatchCall& Cl, uint32_t*
       ++rec;
     }
   }
+}
+
+// One task: lattice B, sweeps B.t .. B.t+n-1, all in LDS.  n == 0 with
+// every > 0 records the current state once.
+template <int D, bool EA, int NT>
+__device__ void batch_task(const BatchLattice& Bg, const BatchCall& Cg, uint32_t* sp, uint32_t* bound,
+                           int64_t* red) {
+  const BatchLattice B = uniform_lattice(Bg);
+  const BatchCall Cl = uniform_call(Cg);
+  const uint32_t L = B.L;
+  const uint32_t R = (D == 3) ? L * L : L;
+  const uint32_t NW = R * (L / 8);
+  const uint32_t tid = threadIdx.x;
+  // pack the lattice into LDS
+  for (uint32_t w = tid; w < NW; w += NT) {
+    const uint2 b = reinterpret_cast<const uint2*>(B.spins)[w];
+    sp[w] = pack_nibbles(b.x, b.y);
+  }
+  if (tid < 8) bound[tid] = Cl.bound[tid];
+  __syncthreads();
+  if (Cl.never4)
+    batch_sweeps<D, EA, NT, true>(B, Cl, sp, bound, red);
+  else
+    batch_sweeps<D, EA, NT, false>(B, Cl, sp, bound, red);
   if (Cl.n == 0 && Cl.every) batch_record<D, EA, NT>(B, Cl, sp, red, 0);
   for (uint32_t w = tid; w < NW; w += NT) {
     uint2 b;
@@ -205,14 +296,23 @@ __global__ __launch_bounds__(NT) void k_batch(BatchLattice* lats, const BatchCal
   __shared__ uint32_t task;
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* sp = lds;
-  // Termination: the queue fetch (thread 0's atomic), both barriers, the
-  // readfirstlane of the task index and the exit test sit at this one loop
-  // level and nothing before the exit test branches on per-lane data, so
-  // every wave reads the same k and leaves on the same iteration.  Moving the
-  // fetch or a barrier into a nested loop or a lane-dependent branch breaks
-  // that: a wave can then re-read a stale index and never reach k >= ntasks.
+  // Termination: the queue fetch, both barriers, the readfirstlane of the
+  // task index and the exit test sit at this one loop level, and no branch
+  // at this level depends on per-lane data: the fetch and the counter store
+  // are made by all of wave 0 (a wave-uniform condition; lane 0 adds 1, the
+  // other lanes 0, and every lane stores lane 0's result), the task body ends
+  // with a barrier.  So every wave reads the same k and leaves on the same
+  // iteration.  A lane-dependent branch here (thread 0 alone fetching) let
+  // the compiler move the fetch into an outer loop and the barriers into a
+  // nested one whose exit is per lane, so that lanes re-read a stale index
+  // and the loop never ended.
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
   for (;;) {
-    if (threadIdx.x == 0) task = atomicAdd(next, 1u);
+    if (wave == 0) {
+      const uint32_t got = atomicAdd(next, lane == 0 ? 1u : 0u);
+      task = __builtin_amdgcn_readlane(got, 0);
+    }
     __syncthreads();
     const uint32_t k = __builtin_amdgcn_readfirstlane(task);  // uniform: scalar loads below
     __syncthreads();
@@ -221,7 +321,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchLattice* lats, const BatchCal
     const BatchCall Cl = calls[li];
     const BatchLattice B = lats[li];
     batch_task<D, EA, NT>(B, Cl, sp, bound, red);
-    if (threadIdx.x == 0) lats[li].t = B.t + Cl.n;
+    if (wave == 0) lats[li].t = __builtin_amdgcn_readfirstlane(B.t + Cl.n);
+    __syncthreads();
   }
 }
 
