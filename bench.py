@@ -45,6 +45,10 @@ BYTES_PER_ATTEMPT = 2.0  # int8 spin read once and written once per sweep (Ising
 # 8 + 72 + 64 = 144 B, per 8 attempts.
 LDS_PEAK_GBS = 256 * 128 * 2.4
 LDS_BYTES_PER_ATTEMPT = {2: 112 / 8.0, 3: 144 / 8.0}
+# The 3D register-column kernel (L = 512) keeps z columns and the wave's own rows in registers: per
+# 8-site group and sweep it stores the loaded row and the colour-0 result (16 B), reads one 8-byte
+# y neighbour per colour unit (16 B) and four bounds per unit (32 B): 64 B per 8 attempts.
+LDS_BYTES_PER_ATTEMPT_3R = 64 / 8.0
 
 
 def parse():
@@ -59,10 +63,13 @@ def parse():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D Ising L=512 leg")
     ap.add_argument("--c3-steps", type=int, default=100, help="steps of 10 sweeps of the 3D leg (100: whole job)")
     ap.add_argument("--no-large", action="store_true", help="skip the 2D L=16384 sensitivity row")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 2D Ising L=64 leg")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the probe kernels")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D EA workload")
+    ap.add_argument("--batched-static-only", action="store_true",
+                    help="batched workload: one call with the static launch rule only (no autotuner, no graph)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--no-coarse", action="store_true", help="skip the coarse-tile multi-hit schedule")
@@ -83,6 +90,7 @@ def parse():
 KERNEL_SOURCES = {
     "k_stream2d": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
+    "k_stream3r": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_msc_stream": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),
@@ -204,7 +212,7 @@ def cpu_aggregate(workloads, kind, procs, seconds=5.0, oracle_rate=0.015):
                                           kind == "ea3d_batch" else "the trace's first jobs, sweeps capped", span)}
 
 
-def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
+def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100, static_only=False):
     """Batched 3D +-J EA workload: 512 realisations (L in 16..64) x 16 betas = 8192 lattices, all
     advanced `sweeps` sweeps by one pool call, (E, M) every `every` sweeps.  Plain: the same
     lattices on lone handles one after another; its time is the sum over lattices of L^3 * sweeps
@@ -238,6 +246,10 @@ def bench_batched(torch, spin, workloads, sweeps, every=100, plain_sweeps=100):
         return wall, ev0.elapsed_time(ev1), h
 
     wall_static, ms_static, h_static = one_call("static plan")
+    if static_only:
+        return {"workload": "ea3d_batch", "lattices": len(descs), "sweeps": sweeps, "record_every": every,
+                "attempts": attempts, "static_plan_attempts_per_ns": round(attempts / (wall_static * 1e9), 2),
+                "static_plan_gpu_ms": round(ms_static, 2)}
     # the project's autotuner picks each lattice shape's launch plan by timing (outside the timed region)
     b = spin.Batch(descs, stream=stream)
     t0 = time.perf_counter()
@@ -559,11 +571,14 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
     L, d, every = cfg["L"], cfg["d"], cfg["every"]
     N = L ** d
     sweeps_per_step = 10  # one record interval of the L=8192 / L=512 workloads
-    stream = torch.cuda.Stream()
+    # one stream per lattice: the lattices are independent chains, so one lattice's sweep can start on
+    # CUs that another's sweep has already left
+    streams = [torch.cuda.Stream() for _ in cfg["betas"]]
+    stream = streams[0]
     torch.cuda.synchronize()
     lats = []
-    for b in cfg["betas"]:
-        lat = spin.Lattice(cfg["model"], L, d, cfg["seed"], stream=stream)
+    for b, st in zip(cfg["betas"], streams):
+        lat = spin.Lattice(cfg["model"], L, d, cfg["seed"], stream=st)
         if kern:
             lat.set_kernel(kern, *tile)
         lats.append((lat, b))
@@ -572,7 +587,8 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
     nrec = steps * recs_per_step
     Erec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
     Mrec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
-    stream.wait_stream(torch.cuda.current_stream())
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
     for lat, _ in lats:
         lat.synchronize()
 
@@ -594,10 +610,11 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
     # sweep-only segment (measurement excluded): the same kernel, HIP events on its stream
     ev_a = torch.cuda.Event(enable_timing=True)
     ev_b = torch.cuda.Event(enable_timing=True)
-    lat0, b0 = lats[1] if len(lats) > 1 else lats[0]
-    ev_a.record(stream)
+    k0 = 1 if len(lats) > 1 else 0
+    lat0, b0 = lats[k0]
+    ev_a.record(streams[k0])
     lat0.sweep(so_sweeps, b0)
-    ev_b.record(stream)
+    ev_b.record(streams[k0])
     torch.cuda.synchronize()
     so_ms = ev_a.elapsed_time(ev_b)
     for lat, _ in lats:
@@ -621,8 +638,8 @@ def roofline_of(kname, L, d, N, so_sweeps, so_ms):
     alg_ops = ALG_OPS_PER_ATTEMPT[d]
     alu_tops = alg_ops * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e12
     hbm_gbs = BYTES_PER_ATTEMPT * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
-    kernel_tag = {("fused", 2): "k_stream2d", ("fused", 3): "k_stream3d", ("tiled", 3): "k_tiled3d"}.get(
-        (kname, d), kname)
+    kernel_tag = {("fused", 2): "k_stream2d", ("fused", 3): "k_stream3r" if L == 512 else "k_stream3d",
+                  ("tiled", 3): "k_tiled3d"}.get((kname, d), kname)
     traffic = profiled_traffic(kernel_tag, L)
     roof = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s", "frac": round(alu_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
@@ -632,12 +649,46 @@ def roofline_of(kname, L, d, N, so_sweeps, so_ms):
                     "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                     "alg_bytes_per_launch": int(BYTES_PER_ATTEMPT * attempts_per_launch)}}
     if kname == "fused":  # the streaming kernels
-        lds_gbs = LDS_BYTES_PER_ATTEMPT[d] * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
+        lb = LDS_BYTES_PER_ATTEMPT_3R if kernel_tag == "k_stream3r" else LDS_BYTES_PER_ATTEMPT[d]
+        lds_gbs = lb * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
         roof["lds"] = {"achieved": round(lds_gbs, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
                        "frac": round(lds_gbs / LDS_PEAK_GBS, 4),
-                       "alg_bytes_per_launch": int(LDS_BYTES_PER_ATTEMPT[d] * attempts_per_launch)}
+                       "alg_bytes_per_launch": int(lb * attempts_per_launch)}
     return {"sweep_only_attempts_per_ns": round(sweep_only_rate, 2),
             "hbm_frac_sweep_only": round(hbm_gbs / HBM_PEAK_GBS, 4), "roofline": roof}
+
+
+def bench_c1(torch, spin, workloads):
+    """The 2D Ising L = 64 job (1000 sweeps at beta 0.4406868, E and M after every sweep): one call of
+    1000 sweeps with the 1000 records, and the same as 100 calls of 10 sweeps.  The lattice (4 KiB)
+    sits in one workgroup's LDS for a whole call, so the rate is one CU's, bound by latency: no
+    chip-wide roofline applies."""
+    cfg = workloads.CONFIGS["ising2d_L64"]
+    L, beta, n = cfg["L"], cfg["betas"][0], cfg["sweeps"]
+    stream = torch.cuda.Stream()
+    E = torch.zeros(n, dtype=torch.int64, device="cuda")
+    M = torch.zeros(n, dtype=torch.int64, device="cuda")
+    res = {"workload": "ising2d_L64", "sweeps": n, "record_every": 1, "beta": beta}
+    warm = spin.Lattice(0, L, 2, cfg["seed"], stream=stream)
+    warm.sweep_record_device(10, beta, 1, E, M)   # module load and first launch outside the timing
+    warm.synchronize()
+    warm.close()
+    for tag, calls in (("one_call", 1), ("calls_of_10", n // 10)):
+        lat = spin.Lattice(0, L, 2, cfg["seed"], stream=stream)
+        lat.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        per = n // calls
+        a.record(stream)
+        for c in range(calls):
+            lat.sweep_record_device(per, beta, 1, E[c * per:], M[c * per:])
+        b.record(stream)
+        lat.synchronize()
+        ms = a.elapsed_time(b)
+        res[tag] = {"kernel": spin.KERNEL_NAMES[lat.kernel], "us_per_sweep": round(ms * 1e3 / n, 3),
+                    "attempts_per_ns": round(n * L * L / (ms * 1e6), 3)}
+        lat.close()
+    res["note"] = "latency-bound: the lattice lives in one CU's LDS for the whole call"
+    return res
 
 
 def bench_large2d(torch, spin, workloads, L=16384, sweeps=100):
@@ -763,13 +814,17 @@ def main():
         # the 3D workload as its own leg: the whole 1000-sweep job (100 steps of 10 sweeps, E/M every 10)
         out["ising3d_L512"] = lattice_job(torch, spin, workloads, "ising3d_L512", args.c3_steps, 2)
         print("ising3d_L512:", json.dumps(out["ising3d_L512"]), file=sys.stderr, flush=True)
+    if not args.no_c1 and args.workload != "ising2d_L64":
+        out["ising2d_L64"] = bench_c1(torch, spin, workloads)
+        print("ising2d_L64:", json.dumps(out["ising2d_L64"]), file=sys.stderr, flush=True)
     if not args.no_large:
         out["large2d_L16384"] = bench_large2d(torch, spin, workloads)
     if not args.no_ceilings:
         out["ceilings"] = bench_ceilings(torch, spin)
         print("ceilings:", json.dumps(out["ceilings"]), file=sys.stderr, flush=True)
     if not args.no_batched:
-        out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps)
+        out["batched"] = bench_batched(torch, spin, workloads, args.batched_sweeps,
+                                       static_only=args.batched_static_only)
         print("batched:", json.dumps(out["batched"]), file=sys.stderr, flush=True)
     if not args.no_coarse:
         if args.coarse_only:

@@ -54,9 +54,16 @@ __global__ __launch_bounds__(NT) void k_coarse(int8_t* __restrict__ spins, const
   __shared__ uint32_t jl[EA ? D * NWL : 1];
   const uint32_t L = a.L, GPR = L / 8;
   const uint32_t NW = (D == 3) ? L * L * GPR : L * GPR;  // words of one direction of couplings
+  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each XCD takes a
+  // contiguous run of tiles in (x, y, z) order: neighbouring tiles share the 128-byte lines of their
+  // rows and their boundary rows, and then they share one L2.
+  const uint32_t nbx = gridDim.x, nby = gridDim.y, nblk = gridDim.x * gridDim.y * gridDim.z;
+  uint32_t blk = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+  if ((nblk & 7u) == 0) blk = (blk & 7u) * (nblk >> 3) + (blk >> 3);
+  const uint32_t bxh = blk % nbx, byz = blk / nbx;
   // tile coordinates: the launch covers the tiles with bx + by (+ bz) = q (mod 2)
-  const uint32_t by = blockIdx.y, bz = (D == 3) ? blockIdx.z : 0u;
-  const uint32_t bx = 2u * blockIdx.x + ((by + bz + a.q) & 1u);
+  const uint32_t by = byz % nby, bz = (D == 3) ? byz / nby : 0u;
+  const uint32_t bx = 2u * bxh + ((by + bz + a.q) & 1u);
   const uint32_t x0w = bx * TW, y0 = by * T, z0 = bz * T;  // first word column, row, plane
   if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
   gu32* Jn = as_global(Jraw);
