@@ -94,6 +94,7 @@ KERNEL_SOURCES = {
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_batch": ("spin_batch_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_msc_stream": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),
+    "k_msc_col": ("spin_msc_kernels.hip", "spin_msc.h", "spin_device.h"),
     "k_coarse": ("spin_coarse_kernels.hip", "spin_nibble.h", "spin_device.h"),
     "k_heis_phase": ("spin_heis_kernels.hip", "spin_heis.h", "spin_device.h"),
 }
@@ -479,12 +480,13 @@ def bench_msc(torch, spin, workloads, shapes=((512, 3), (256, 3), (128, 3), (409
         ms = a.elapsed_time(b)
         # fewest HBM bytes a sweep can move: read and write each site word, read the d coupling words
         hbm_min = N * (8 + 4 * d)
-        rec = {"attempts_per_ns": round(32 * N * n / (ms * 1e6), 1),
+        kname = {0: "k_msc_phase", 1: "k_msc_stream", 2: "k_msc_col"}.get(m.kernel, "?")
+        rec = {"kernel": kname, "attempts_per_ns": round(32 * N * n / (ms * 1e6), 1),
                "ps_per_attempt": round(ms * 1e9 / (32 * N * n), 4), "sweeps": n,
                "ms_per_sweep": round(ms / n, 4),
                "min_hbm_GBps": round(hbm_min * n / (ms * 1e6), 1),
                "min_hbm_frac": round(hbm_min * n / (ms * 1e-3) / 8e12, 4)}
-        traffic = profiled_traffic("k_msc_stream", L) if d == 3 else None
+        traffic = profiled_traffic(kname, L) if d == 3 else None
         if traffic is not None:   # HBM bytes per sweep counted by rocprofv3 for this kernel and L
             rec["traffic_bytes_per_sweep"] = traffic
             rec["traffic_GBps"] = round(traffic * n / (ms * 1e6), 1)

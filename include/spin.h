@@ -470,15 +470,24 @@ int spin_msc_get_spins(const spin_msc* h, int system, int8_t* out, size_t n);
 /* Absolute index of the next sweep. */
 uint64_t spin_msc_sweeps_done(const spin_msc* h);
 
-/* Kernel choice (bits never change): streaming != 0 sweeps both colours in
+/* Kernel choice (bits never change): streaming == 1 sweeps both colours in
  * one launch streamed over planes, with rows (3D: rows per workgroup,
  * dividing L, <= 32), planes (per strip), threads (256 or 512) and width
  * (sites of a row per workgroup: a multiple of 8 dividing L), 0 meaning the
- * default (8, 16, 512, L); streaming == 0 launches one kernel per colour.
+ * default (8, 16, 512, L); streaming == 2 (3D, L = 512 only) is the
+ * register-column kernel, which reads every coupling word once per sweep:
+ * rows 4 or 8 (default 8), planes even and dividing L (default 32), threads
+ * 0 or 64 * (rows + 2), width 0 or L; streaming == 0 launches one kernel per
+ * colour.
  * At creation the library picks a streaming shape measured to be fast for
  * L and d where one fits, else the per-colour kernel.  SPIN_EINVAL if the
  * streaming shape does not fit L. */
 int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int threads, int width);
+
+/* The kernel the next sweep uses: 0 (one launch per colour), 1 (streamed
+ * over planes) or 2 (register columns), as spin_msc_set_kernel's streaming;
+ * -1 for a NULL handle. */
+int spin_msc_kernel(const spin_msc* h);
 
 /* Wait for the handle's queued work. */
 int spin_msc_synchronize(spin_msc* h);

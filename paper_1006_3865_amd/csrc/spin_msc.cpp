@@ -34,6 +34,7 @@ struct spin_msc {
   uint32_t* S;       // [N] current spins
   uint32_t* S2;      // [N] second buffer of the streaming kernel (allocated on first use)
   uint32_t TY, H, NT, XW;  // streaming shape; NT == 0: the per-colour phase kernel
+  bool col;          // the register-column kernel (3D L = 512; shape TY, H)
   uint32_t* J;       // [d][N] (measurement)
   uint32_t* J6;      // [N/8][2][4][2d]: bonds of the active sites of each group and colour (phase kernel, on first use)
   int64_t* part;     // measurement partial counts
@@ -79,8 +80,9 @@ static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int6
   if (std::isnan(beta) || beta < 0) return mfail(SPIN_EINVAL, "beta must be >= 0 or +inf (got %g)", beta);
   if (h->t + (uint64_t)n > ((uint64_t)1 << 32)) return mfail(SPIN_EINVAL, "sweep index would exceed 2^32");
   MscArgs a = msc_args(h, beta);
-  if (h->NT && !h->S2 && n > 0 && !dalloc(&h->S2, h->N * 4)) return mfail(SPIN_ENOMEM, "second spin buffer");
-  if (!h->NT && !h->J6 && n > 0) {
+  const bool streamed = h->NT || h->col;
+  if (streamed && !h->S2 && n > 0 && !dalloc(&h->S2, h->N * 4)) return mfail(SPIN_ENOMEM, "second spin buffer");
+  if (!streamed && !h->J6 && n > 0) {
     if (!dalloc(&h->J6, (size_t)2 * h->d * h->N * 4)) return mfail(SPIN_ENOMEM, "coupling copy");
     hipError_t e = launch_msc_bonds(h->J, h->J6, (uint32_t)h->L, (uint32_t)h->d, h->N, h->stream);
     if (e != hipSuccess) return mfail(SPIN_EDEVICE, "coupling copy: %s", hipGetErrorString(e));
@@ -88,7 +90,11 @@ static int msc_run(spin_msc* h, int n, double beta, int every, int64_t* dE, int6
   uint32_t rec = 0;
   for (int i = 0; i < n; ++i) {
     a.t = (uint32_t)(h->t + (uint64_t)i);
-    if (h->NT) {
+    if (h->col) {
+      hipError_t e = launch_msc_col(h->S, h->S2, h->J, a, (uint32_t)h->d, h->TY, h->H, h->stream);
+      if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin column launch: %s", hipGetErrorString(e));
+      std::swap(h->S, h->S2);
+    } else if (h->NT) {
       hipError_t e = launch_msc_stream(h->S, h->S2, h->J, a, (uint32_t)h->d, h->TY, h->H, h->NT, h->XW, h->stream);
       if (e != hipSuccess) return mfail(SPIN_EDEVICE, "multi-spin stream launch: %s", hipGetErrorString(e));
       std::swap(h->S, h->S2);
@@ -160,6 +166,7 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
   }
   (void)hipGetLastError();
   h->NT = 0;
+  h->col = false;
   h->TY = d == 3 ? 8u : 1u;
   h->H = 16;
   h->XW = (uint32_t)L;
@@ -174,6 +181,14 @@ spin_msc* spin_msc_create(int L, int d, uint64_t coupling_seed, uint32_t realisa
         h->H = H;
         h->NT = nt;
       }
+    }
+    // 3D L = 512: the register-column kernel, slabs of 4 rows and strips of L/2 planes (one workgroup
+    // per compute unit; measured 1.6x the plane-streaming kernel's rate at this size)
+    if (msc_col_supported((uint32_t)L, 3, 4, (uint32_t)L / 2)) {
+      h->col = true;
+      h->NT = 0;
+      h->TY = 4;
+      h->H = (uint32_t)L / 2;
     }
   } else {
     while (h->XW > 2048 && (h->XW / 2) % 8 == 0) h->XW /= 2;
@@ -255,9 +270,24 @@ int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int th
   if (!h) return mfail(SPIN_EINVAL, "NULL handle");
   if (!streaming) {
     h->NT = 0;
+    h->col = false;
     return SPIN_OK;
   }
   if (rows < 0 || planes < 0 || threads < 0 || width < 0) return mfail(SPIN_EINVAL, "negative streaming shape");
+  if (streaming == 2) {
+    const uint32_t TY = (uint32_t)(rows ? rows : 8), H = (uint32_t)(planes ? planes : 32);
+    if (!msc_col_supported((uint32_t)h->L, (uint32_t)h->d, TY, H) || (threads && (uint32_t)threads != 64 * (TY + 2)) ||
+        (width && width != h->L))
+      return mfail(SPIN_EINVAL, "register-column shape rows=%d planes=%d threads=%d width=%d cannot run L=%d d=%d",
+                   rows, planes, threads, width, h->L, h->d);
+    h->col = true;
+    h->NT = 0;
+    h->TY = TY;
+    h->H = H;
+    h->XW = (uint32_t)h->L;
+    return SPIN_OK;
+  }
+  if (streaming != 1) return mfail(SPIN_EINVAL, "streaming must be 0, 1 or 2 (got %d)", streaming);
   const uint32_t TY = h->d == 3 ? (uint32_t)(rows ? rows : 8) : 1u, H = (uint32_t)(planes ? planes : 16),
                  NT = (uint32_t)(threads ? threads : 512), XW = (uint32_t)(width ? width : h->L);
   if (!msc_stream_supported((uint32_t)h->L, (uint32_t)h->d, TY, H, NT, XW))
@@ -267,7 +297,13 @@ int spin_msc_set_kernel(spin_msc* h, int streaming, int rows, int planes, int th
   h->H = H;
   h->NT = NT;
   h->XW = XW;
+  h->col = false;
   return SPIN_OK;
+}
+
+int spin_msc_kernel(const spin_msc* h) {
+  if (!h) return -1;
+  return h->col ? 2 : (h->NT ? 1 : 0);
 }
 
 int spin_msc_synchronize(spin_msc* h) {

@@ -499,6 +499,368 @@ hipError_t launch_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t*
                    : go_msc_stream<2, 512>(src, dst, J, a, TY, H, XW, stream);
 }
 
+// ------------------------------------------------------------ register columns
+// 3D, L = 512: one whole sweep per launch with each row's z column in
+// registers, and every coupling word read from HBM once per sweep (the plane
+// streaming kernel above reads the couplings of a site once per colour).
+//
+// A workgroup owns the TY rows [y0, y0+TY) of the planes [z0, z0+H) and has
+// TY + 2 waves; wave w keeps slab row r = w + 1 (y = y0 - 2 + r) for the
+// whole launch: rows 2..TY+1 are owned, 1 and TY+2 a ring whose colour 0 is
+// recomputed here (colour 1 of the owned edge rows needs it), and 0 and TY+3
+// a halo that the ring's colour 0 reads.  Lane l holds the group of sites
+// x = 8l .. 8l+7 of its row (a 512-site row is one wavefront).
+// Step i = 0..H+1 with a = z0-1+i, b = a-1.  Both colour units of a step
+// have active sites of x parity P = (y + a) & 1 (colour 0 on plane a,
+// colour 1 on plane b):
+//   write plane a+1's spins as loaded (the parity-P words: colour-1 sites,
+//     which the neighbouring rows' colour 0 reads in step i+1) and y bonds
+//     (all words) into LDS slot N;
+//   issue the loads of plane a+2's spins and y bonds and plane a+1's x and z
+//     bonds (registers; used in step i+1);
+//   colour 0 on plane a: z neighbours plane b after its colour 0 (its
+//     colour-1 words still the old ones) and plane a+1 as loaded, from
+//     registers; y neighbours and y bonds from slot A; x neighbours and the
+//     x bond left of the group by a wavefront rotate; the new parity-P words
+//     go into slot A (the other rows read the other half of it in this step);
+//   colour 1 on plane b (owned rows, i >= 2): z neighbours plane b-1 and
+//     plane a after colour 0 (registers), y neighbours and bonds from slot B
+//     (plane b after colour 0, written in step i-1); the group goes to dst;
+//   barrier.
+// Register lifetimes: an x-bond word serves colour 0 of its plane in one
+// step and colour 1 of the same plane in the next; a z-bond word (bond to the
+// plane above) serves its plane's colour-0 unit and the next plane's
+// colour-1 unit for one parity half, and the next plane's colour-0 and its
+// own plane's colour-1 unit for the other, over three steps.  LDS rows keep
+// the parity split of the y and z bonds in HBM (even-x words, then odd-x
+// words), so the four active words of a group are 16 contiguous bytes.
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+namespace col {
+
+constexpr uint32_t L = 512;
+constexpr uint32_t RW = L;       // words per LDS row
+constexpr uint32_t HW = L / 2;   // words per parity half
+
+struct G8 {  // one group, natural site order: words 0-3 in lo, 4-7 in hi
+  v4u lo, hi;
+};
+struct H8 {  // one group's y or z bonds, split by parity: h[0] even x, h[1] odd x
+  v4u h[2];
+};
+
+template <uint32_t P>
+__device__ __forceinline__ v4u half(const G8& g) {
+  return v4u{g.lo[P], g.lo[2 + P], g.hi[P], g.hi[2 + P]};
+}
+
+__device__ __forceinline__ G8 ld_group(__amdgpu_buffer_rsrc_t r, uint32_t row, uint32_t lane) {
+  G8 g;
+  g.lo = __builtin_amdgcn_raw_buffer_load_b128(r, 32u * lane, row, 0);
+  g.hi = __builtin_amdgcn_raw_buffer_load_b128(r, 32u * lane + 16u, row, 0);
+  return g;
+}
+
+__device__ __forceinline__ H8 ld_split(__amdgpu_buffer_rsrc_t r, uint32_t row, uint32_t lane) {
+  H8 g;
+  g.h[0] = __builtin_amdgcn_raw_buffer_load_b128(r, 16u * lane, row, 0);
+  g.h[1] = __builtin_amdgcn_raw_buffer_load_b128(r, 4u * HW + 16u * lane, row, 0);
+  return g;
+}
+
+__device__ __forceinline__ uint32_t ror1(uint32_t v) {  // lane l gets lane l-1's value (periodic)
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t rol1(uint32_t v) {  // lane l gets lane l+1's value (periodic)
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xF, 0xF, false);
+}
+
+// One colour unit on the active sites j = 2i + P of group g: nb is the x
+// neighbour outside the group (P = 0: word 7 of the group to the left; P = 1:
+// word 0 of the group to the right), jx the group's x bonds and jl the x
+// bond left of the group (P = 0 only); ym, yp, zm, zp the active sites'
+// neighbours and jym, jy, jzm, jz their y and z bonds, word i for site 2i+P;
+// r the shared draws.  Same bit-sliced count and acceptance as msc_update8.
+template <uint32_t P>
+__device__ __forceinline__ void unit(G8& g, uint32_t nb, const G8& jx, uint32_t jl, v4u ym, v4u yp, v4u zm, v4u zp,
+                                     v4u jym, v4u jy, v4u jzm, v4u jz, const uint32_t (&r)[4],
+                                     const uint64_t (&thr)[3]) {
+  uint32_t w[8] = {g.lo.x, g.lo.y, g.lo.z, g.lo.w, g.hi.x, g.hi.y, g.hi.z, g.hi.w};
+  const uint32_t x[8] = {jx.lo.x, jx.lo.y, jx.lo.z, jx.lo.w, jx.hi.x, jx.hi.y, jx.hi.z, jx.hi.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = 2 * i + (int)P;
+    const uint32_t s = w[j];
+    const uint32_t left = j ? w[j - 1] : nb;
+    const uint32_t right = j < 7 ? w[j + 1] : nb;
+    const uint32_t b0 = xor3(s, left, j ? x[j - 1] : jl), b1 = xor3(s, right, x[j]);
+    const uint32_t b2 = xor3(s, ym[i], jym[i]), b3 = xor3(s, yp[i], jy[i]);
+    const uint32_t b4 = xor3(s, zm[i], jzm[i]), b5 = xor3(s, zp[i], jz[i]);
+    const uint32_t s1 = xor3(b0, b1, b2), c1 = maj3(b0, b1, b2);
+    const uint32_t s2 = xor3(b3, b4, b5), c2 = maj3(b3, b4, b5);
+    const uint32_t u0 = s1 ^ s2, t = s1 & s2;
+    const uint32_t u1 = xor3(c1, c2, t), u2 = maj3(c1, c2, t);
+    const uint64_t ri = r[i];
+    const uint32_t us = (ri >= thr[0] ? 1u : 0u) + (ri >= thr[1] ? 1u : 0u) + (ri >= thr[2] ? 1u : 0u);
+    w[j] = s ^ at_least(u0, u1, u2, us);
+  }
+  g.lo = v4u{w[0], w[1], w[2], w[3]};
+  g.hi = v4u{w[4], w[5], w[6], w[7]};
+}
+
+// Roles of the waves: row r, its parity, whether it is owned, and which halo
+// row it loads (TOP: spins of row 0; JH: y bonds of row 0; BOT: spins of row TY+3).
+enum { TOP = 0, JH = 1, BOT = 2, ODD = 3, EVEN = 4 };
+
+template <int ROLE>
+struct Role {
+  static constexpr uint32_t RP = (ROLE == TOP || ROLE == ODD) ? 1u : 0u;
+  static constexpr bool OWN = ROLE != TOP && ROLE != BOT;
+};
+
+struct Ctx {
+  __amdgpu_buffer_rsrc_t src, dst, jx, jy, jz;
+  uint32_t* ls;  // spin slices: 3 x (TY+4) rows
+  uint32_t* lj;  // y-bond slices: 3 x (TY+3) rows
+  const RoundKeys* keys;
+  PhiloxUniform U0, U1;
+  uint64_t thr[3];
+  uint32_t z0, H, lane, r, y, yh;  // yh: the halo row this wave loads (TOP, JH: row 0; BOT: row TY+3)
+};
+
+struct Regs {
+  G8 s2, s1, sa, sb;  // spins: plane a+2 (in flight), a+1 as loaded, a as loaded, b after colour 0
+  v4u sbb;            // plane b-1 after colour 0, this step's active half
+  H8 jy1;             // y bonds of plane a+1 (written to LDS at the start of the step), then of a+2
+  G8 jxn, jxa, jxb;   // x bonds of planes a+1 (in flight), a, b
+  H8 jzn, jza, jzb;   // z bonds of planes a+1 (in flight), a, b
+  v4u jzbb;           // z bonds of plane b-1, this step's active half
+  G8 hs;              // halo spins (TOP, BOT): plane a+1, then a+2
+  H8 hj;              // halo y bonds (JH): plane a+1, then a+2
+  uint32_t sA, sB, sN;  // LDS slots of planes a, b, a+1
+};
+
+__device__ __forceinline__ uint32_t row_off(uint32_t z, uint32_t y) { return (z * L + y) * L * 4u; }
+
+template <int TY, int ROLE, uint32_t Q, bool C1>
+__device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
+  using RL = Role<ROLE>;
+  constexpr uint32_t SS = (TY + 4) * RW, JS = (TY + 3) * RW;  // words per spin / y-bond slice
+  constexpr uint32_t P = (RL::RP + Q + 1u) & 1u;
+  const uint32_t lane = c.lane, r = c.r, y = c.y;
+  const uint32_t a = (c.z0 + i + L - 1u) & (L - 1u);
+  const uint32_t b = (a + L - 1u) & (L - 1u);
+  const uint32_t ic = i <= c.H ? i : c.H;  // loads past the strip's needs reload a plane already read
+  const uint32_t zs = (c.z0 + 1u + ic) & (L - 1u), zx = (c.z0 + ic) & (L - 1u);
+  // plane a+1 into slot N (free since the last barrier: it held plane b-1)
+  {
+    uint32_t* sN = c.ls + R.sN * SS;
+    uint32_t* jN = c.lj + R.sN * JS;
+    *reinterpret_cast<v4u*>(sN + r * RW + P * HW + 4u * lane) = half<P>(R.s1);
+    *reinterpret_cast<v4u*>(jN + r * RW + 4u * lane) = R.jy1.h[0];
+    *reinterpret_cast<v4u*>(jN + r * RW + HW + 4u * lane) = R.jy1.h[1];
+    if (ROLE == TOP) {
+      constexpr uint32_t PH = (0u + Q + 1u) & 1u;
+      *reinterpret_cast<v4u*>(sN + PH * HW + 4u * lane) = half<PH>(R.hs);
+    }
+    if (ROLE == BOT) {
+      constexpr uint32_t PH = ((uint32_t)TY + 3u + Q + 1u) & 1u;
+      *reinterpret_cast<v4u*>(sN + (TY + 3) * RW + PH * HW + 4u * lane) = half<PH>(R.hs);
+    }
+    if (ROLE == JH) {
+      *reinterpret_cast<v4u*>(jN + 4u * lane) = R.hj.h[0];
+      *reinterpret_cast<v4u*>(jN + HW + 4u * lane) = R.hj.h[1];
+    }
+  }
+  // loads for the next step
+  R.s2 = ld_group(c.src, row_off(zs, y), lane);
+  R.jy1 = ld_split(c.jy, row_off(zs, y), lane);
+  R.jxn = ld_group(c.jx, row_off(zx, y), lane);
+  R.jzn = ld_split(c.jz, row_off(zx, y), lane);
+  if (ROLE == TOP || ROLE == BOT) R.hs = ld_group(c.src, row_off(zs, c.yh), lane);
+  if (ROLE == JH) R.hj = ld_split(c.jy, row_off(zs, c.yh), lane);
+  // colour 0 on plane a
+  const uint32_t* sA = c.ls + R.sA * SS;
+  const uint32_t* jA = c.lj + R.sA * JS;
+  const uint32_t o = P * HW + 4u * lane;
+  uint32_t rnd[4];
+  philox_lane((a * L + y) * 64u + lane, c.U0, *c.keys, rnd);
+  G8 na = R.sa;
+  {
+    const v4u ym = *reinterpret_cast<const v4u*>(sA + (r - 1) * RW + o);
+    const v4u yp = *reinterpret_cast<const v4u*>(sA + (r + 1) * RW + o);
+    const v4u jy = *reinterpret_cast<const v4u*>(jA + r * RW + o);
+    const v4u jym = *reinterpret_cast<const v4u*>(jA + (r - 1) * RW + o);
+    const uint32_t nb = P == 0 ? ror1(R.sa.hi.w) : rol1(R.sa.lo.x);
+    const uint32_t jl = P == 0 ? ror1(R.jxa.hi.w) : 0u;
+    unit<P>(na, nb, R.jxa, jl, ym, yp, half<P>(R.sb), half<P>(R.s1), jym, jy, R.jzb.h[P], R.jza.h[P], rnd, c.thr);
+    *reinterpret_cast<v4u*>(c.ls + R.sA * SS + r * RW + o) = half<P>(na);
+  }
+  // colour 1 on plane b
+  if (C1 && RL::OWN) {
+    const uint32_t* sB = c.ls + R.sB * SS;
+    const uint32_t* jB = c.lj + R.sB * JS;
+    philox_lane((b * L + y) * 64u + lane, c.U1, *c.keys, rnd);
+    const v4u ym = *reinterpret_cast<const v4u*>(sB + (r - 1) * RW + o);
+    const v4u yp = *reinterpret_cast<const v4u*>(sB + (r + 1) * RW + o);
+    const v4u jy = *reinterpret_cast<const v4u*>(jB + r * RW + o);
+    const v4u jym = *reinterpret_cast<const v4u*>(jB + (r - 1) * RW + o);
+    const uint32_t nb = P == 0 ? ror1(R.sb.hi.w) : rol1(R.sb.lo.x);
+    const uint32_t jl = P == 0 ? ror1(R.jxb.hi.w) : 0u;
+    G8 nbk = R.sb;
+    unit<P>(nbk, nb, R.jxb, jl, ym, yp, R.sbb, half<P>(na), jym, jy, R.jzbb, R.jzb.h[P], rnd, c.thr);
+    __builtin_amdgcn_raw_buffer_store_b128(nbk.lo, c.dst, 32u * lane, row_off(b, y), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(nbk.hi, c.dst, 32u * lane + 16u, row_off(b, y), 0);
+  }
+  // the next step's registers (its active half is 1 - P)
+  R.sbb = half<P ^ 1u>(R.sb);
+  R.sb = na;
+  R.sa = R.s1;
+  R.s1 = R.s2;
+  R.jxb = R.jxa;
+  R.jxa = R.jxn;
+  R.jzbb = R.jzb.h[P ^ 1u];
+  R.jzb = R.jza;
+  R.jza = R.jzn;
+  const uint32_t t = R.sB;
+  R.sB = R.sA;
+  R.sA = R.sN;
+  R.sN = t;
+  __syncthreads();
+}
+
+template <int TY, int ROLE>
+__device__ __forceinline__ void run(const Ctx& c) {
+  using RL = Role<ROLE>;
+  constexpr uint32_t SS = (TY + 4) * RW, JS = (TY + 3) * RW;
+  const uint32_t lane = c.lane, r = c.r, y = c.y;
+  const uint32_t zm2 = (c.z0 + L - 2u) & (L - 1u), zm1 = (c.z0 + L - 1u) & (L - 1u);
+  Regs R;
+  // prologue: plane z0-1 into slot 0 (spins half P(r, step -1) = r & 1, all y bonds); registers for step 0
+  R.sb = ld_group(c.src, row_off(zm2, y), lane);
+  R.sa = ld_group(c.src, row_off(zm1, y), lane);
+  R.s1 = ld_group(c.src, row_off(c.z0, y), lane);
+  R.jxa = ld_group(c.jx, row_off(zm1, y), lane);
+  R.jza = ld_split(c.jz, row_off(zm1, y), lane);
+  R.jzb = ld_split(c.jz, row_off(zm2, y), lane);
+  const H8 jy0 = ld_split(c.jy, row_off(zm1, y), lane);
+  R.jy1 = ld_split(c.jy, row_off(c.z0, y), lane);
+  R.jxb = R.jxa;
+  R.sbb = v4u{0u, 0u, 0u, 0u};
+  R.jzbb = v4u{0u, 0u, 0u, 0u};
+  R.hs.lo = R.hs.hi = v4u{0u, 0u, 0u, 0u};
+  R.hj.h[0] = R.hj.h[1] = v4u{0u, 0u, 0u, 0u};
+  if (RL::RP)
+    *reinterpret_cast<v4u*>(c.ls + r * RW + HW + 4u * lane) = half<1>(R.sa);
+  else
+    *reinterpret_cast<v4u*>(c.ls + r * RW + 4u * lane) = half<0>(R.sa);
+  *reinterpret_cast<v4u*>(c.lj + r * RW + 4u * lane) = jy0.h[0];
+  *reinterpret_cast<v4u*>(c.lj + r * RW + HW + 4u * lane) = jy0.h[1];
+  if (ROLE == TOP) {  // row 0: half 0
+    const G8 h = ld_group(c.src, row_off(zm1, c.yh), lane);
+    *reinterpret_cast<v4u*>(c.ls + 4u * lane) = half<0>(h);
+    R.hs = ld_group(c.src, row_off(c.z0, c.yh), lane);
+  }
+  if (ROLE == BOT) {  // row TY+3: half (TY+3) & 1 = 1
+    const G8 h = ld_group(c.src, row_off(zm1, c.yh), lane);
+    *reinterpret_cast<v4u*>(c.ls + (TY + 3) * RW + HW + 4u * lane) = half<1>(h);
+    R.hs = ld_group(c.src, row_off(c.z0, c.yh), lane);
+  }
+  if (ROLE == JH) {
+    const H8 h = ld_split(c.jy, row_off(zm1, c.yh), lane);
+    *reinterpret_cast<v4u*>(c.lj + 4u * lane) = h.h[0];
+    *reinterpret_cast<v4u*>(c.lj + HW + 4u * lane) = h.h[1];
+    R.hj = ld_split(c.jy, row_off(c.z0, c.yh), lane);
+  }
+  (void)SS;
+  (void)JS;
+  R.sA = 0;
+  R.sN = 1;
+  R.sB = 2;
+  __syncthreads();
+  step<TY, ROLE, 0, false>(c, R, 0u);
+  step<TY, ROLE, 1, false>(c, R, 1u);
+  for (uint32_t i0 = 2; i0 < c.H + 2u; i0 += 2) {
+    step<TY, ROLE, 0, true>(c, R, i0);
+    step<TY, ROLE, 1, true>(c, R, i0 + 1u);
+  }
+}
+
+}  // namespace col
+
+template <int TY>
+__global__ __launch_bounds__(64 * (TY + 2)) void k_msc_col(const uint32_t* __restrict__ src,
+                                                           uint32_t* __restrict__ dst,
+                                                           const uint32_t* __restrict__ J, MscArgs a,
+                                                           uint32_t H) {
+  using namespace col;
+  extern __shared__ __align__(16) uint32_t lds[];
+  constexpr uint32_t Nw = L * L * L;
+  Ctx c;
+  c.src = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(Nw * 4u), 0x00020000);
+  c.dst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(Nw * 4u), 0x00020000);
+  c.jx = __builtin_amdgcn_make_buffer_rsrc((void*)J, 0, (int)(Nw * 4u), 0x00020000);
+  c.jy = __builtin_amdgcn_make_buffer_rsrc((void*)(J + Nw), 0, (int)(Nw * 4u), 0x00020000);
+  c.jz = __builtin_amdgcn_make_buffer_rsrc((void*)(J + 2u * (size_t)Nw), 0, (int)(Nw * 4u), 0x00020000);
+  c.ls = lds;
+  c.lj = lds + 3u * (TY + 4) * RW;
+  c.keys = &a.keys;
+  c.U0 = philox_uniform(a.t, a.p0, 4u, a.keys);
+  c.U1 = philox_uniform(a.t, a.p0, 5u, a.keys);
+  c.thr[0] = a.thr[0];
+  c.thr[1] = a.thr[1];
+  c.thr[2] = a.thr[2];
+  // workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles (the slabs of
+  // one strip side by side), so that the halo rows of neighbouring slabs are read through the same L2
+  const uint32_t nslab = L / TY, nblk = gridDim.x, bk = blockIdx.x;
+  const uint32_t tile = (nblk % 8u == 0u) ? (bk % 8u) * (nblk / 8u) + bk / 8u : bk;
+  const uint32_t y0 = (tile % nslab) * TY;
+  c.z0 = (tile / nslab) * H;
+  c.H = H;
+  c.lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  c.r = wave + 1u;
+  c.y = (y0 + L - 2u + c.r) & (L - 1u);
+  c.yh = (wave == (uint32_t)TY + 1u) ? (y0 + TY + 1u) & (L - 1u) : (y0 + L - 2u) & (L - 1u);
+  if (wave == 0)
+    run<TY, TOP>(c);
+  else if (wave == 1)
+    run<TY, JH>(c);
+  else if (wave == (uint32_t)TY + 1u)
+    run<TY, BOT>(c);
+  else if (c.r & 1u)
+    run<TY, ODD>(c);
+  else
+    run<TY, EVEN>(c);
+}
+
+size_t msc_col_lds(uint32_t TY) { return (size_t)(3 * (TY + 4) + 3 * (TY + 3)) * col::RW * 4; }
+
+bool msc_col_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H) {
+  return d == 3 && L == col::L && (TY == 4 || TY == 8) && H >= 2 && H % 2 == 0 && L % H == 0;
+}
+
+template <int TY>
+static hipError_t go_msc_col(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t H,
+                             hipStream_t stream) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_msc_col<TY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)msc_col_lds(TY));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const dim3 grid((col::L / TY) * (col::L / H));
+  hipLaunchKernelGGL((k_msc_col<TY>), grid, dim3(64 * (TY + 2)), msc_col_lds(TY), stream, src, dst, J, a, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_msc_col(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
+                          uint32_t TY, uint32_t H, hipStream_t stream) {
+  if (!msc_col_supported(a.L, d, TY, H)) return hipErrorInvalidValue;
+  return TY == 8 ? go_msc_col<8>(src, dst, J, a, H, stream) : go_msc_col<4>(src, dst, J, a, H, stream);
+}
+
 // E and M of the 32 systems: per workgroup, counts of unsatisfied bonds and
 // of negative spins for every bit into part[wg*64 + bit] (unsat) and
 // part[wg*64 + 32 + bit] (negative); k_msc_finalize sums the workgroups.

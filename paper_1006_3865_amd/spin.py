@@ -88,6 +88,7 @@ SIGNATURES = {
     "spin_msc_sweeps_done": (_c.c_uint64, [_P]),
     "spin_msc_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "spin_msc_synchronize": (_c.c_int, [_P]),
+    "spin_msc_kernel": (_c.c_int, [_P]),
     "spin_synchronize": (_c.c_int, [_P]),
     "spin_device_spins": (_c.c_void_p, [_P]),
     "spin_threshold_table": (_c.c_int, [_c.c_double, _c.c_int, _u64p]),
@@ -652,6 +653,11 @@ class Msc:
 
     def set_kernel(self, streaming, rows=0, planes=0, threads=0, width=0):
         _check(load().spin_msc_set_kernel(self.h, int(streaming), int(rows), int(planes), int(threads), int(width)))
+
+    @property
+    def kernel(self):
+        """0: one launch per colour; 1: streamed over planes; 2: register columns (3D L = 512)."""
+        return int(load().spin_msc_kernel(self.h))
 
     def synchronize(self):
         _check(load().spin_msc_synchronize(self.h))

@@ -84,17 +84,30 @@ def test_msc_rejects_bad_shapes():
     m.close()
 
 
-def test_msc_full_size_sampled_sites(oracle_mod):
-    """The 3D L = 512 handle in the launch shape the benchmark times: one sweep checked site by site
-    on a sample.  A colour-0 site is decided from the state before the sweep (its neighbours are
-    colour 1), a colour-1 site from its old value and the final colour-0 neighbours; each decision is
-    the oracle's rule (Eq. 2) with the shared Philox word of the site."""
+def boundary_sites(L, rows, planes):
+    """Sites on the edges of the kernels' tiles: slab rows (y = 0, rows-1, rows mod rows), strip planes,
+    the periodic x wrap and the edges of 8-site groups."""
+    ys = sorted({v % L for v in (0, 1, rows - 1, rows, rows + 1, L - 2, L - 1)})
+    zs = sorted({v % L for v in (0, 1, planes - 1, planes, planes + 1, L - 2, L - 1)})
+    xs = sorted({0, 1, 7, 8, L - 8, L - 1})
+    return np.array([(z * L + y) * L + x for z in zs for y in ys for x in xs], dtype=np.int64)
+
+
+@pytest.mark.parametrize("kernel", [None, (1, 8, 128, 512), (2, 8, 32), (2, 4, 16), (2, 8, 512)])
+def test_msc_full_size_sampled_sites(oracle_mod, kernel):
+    """The 3D L = 512 handle: the launch shape the benchmark times (the default, register columns), the
+    plane-streaming kernel and other register-column shapes; one sweep checked site by site on a sample that includes every tile edge.  A
+    colour-0 site is decided from the state before the sweep (its neighbours are colour 1), a colour-1
+    site from its old value and the final colour-0 neighbours; each decision is the oracle's rule
+    (Eq. 2) with the shared Philox word of the site."""
     L, d = 512, 3
     N = L ** d
     cs, seed, r0, p0 = workloads.seed(0x11), workloads.seed(0x10), 0, 0
     beta = workloads.ea_betas()[7]
-    note("msc full size", L, d)
+    note("msc full size", L, d, kernel)
     m = spin.Msc(L, d, cs, r0, seed, p0)
+    if kernel is not None:
+        m.set_kernel(*kernel)
     m.sweep(2, beta)
     systems = (0, 19, 31)
     before = {b: m.spins(b) for b in systems}
@@ -105,7 +118,10 @@ def test_msc_full_size_sampled_sites(oracle_mod):
     T = oracle_mod.table(beta, d)
     key = (seed & 0xFFFFFFFF, seed >> 32)
     rng = np.random.default_rng(0x5A)
-    sites = rng.choice(N, 3000, replace=False)
+    rows, planes = (kernel[1], kernel[2]) if kernel else (4, 256)   # the default: register columns
+    edge = boundary_sites(L, rows, planes)
+    rand = rng.choice(N, 3000, replace=False)
+    sites = np.unique(np.concatenate([edge, rand]))
     x, y, z = sites % L, (sites // L) % L, sites // (L * L)
     step = (1, L, L * L)
     coord = (x, y, z)
@@ -130,3 +146,42 @@ def test_msc_full_size_sampled_sites(oracle_mod):
             flip = r < int(T[(k + 2 * d) // 2])
             expect = -int(old[s]) if flip else int(old[s])
             assert int(new[s]) == expect, ("system", b, "site", s, "colour", c)
+
+
+@pytest.mark.parametrize("shape", [(8, 32), (4, 64), (8, 2)])
+def test_msc_column_kernel_equals_streaming_kernel(shape):
+    """The register-column kernel (3D L = 512) against the plane-streaming kernel, whose chain is the
+    oracle's at every size it was compared on: all 32 systems' spins (as the words of every site) and
+    the 32 energies and magnetisations after every sweep, over sweeps at several temperatures."""
+    import torch
+    L, d = 512, 3
+    cs, seed, r0, p0 = workloads.seed(0x64), workloads.seed(0x65), 3, 11
+    note("msc column vs stream", shape)
+    a = spin.Msc(L, d, cs, r0, seed, p0)
+    b = spin.Msc(L, d, cs, r0, seed, p0)
+    a.set_kernel(2, shape[0], shape[1])
+    b.set_kernel(1, 8, 64, 512)
+    for beta in (workloads.ea_betas()[3], math.inf, 0.0, 3.0):
+        Ea, Ma = a.sweep_record(2, beta, 1)
+        Eb, Mb = b.sweep_record(2, beta, 1)
+        np.testing.assert_array_equal(Ea, Eb)
+        np.testing.assert_array_equal(Ma, Mb)
+    for sysb in (0, 7, 31):
+        np.testing.assert_array_equal(a.spins(sysb), b.spins(sysb), err_msg="system %d" % sysb)
+    assert a.t == b.t == 8
+    a.close()
+    b.close()
+
+
+def test_msc_column_kernel_shapes():
+    m = spin.Msc(512, 3, 1, 0, 1)
+    for k in ((2, 6, 32), (2, 8, 3), (2, 8, 0, 512), (2, 8, 32, 0, 256), (3, 8, 32)):
+        with pytest.raises(spin.SpinError):
+            m.set_kernel(*k)
+    m.set_kernel(2, 8, 32, 640)
+    m.set_kernel(2, 4, 2)
+    m.close()
+    s = spin.Msc(256, 3, 1, 0, 1)
+    with pytest.raises(spin.SpinError):
+        s.set_kernel(2, 8, 32)
+    s.close()
