@@ -49,6 +49,9 @@ LDS_BYTES_PER_ATTEMPT = {2: 112 / 8.0, 3: 144 / 8.0}
 # 8-site group and sweep it stores the loaded row and the colour-0 result (16 B), reads one 8-byte
 # y neighbour per colour unit (16 B) and four bounds per unit (32 B): 64 B per 8 attempts.
 LDS_BYTES_PER_ATTEMPT_3R = 64 / 8.0
+# The 2D register-column form keeps every row of its column in registers: per 8-site group and sweep
+# four bounds per colour unit (32 B) and one 4-byte segment-end word for colour 1 (4 B).
+LDS_BYTES_PER_ATTEMPT_2C = 36 / 8.0
 
 
 def parse():
@@ -89,6 +92,7 @@ def parse():
 # Source files that define each profiled kernel (its counters are valid while they are unchanged).
 KERNEL_SOURCES = {
     "k_stream2d": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
+    "k_stream2c": ("spin_stream2d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_stream3d": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_stream3r": ("spin_stream3d.hip", "spin_phase.h", "spin_device.h", "spin_packed.h"),
     "k_streamg": ("spin_stream_kernels.hip", "spin_nibble.h", "spin_device.h"),
@@ -585,6 +589,7 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
             lat.set_kernel(kern, *tile)
         lats.append((lat, b))
     kname = spin.KERNEL_NAMES[lats[0][0].kernel]
+    ktile = lats[0][0].tile
     recs_per_step = sweeps_per_step // every
     nrec = steps * recs_per_step
     Erec = [torch.zeros(max(1, nrec), dtype=torch.int64, device="cuda") for _ in lats]
@@ -625,11 +630,11 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
            "sweeps_per_step": sweeps_per_step, "record_every": every,
            "value": round(steps * sweeps_per_step * N * len(lats) / (wall * 1e9), 2),
            "ms_per_step": round(wall * 1e3 / max(1, steps), 4)}
-    res.update(roofline_of(kname, L, d, N, so_sweeps, so_ms))
+    res.update(roofline_of(kname, L, d, N, so_sweeps, so_ms, ktile))
     return res
 
 
-def roofline_of(kname, L, d, N, so_sweeps, so_ms):
+def roofline_of(kname, L, d, N, so_sweeps, so_ms, tile=(0, 0, 0, 0)):
     """Sweep-only rate and the roofline of the dominant kernel from so_sweeps back-to-back sweeps that
     took so_ms (HIP events on the lattice's stream)."""
     launches_per_sweep = {"fused": 1, "tiled": 2, "generic": 2}.get(kname, 0)
@@ -640,7 +645,9 @@ def roofline_of(kname, L, d, N, so_sweeps, so_ms):
     alg_ops = ALG_OPS_PER_ATTEMPT[d]
     alu_tops = alg_ops * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e12
     hbm_gbs = BYTES_PER_ATTEMPT * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
-    kernel_tag = {("fused", 2): "k_stream2d", ("fused", 3): "k_stream3r" if L == 512 else "k_stream3d",
+    col2 = d == 2 and tile[0] == L and tile[2] == 1   # the register-column form of the 2D row streaming
+    kernel_tag = {("fused", 2): "k_stream2c" if col2 else "k_stream2d",
+                  ("fused", 3): "k_stream3r" if L == 512 else "k_stream3d",
                   ("tiled", 3): "k_tiled3d"}.get((kname, d), kname)
     traffic = profiled_traffic(kernel_tag, L)
     roof = {"bound": "alu", "achieved": round(alu_tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
@@ -651,7 +658,8 @@ def roofline_of(kname, L, d, N, so_sweeps, so_ms):
                     "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                     "alg_bytes_per_launch": int(BYTES_PER_ATTEMPT * attempts_per_launch)}}
     if kname == "fused":  # the streaming kernels
-        lb = LDS_BYTES_PER_ATTEMPT_3R if kernel_tag == "k_stream3r" else LDS_BYTES_PER_ATTEMPT[d]
+        lb = {"k_stream3r": LDS_BYTES_PER_ATTEMPT_3R, "k_stream2c": LDS_BYTES_PER_ATTEMPT_2C}.get(
+            kernel_tag, LDS_BYTES_PER_ATTEMPT[d])
         lds_gbs = lb * attempts_per_launch / (kernel_avg_us * 1e-6) / 1e9
         roof["lds"] = {"achieved": round(lds_gbs, 1), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
                        "frac": round(lds_gbs / LDS_PEAK_GBS, 4),
@@ -705,10 +713,11 @@ def bench_large2d(torch, spin, workloads, L=16384, sweeps=100):
     b.record(stream)
     lat.synchronize()
     kname = spin.KERNEL_NAMES[lat.kernel]
+    ktile = lat.tile
     lat.close()
     out = {"workload": "ising2d_L%d (sensitivity, not a workload)" % L, "beta": workloads.BETA_2D_CRIT,
            "kernel": kname, "sweeps": sweeps, "ping_pong_bytes": 2 * L * L}
-    out.update(roofline_of(kname, L, 2, L * L, sweeps, a.elapsed_time(b)))
+    out.update(roofline_of(kname, L, 2, L * L, sweeps, a.elapsed_time(b), ktile))
     return out
 
 

@@ -182,7 +182,10 @@ int spin_set_stream(spin_lattice* h, void* stream);
 /* Choose the kernel family and tile shape: tile_x (bytes, multiple of 8),
  * tile_y, tile_z (rows/planes) and threads per workgroup (multiple of 64).
  * 0 means the library default.  SPIN_EINVAL if the family cannot run this
- * lattice.  Results are bit-identical for every accepted choice. */
+ * lattice.  Results are bit-identical for every accepted choice.  2D Ising
+ * in SPIN_KERNEL_FUSED with full rows (tile_x == L >= 4096): tile_y is the
+ * strip height (even, >= 4) and tile_z 0 the row-streaming kernel, 1 its
+ * register-column form (sweeps that record E/M run the former). */
 int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads);
 
 /* Sec. 3, steps 1-7, with the generalized multi-hit of the paragraph after
@@ -221,6 +224,11 @@ int spin_get_rng_state(const spin_lattice* h, uint64_t* out, size_t n);
 
 /* Kernel family that spin_sweep will use next (spin_kernel value). */
 int spin_get_kernel(const spin_lattice* h);
+
+/* Tile shape that spin_sweep will use next (as spin_set_kernel takes it;
+ * for the 2D row-streaming kernel tile_z == 1 selects its register-column
+ * form).  Host ints; NULL pointers are skipped. */
+int spin_get_tile(const spin_lattice* h, int* tile_x, int* tile_y, int* tile_z, int* threads);
 
 /* Wait for the handle's queued work. */
 int spin_synchronize(spin_lattice* h);

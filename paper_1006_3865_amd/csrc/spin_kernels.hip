@@ -755,10 +755,10 @@ __global__ __launch_bounds__(256) void k_fused2d_w(const int8_t* __restrict__ sr
 bool fused_supported(const Lat& lat, const Tile& tile) {
   if (lat.d == 3) return stream3d_shape(lat, tile);
   if (lat.J != nullptr || lat.d != 2) return false;
-  if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
+  if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {  // row streaming; tile.z == 1: register columns
     int G;
     return stream2d_shape(lat.L, tile.threads, &G) && tile.y >= 4 && tile.y % 2 == 0 &&
-           lat.L % (uint32_t)tile.y == 0 && (uint32_t)tile.y <= lat.L;
+           lat.L % (uint32_t)tile.y == 0 && (uint32_t)tile.y <= lat.L && (tile.z == 0 || tile.z == 1);
   }
   if (lat.L % 16 != 0 || lat.L < 32) return false;
   if (lat.L % tile.x != 0 || lat.L % tile.y != 0) return false;
@@ -811,6 +811,10 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
   if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
     int G = 0;
     stream2d_shape(lat.L, tile.threads, &G);
+    // the register-column kernel does not count E/M: a sweep that records runs the row-streaming
+    // kernel, which counts inside the sweep (same chain)
+    if (tile.z == 1 && rec == nullptr)
+      return launch_stream2c(lat, src, dst, a, never, (uint32_t)tile.y, tile.threads, G, stream);
     if (measured) *measured = (rec != nullptr);
     return launch_stream2d(lat, src, dst, a, never, (uint32_t)tile.y, rec, tile.threads, G, stream);
   }

@@ -222,6 +222,183 @@ __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2D Ising, one whole sweep per launch, with each thread's column of groups
+// held in registers (k_stream2c).  L = 8 * NT * G; thread t owns the groups
+// g = t + NT*j (j < G) of every row of the strip [y0, y0+H), so the 64 lanes
+// of a wave hold one 512-site segment of each row (segment s = wave + W*j, W
+// = NT/64 waves, NS = L/512 segments per row).  Row k of the strip (y =
+// y0-2+k) lives in register slot k & 7.  Step i = 0..H+4, a = y0-1+i:
+//   load row a+2 (and each lane's edge word, below);
+//   colour 0 on row a (i <= H+1): y neighbours rows a-1 (after its colour 0)
+//     and a+1 (as loaded) from registers, x neighbours by a wavefront rotate;
+//   colour 1 on row b = a-4 (i >= 5): rows b-1..b+1 after colour 0 from
+//     registers; the group goes to dst.
+// The only data that crosses waves is the x neighbour at a segment's ends.
+// Colour 0 reads it as loaded: every lane loads one more word with its row,
+// lane 0 the word left of its segment, lane 63 the word right of it (the
+// others a word of their own group).  Colour 1 needs the neighbouring
+// segment's colour-0 result: after colour 0 on a row, lane 0 of each
+// segment puts its low word and lane 63 its high word into an LDS ring of 8
+// rows, and colour 1 reads them 4 steps later.  A barrier after every 4th
+// step orders each such write before its read and each read before the slot
+// is written again (written in step k-1 for row k, read in step k+3,
+// rewritten in step k+7).  No spin row goes through LDS.
+template <int NT, int G>
+struct Col2Ctx {
+  static constexpr uint32_t L = 8u * NT * G;
+  static constexpr uint32_t GPR = L / 8;
+  static constexpr uint32_t W = NT / 64;
+  static constexpr uint32_t NS = W * G;  // segments per row
+  __amdgpu_buffer_rsrc_t rsrc, rdst;
+  uint32_t* edge;                        // LDS: [slot 8][segment NS][lo, hi]
+  const uint32_t* bound;
+  const RoundKeys* keys;
+  PhiloxUniform U0, U1;
+  uint32_t never4, y0, H, t, lane;
+  uint32_t eoff[G];                      // byte offset in a row of this lane's edge word
+  uint32_t lnb[G], rnb[G];               // LDS word of the left segment's high word, the right one's low word
+  uint32_t own[G];                       // LDS word of this segment's low word
+};
+
+template <uint32_t P, bool NEVER>
+__device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t nb, uint32_t c0,
+                                           const PhiloxUniform& U, const RoundKeys& K, const uint32_t* bound,
+                                           uint32_t never4) {
+  uint32_t rnd[4];
+  philox_lane(c0, U, K, rnd);
+  const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
+  const uint32_t Sp = unsat_packed<2>(P, c.x, c.y, nb, nb, o0, o1);
+  uint32_t c0n = c.x, c1n = c.y;
+  apply_packed<NEVER>(P, c0n, c1n, Sp, rnd, bound, never4);
+  return make_uint2(c0n, c1n);
+}
+
+// x neighbour dword for active parity P (P = 0: the high dword of the group to
+// the left; P = 1: the low dword of the group to the right) from the
+// adjacent lane, or at the segment's end (lane 0 / lane 63) the value given.
+template <uint32_t P>
+__device__ __forceinline__ uint32_t col2_xnb(uint2 c, uint32_t lane, uint32_t end) {
+  if (P == 0) {
+    const uint32_t v = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.y, 0x13C, 0xF, 0xF, false);  // wave_ror:1
+    return lane == 0 ? end : v;
+  }
+  const uint32_t v = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.x, 0x134, 0xF, 0xF, false);    // wave_rol:1
+  return lane == 63 ? end : v;
+}
+
+template <int NT, int G, bool NEVER, uint32_t S>
+__device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8][G], uint32_t (&E)[8][G],
+                                          uint32_t i) {
+  using C = Col2Ctx<NT, G>;
+  constexpr uint32_t L = C::L, GPR = C::GPR, NS = C::NS;
+  if (i >= c.H + 5) return;
+  // row a+2 = strip row i+3 (steps after i = H reload row H+3, which nothing reads)
+  const uint32_t yl = wrap_row(c.y0 + (i <= c.H ? i : c.H) + 3u, 2u, L);
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * (c.t + NT * j), yl * L, 0);
+    R[(S + 3) & 7][j] = make_uint2(w.x, w.y);
+    E[(S + 3) & 7][j] = __builtin_amdgcn_raw_buffer_load_b32(c.rsrc, c.eoff[j], yl * L, 0);
+  }
+  if (i <= c.H + 1) {
+    // colour 0 on row a (strip row i+1, register slot S+1); a has the parity of i+1
+    constexpr uint32_t P = (S + 1u) & 1u;
+    const uint32_t y = wrap_row(c.y0 + i + 1u, 2u, L);
+    uint32_t* slot = c.edge + ((S + 1u) & 7u) * (2u * NS);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint2 cc = R[(S + 1) & 7][j];
+      const uint32_t nb = col2_xnb<P>(cc, c.lane, E[(S + 1) & 7][j]);
+      const uint2 n = col2_unit<P, NEVER>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, y * GPR + c.t + NT * j, c.U0,
+                                          *c.keys, c.bound, c.never4);
+      R[(S + 1) & 7][j] = n;
+      if (c.lane == 0) slot[c.own[j]] = n.x;
+      if (c.lane == 63) slot[c.own[j] + 1u] = n.y;
+    }
+  }
+  if (i >= 5) {
+    // colour 1 on row b (strip row i-3, register slot S+5); 1 + b has the parity of i
+    constexpr uint32_t P = S & 1u;
+    const uint32_t y = c.y0 + i - 5u;
+    const uint32_t* slot = c.edge + ((S + 5u) & 7u) * (2u * NS);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const uint2 cc = R[(S + 5) & 7][j];
+      const uint32_t nb = col2_xnb<P>(cc, c.lane, slot[P == 0 ? c.lnb[j] : c.rnb[j]]);
+      const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, y * GPR + c.t + NT * j,
+                                          c.U1, *c.keys, c.bound, c.never4);
+      R[(S + 5) & 7][j] = n;
+      const u32x2 w = {n.x, n.y};
+      __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * (c.t + NT * j), y * L, 0);
+    }
+  }
+  if ((S & 3u) == 3u) __syncthreads();
+}
+
+template <int NT, int G, bool NEVER>
+__global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src, int8_t* __restrict__ dst,
+                                                 PhaseArgs a, uint32_t H) {
+  using C = Col2Ctx<NT, G>;
+  constexpr uint32_t L = C::L, NS = C::NS;
+  __shared__ __align__(16) uint32_t lds[8 + 8 * 2 * NS];
+  C c;
+  c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(L * L), 0x00020000);
+  c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(L * L), 0x00020000);
+  c.bound = lds;
+  c.edge = lds + 8;
+  c.keys = &a.keys;
+  c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
+  c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
+  c.never4 = a.never4;
+  c.y0 = blockIdx.x * H;
+  c.H = H;
+  c.t = threadIdx.x;
+  c.lane = threadIdx.x & 63u;
+  const uint32_t wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const uint32_t g = c.t + NT * j, s = wave + C::W * j;
+    c.eoff[j] = c.lane == 0 ? (g ? 8u * g - 4u : L - 4u) : (c.lane == 63 ? (8u * (g + 1u)) % L : 8u * g);
+    c.own[j] = 2u * s;
+    c.lnb[j] = 2u * ((s + NS - 1u) % NS) + 1u;
+    c.rnb[j] = 2u * ((s + 1u) % NS);
+  }
+  if (threadIdx.x < 8) lds[threadIdx.x] = a.bound[threadIdx.x];
+  uint2 R[8][G];
+  uint32_t E[8][G];
+  // prologue: strip rows 0, 1, 2 (y0-2, y0-1, y0)
+#pragma unroll
+  for (uint32_t k = 0; k < 3; ++k) {
+    const uint32_t y = wrap_row(c.y0 + k, 2u, L);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * (c.t + NT * j), y * L, 0);
+      R[k][j] = make_uint2(w.x, w.y);
+      E[k][j] = __builtin_amdgcn_raw_buffer_load_b32(c.rsrc, c.eoff[j], y * L, 0);
+    }
+  }
+#pragma unroll
+  for (int k = 3; k < 8; ++k)
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      R[k][j] = make_uint2(0u, 0u);
+      E[k][j] = 0u;
+    }
+  __syncthreads();
+  const uint32_t steps = H + 5;
+  for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
+    col2_step<NT, G, NEVER, 0>(c, R, E, i0 + 0);
+    col2_step<NT, G, NEVER, 1>(c, R, E, i0 + 1);
+    col2_step<NT, G, NEVER, 2>(c, R, E, i0 + 2);
+    col2_step<NT, G, NEVER, 3>(c, R, E, i0 + 3);
+    col2_step<NT, G, NEVER, 4>(c, R, E, i0 + 4);
+    col2_step<NT, G, NEVER, 5>(c, R, E, i0 + 5);
+    col2_step<NT, G, NEVER, 6>(c, R, E, i0 + 6);
+    col2_step<NT, G, NEVER, 7>(c, R, E, i0 + 7);
+  }
+}
+
 // Streaming variants: tile.x == L (full rows), tile.y = strip height H,
 // tile.threads = NT with L = 8 * NT * G.
 bool stream2d_shape(uint32_t L, int threads, int* G) {
@@ -251,6 +428,27 @@ static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const
       hipLaunchKernelGGL((k_stream2d<NT, G, false, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
   }
   return hipGetLastError();
+}
+
+template <int NT, int G>
+static hipError_t gocol2(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
+                         uint32_t H, hipStream_t stream) {
+  dim3 grid(lat.L / H);
+  if (never)
+    hipLaunchKernelGGL((k_stream2c<NT, G, true>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  else
+    hipLaunchKernelGGL((k_stream2c<NT, G, false>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream2c(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
+                           uint32_t H, int threads, int G, hipStream_t stream) {
+  if (threads == 1024 && G == 1) return gocol2<1024, 1>(lat, src, dst, a, never, H, stream);
+  if (threads == 1024 && G == 2) return gocol2<1024, 2>(lat, src, dst, a, never, H, stream);
+  if (threads == 512 && G == 1) return gocol2<512, 1>(lat, src, dst, a, never, H, stream);
+  if (threads == 512 && G == 2) return gocol2<512, 2>(lat, src, dst, a, never, H, stream);
+  if (threads == 256 && G == 2) return gocol2<256, 2>(lat, src, dst, a, never, H, stream);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stream2d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,

@@ -65,6 +65,7 @@ SIGNATURES = {
     "spin_set_stream": (_c.c_int, [_P, _c.c_void_p]),
     "spin_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "spin_get_kernel": (_c.c_int, [_P]),
+    "spin_get_tile": (_c.c_int, [_P, _ip, _ip, _ip, _ip]),
     "spin_autotune": (_c.c_int, [_P, _c.c_double, _c.c_int]),
     "spin_set_schedule": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int]),
     "spin_set_rng": (_c.c_int, [_P, _c.c_int]),
@@ -440,6 +441,13 @@ class Lattice:
     @property
     def kernel(self):
         return spin_get_kernel(self.h)
+
+    @property
+    def tile(self):
+        """(tile_x, tile_y, tile_z, threads) of the next sweep's kernel."""
+        v = [_c.c_int(0) for _ in range(4)]
+        _check(load().spin_get_tile(self.h, *[_c.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def set_stream(self, stream):
         spin_set_stream(self.h, stream if isinstance(stream, int) or stream is None else stream.cuda_stream)

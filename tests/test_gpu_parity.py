@@ -262,6 +262,20 @@ def test_ising2d_streaming_rows(oracle_mod, tile, L):
                  tag="stream")
 
 
+@pytest.mark.parametrize("tile,L", [
+    ((4096, 16, 1, 512), 4096), ((4096, 8, 1, 256), 4096), ((4096, 64, 1, 512), 4096),
+    ((8192, 16, 1, 1024), 8192), ((8192, 32, 1, 512), 8192), ((8192, 4, 1, 1024), 8192),
+])
+def test_ising2d_register_columns(oracle_mod, tile, L):
+    """Register-column form of the row-streaming kernel (tile_z = 1): sweeps without records run it,
+    sweeps that record run the row-streaming kernel; both continue one chain.  Several strips, one
+    and two 8-site groups per thread, the periodic x wrap between the first and last segment, and
+    betas with T == 0 entries (3, inf) and 0."""
+    sched = [(3, B_CRIT, 0), (2, 3.0, 2), (5, 0.6, 5), (1, 0.0, 0), (2, math.inf, 0), (4, 0.3, 0)]
+    compare_runs(oracle_mod, 0, L, 2, workloads.seed(0x90 + L), sched, replica=2, kernel=FUS, tile=tile,
+                 tag="columns")
+
+
 @pytest.mark.parametrize("model,L,d", [(0, 96, 3), (1, 96, 3), (0, 4112, 2), (1, 48, 3)])
 def test_measure_ragged_row_ranges(oracle_mod, model, L, d):
     """E/M counting when the rows do not divide evenly among the counting workgroups (3D L = 96:
@@ -382,6 +396,19 @@ def check_sweep_sampled(oracle_mod, old, new, L, d, J, seed, replica, t, beta, n
         r = int(oracle_mod.philox4x32_10((s >> 3, t, replica, c), key)[(s >> 1) & 3])
         flip = r < int(T[(k + 2 * d) // 2])
         assert int(new[s]) == (-int(old[s]) if flip else int(old[s])), ("site", s, "colour", c)
+
+
+@pytest.mark.parametrize("L,d,beta,tile,every", [
+    (16384, 2, B_CRIT, (16384, 16, 0, 1024), 1),   # row-streaming kernel, two 8-site groups per thread
+    (16384, 2, B_CRIT, (16384, 16, 1, 1024), 0),   # its register-column form (no record)
+    (16384, 2, B_CRIT, (512, 16, 0, 256), 1),      # tiled fused kernel
+    (1024, 3, B_3D, None, 1)])
+def test_largest_sizes_whole_lattice(oracle_mod, L, d, beta, tile, every):
+    """The largest lattices the specialised kernels take, every site: from the same hot start as the
+    oracle's chain, one sweep (with its record when every = 1); spins at every site and (E, M)."""
+    kern, t = (spin.SPIN_KERNEL_FUSED, tile) if tile else (spin.SPIN_KERNEL_AUTO, (0, 0, 0, 0))
+    compare_runs(oracle_mod, 0, L, d, workloads.seed(0xA0 + d), [(1, beta, every)], replica=1, kernel=kern,
+                 tile=t, tag="largest, whole lattice")
 
 
 @pytest.mark.parametrize("model,L,d,beta,tile", [
