@@ -339,7 +339,7 @@ int spin_batch_sweep(spin_batch* b, const int* n, const double* beta, int every,
 
 /* Sec. 4 (tile sizes chosen by experiment), for the persistent launch: for
  * every lattice shape (d, model, L) among the pool's LDS-held members, time
- * each launch shape -- workgroups of 256, 512 or 1024 threads, 1 .. as many
+ * each launch shape -- workgroups of 256, 512, 576 or 1024 threads, 1 .. as many
  * workgroups per CU as threads and LDS allow -- on scratch lattices of that
  * shape (as many as the pool holds, at most four per CU), `sweeps` sweeps at
  * beta each; check that every candidate leaves identical spins (else

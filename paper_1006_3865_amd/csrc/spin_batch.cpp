@@ -164,7 +164,7 @@ void load_plans_locked() {
   if (g_plan_loaded) return;
   g_plan_loaded = true;
   for (const auto& v : tune_cache_read("batch"))
-    if (v.size() >= 5 && (v[3] == 256 || v[3] == 512 || v[3] == 1024) && v[4] >= 1 && v[4] <= 8)
+    if (v.size() >= 5 && batch_threads_ok((uint32_t)v[3]) && v[4] >= 1 && v[4] <= 8)
       g_plan[std::make_tuple((int)v[0], (int)v[1], (int)v[2])] = Plan{(uint32_t)v[3], (uint32_t)v[4]};
 }
 
@@ -548,7 +548,7 @@ static int batch_run(spin_batch* b, const int* n, const double* beta, int every,
     Plan pl{0, 0};
     const bool planned = b->force_nt ? (pl = Plan{b->force_nt, b->force_per_cu}, true)
                                      : plan_for(mb.d, mb.model, mb.L, &pl);
-    const uint32_t nt = planned ? pl.nt : batch_threads_for(mb.N / 8);
+    const uint32_t nt = planned ? pl.nt : batch_threads_for((uint32_t)mb.L, (uint32_t)mb.d);
     const auto key = std::make_tuple(mb.d, mb.model, nt);
     auto it = cls_index.find(key);
     if (it == cls_index.end()) {
@@ -867,7 +867,7 @@ int spin_batch_autotune(spin_batch* b, double beta, int sweeps) {
       uint64_t hash;
     };
     std::vector<Cand> cands;
-    for (uint32_t nt : {256u, 512u, 1024u}) {
+    for (uint32_t nt : {256u, 512u, 576u, 1024u}) {
       if ((uint32_t)L / 8 > nt) continue;
       for (uint32_t pc = 1; pc <= max_per_cu(nt, lds); ++pc) cands.push_back(Cand{nt, pc, 0.f, 0});
     }

@@ -49,12 +49,22 @@ inline bool batch_fits(uint32_t L, uint32_t d) {
   return L >= 8 && L % 8 == 0 && batch_lds_bytes(L, d) <= kBatchMaxLds;
 }
 
-// Workgroup size of the batch kernel for a lattice of nwords nibble words.
-inline uint32_t batch_threads_for(uint64_t nwords) {
-  if (nwords <= 2048) return 256;
-  if (nwords <= 8192) return 512;
-  return 1024;
+// Workgroup size of the batch kernel for a lattice of edge L in d dimensions:
+// 256, 512 or 1024 threads by size (L^d/8 nibble words up to 2048, 8192,
+// more), or 576 where that size makes the rows a thread visits all share one
+// y (threads / (L/8) a multiple of L, e.g. L = 24 and 48) and the power-of-two
+// size does not.
+inline uint32_t batch_threads_for(uint32_t L, uint32_t d) {
+  const uint64_t nwords = (d == 3 ? (uint64_t)L * L * L : (uint64_t)L * L) / 8;
+  const uint32_t nt = nwords <= 2048 ? 256u : (nwords <= 8192 ? 512u : 1024u);
+  const uint32_t lg = L / 8;
+  const auto yfix = [&](uint32_t t) { return lg >= 1 && lg <= t && (t / lg) % L == 0; };
+  if (!yfix(nt) && yfix(576u)) return 576u;
+  return nt;
 }
+
+// Workgroup sizes the batch kernel is built for.
+inline bool batch_threads_ok(uint32_t nt) { return nt == 256 || nt == 512 || nt == 576 || nt == 1024; }
 
 // Write lat and call into blk (a device BatchSingle) and sweep the lattice as
 // one task (nt threads, LDS for the whole lattice), all on `stream`.

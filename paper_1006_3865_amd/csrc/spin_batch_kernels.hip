@@ -174,8 +174,11 @@ __device__ __forceinline__ void batch_colour(uint32_t* sp, const uint32_t* bound
     nb[1] = sp[wyp];
     uint32_t wzm = 0;
     if (D == 3) {
-      wzm = w + (z ? 0u - PS : g.zm_wrap);
-      const uint32_t wzp = w + ((z + 1 < L) ? PS : 0u - g.zm_wrap);
+      // planes z-1 and z+1, periodic: w -/+ PS wrapped into [0, NW) by an unsigned minimum (the
+      // out-of-range candidate has wrapped past 2^32 or is at least NW), no per-lane select
+      const uint32_t m = w - PS, q = w + PS;
+      wzm = __builtin_elementwise_min(m, m + NW);
+      const uint32_t wzp = __builtin_elementwise_min(q, q - NW);
       nb[2] = sp[wzm];
       nb[3] = sp[wzp];
     }
@@ -358,6 +361,7 @@ hipError_t launch_batch(uint32_t d, bool ea, uint32_t nt, BatchLattice* lats, co
   if (!attr) {
     hipError_t e = set_batch_attrs<256>();
     if (e == hipSuccess) e = set_batch_attrs<512>();
+    if (e == hipSuccess) e = set_batch_attrs<576>();
     if (e == hipSuccess) e = set_batch_attrs<1024>();
     if (e != hipSuccess) return e;
     attr = true;
@@ -367,7 +371,9 @@ hipError_t launch_batch(uint32_t d, bool ea, uint32_t nt, BatchLattice* lats, co
   if (e != hipSuccess) return e;
   if (nt == 256) go_batch<256>(d, ea, dim3(grid), lds_bytes, stream, lats, calls, order, ntasks, counter);
   else if (nt == 512) go_batch<512>(d, ea, dim3(grid), lds_bytes, stream, lats, calls, order, ntasks, counter);
-  else go_batch<1024>(d, ea, dim3(grid), lds_bytes, stream, lats, calls, order, ntasks, counter);
+  else if (nt == 576) go_batch<576>(d, ea, dim3(grid), lds_bytes, stream, lats, calls, order, ntasks, counter);
+  else if (nt == 1024) go_batch<1024>(d, ea, dim3(grid), lds_bytes, stream, lats, calls, order, ntasks, counter);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -62,21 +62,24 @@ __device__ __forceinline__ uint32_t nib_unsat(uint32_t c, uint32_t lw, uint32_t 
 
 // Flip mask (0xE per flipped nibble) for the active nibbles p, p+2, p+4, p+6:
 // S is shifted so the active nibbles sit at 0, 2, 4, 6 (constant offsets),
-// and the mask is shifted back.
+// their 2u values doubled into one byte each (4u: the bound table's byte
+// offset, at most 24), the bytes taken out one operation each, and the mask
+// shifted back.
 template <bool NEVER>
 __device__ __forceinline__ uint32_t nib_flips(uint32_t S, uint32_t p, const uint32_t r[4],
                                               const uint32_t* bound, uint32_t never4) {
-  const uint32_t Sp = S >> (4u * p);
-  uint32_t f = 0;
+  const uint32_t T = ((S >> (4u * p)) & 0x0F0F0F0Fu) << 1;  // byte i: 4u of active nibble i
+  const uint32_t i4[4] = {T & 0xFFu, __builtin_amdgcn_perm(0u, T, 0x0C0C0C01u), __builtin_amdgcn_ubfe(T, 16u, 8u),
+                          T >> 24};
+  uint32_t f[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t u2 = (Sp >> (8 * i)) & 0xFu;  // 2u of active nibble i
-    const uint32_t b = *(const uint32_t*)((const char*)bound + 2u * u2);
+    const uint32_t b = *(const uint32_t*)((const char*)bound + i4[i]);
     bool acc = r[i] <= b;
-    if (NEVER) acc = acc && (2u * u2 >= never4);
-    f |= acc ? (0xEu << (8 * i)) : 0u;
+    if (NEVER) acc = acc && (i4[i] >= never4);
+    f[i] = acc ? (0xEu << (8 * i)) : 0u;
   }
-  return f << (4u * p);
+  return (xor3(f[0], f[1], f[2]) ^ f[3]) << (4u * p);
 }
 
 // Global-address-space view of a device pointer (loads with a 32-bit offset

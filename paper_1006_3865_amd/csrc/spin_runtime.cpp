@@ -304,13 +304,13 @@ static void destroy(spin_lattice* h) {
 
 // Workgroup size when the RESIDENT family runs on the nibble batch kernel
 // (L % 8 == 0 and the packed lattice fits LDS), else 0 (the per-site kernel).
-// A requested size of 256, 512 or 1024 is used; none (0) picks by lattice
-// size; any other requested size selects the per-site kernel.
+// A requested size of 256, 512, 576 or 1024 is used; none (0) picks by
+// lattice shape; any other requested size selects the per-site kernel.
 static uint32_t single_threads(const spin_lattice* h, const Tile& tile) {
   if (!batch_fits((uint32_t)h->L, (uint32_t)h->d)) return 0;
   const int req = tile.threads;
-  if (req == 0) return batch_threads_for(h->N / 8);
-  if (req == 256 || req == 512 || req == 1024) return (uint32_t)req;
+  if (req == 0) return batch_threads_for((uint32_t)h->L, (uint32_t)h->d);
+  if (req > 0 && batch_threads_ok((uint32_t)req)) return (uint32_t)req;
   return 0;
 }
 

@@ -276,15 +276,13 @@ __device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t
 
 // x neighbour dword for active parity P (P = 0: the high dword of the group to
 // the left; P = 1: the low dword of the group to the right) from the
-// adjacent lane, or at the segment's end (lane 0 / lane 63) the value given.
+// adjacent lane, or at the segment's end (lane 0 / lane 63) the value given:
+// a wavefront shift by one lane (wave_shr:1 / wave_shl:1) with bound_ctrl off
+// leaves the lane that has no source lane with the old value, `end`.
 template <uint32_t P>
-__device__ __forceinline__ uint32_t col2_xnb(uint2 c, uint32_t lane, uint32_t end) {
-  if (P == 0) {
-    const uint32_t v = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.y, 0x13C, 0xF, 0xF, false);  // wave_ror:1
-    return lane == 0 ? end : v;
-  }
-  const uint32_t v = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.x, 0x134, 0xF, 0xF, false);    // wave_rol:1
-  return lane == 63 ? end : v;
+__device__ __forceinline__ uint32_t col2_xnb(uint2 c, uint32_t end) {
+  if (P == 0) return (uint32_t)__builtin_amdgcn_update_dpp((int)end, (int)c.y, 0x138, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)end, (int)c.x, 0x130, 0xF, 0xF, false);
 }
 
 template <int NT, int G, bool NEVER, uint32_t S>
@@ -309,7 +307,7 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 1) & 7][j];
-      const uint32_t nb = col2_xnb<P>(cc, c.lane, E[(S + 1) & 7][j]);
+      const uint32_t nb = col2_xnb<P>(cc, E[(S + 1) & 7][j]);
       const uint2 n = col2_unit<P, NEVER>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, y * GPR + c.t + NT * j, c.U0,
                                           *c.keys, c.bound, c.never4);
       R[(S + 1) & 7][j] = n;
@@ -325,7 +323,7 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 5) & 7][j];
-      const uint32_t nb = col2_xnb<P>(cc, c.lane, slot[P == 0 ? c.lnb[j] : c.rnb[j]]);
+      const uint32_t nb = col2_xnb<P>(cc, slot[P == 0 ? c.lnb[j] : c.rnb[j]]);
       const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, y * GPR + c.t + NT * j,
                                           c.U1, *c.keys, c.bound, c.never4);
       R[(S + 5) & 7][j] = n;

@@ -48,7 +48,7 @@ def test_queue_barriers_in_outermost_loop(tmp_path):
                            "-o", asm], stderr=subprocess.DEVNULL)
     lines = open(asm).read().split("\n")
     names = [l.split(":")[0] for l in lines if re.match(r"^_ZN4spin7k_batch\w+:", l)]
-    assert len(names) == 12
+    assert len(names) == 16
     for name in names:
         start = next(i for i, l in enumerate(lines) if l.startswith(name + ":"))
         end = next(i for i in range(start, len(lines)) if lines[i].strip().startswith(".Lfunc_end"))

@@ -55,7 +55,7 @@ def test_autotune_plans_persist_and_keep_bits(oracle_mod):
     note("plans: 3D +-J L=16", p16, " 2D Ising L=64", p64)
     assert p16 is not None and p64 is not None
     for nt, w in (p16, p64):
-        assert nt in (256, 512, 1024) and 1 <= w <= 2048 // nt
+        assert nt in (256, 512, 576, 1024) and 1 <= w <= 2048 // nt
     assert all(b.t(i) == 0 for i in range(len(ds)))        # the pool's own lattices untouched
     b.close()
     after = run_pool(ds, 12, 0.7, 4)
