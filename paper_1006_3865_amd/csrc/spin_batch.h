@@ -51,19 +51,15 @@ inline bool batch_fits(uint32_t L, uint32_t d) {
 
 // Workgroup size of the batch kernel for a lattice of edge L in d dimensions:
 // 256, 512 or 1024 threads by size (L^d/8 nibble words up to 2048, 8192,
-// more), or 576 where that size makes the rows a thread visits all share one
-// y (threads / (L/8) a multiple of L, e.g. L = 24 and 48) and the power-of-two
-// size does not.
+// more).  Sizes shared by many shapes keep them in one persistent launch.
 inline uint32_t batch_threads_for(uint32_t L, uint32_t d) {
   const uint64_t nwords = (d == 3 ? (uint64_t)L * L * L : (uint64_t)L * L) / 8;
-  const uint32_t nt = nwords <= 2048 ? 256u : (nwords <= 8192 ? 512u : 1024u);
-  const uint32_t lg = L / 8;
-  const auto yfix = [&](uint32_t t) { return lg >= 1 && lg <= t && (t / lg) % L == 0; };
-  if (!yfix(nt) && yfix(576u)) return 576u;
-  return nt;
+  return nwords <= 2048 ? 256u : (nwords <= 8192 ? 512u : 1024u);
 }
 
-// Workgroup sizes the batch kernel is built for.
+// Workgroup sizes the batch kernel is built for (576 = 9 wavefronts: rows of a
+// fixed y for L = 24 and 48 with every thread busy; a choice of the autotuner
+// or the caller).
 inline bool batch_threads_ok(uint32_t nt) { return nt == 256 || nt == 512 || nt == 576 || nt == 1024; }
 
 // Write lat and call into blk (a device BatchSingle) and sweep the lattice as

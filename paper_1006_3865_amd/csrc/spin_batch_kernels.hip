@@ -213,6 +213,93 @@ __device__ __forceinline__ void batch_colour(uint32_t* sp, const uint32_t* bound
   }
 }
 
+// The same phase with two adjacent words per thread (rows of an even number
+// of words): the pair is one 8-byte LDS access per neighbour row and one
+// 8-byte coupling load per direction and side, so a word costs 3 coupling
+// loads instead of 6 and 4.5 LDS reads instead of 7 (the coupling loads
+// through the vector memory path, not the ALU, set this kernel's pace).  The
+// x neighbours and the x bond between the two words come from the pair
+// itself.  g describes the pair columns: xg the pair, wl / wr the offsets of
+// the words left of the first and right of the second word.
+template <int D, bool EA, bool NEVER, bool YFIX>
+__device__ __forceinline__ void batch_colour2(uint32_t* sp, const uint32_t* bound, __amdgpu_buffer_rsrc_t rj,
+                                              const BatchGeo& g, const PhiloxUniform& U, const RoundKeys& K,
+                                              uint32_t colour, uint32_t nev) {
+  const uint32_t L = g.L, LG = g.LG, PS = g.PS, NW = g.NW;
+  uint32_t y = g.r_first % L, z = g.r_first / L;
+  const uint32_t ymo = y ? 0u - LG : g.ym_wrap;               // used when YFIX
+  const uint32_t ypo = (y + 1 < L) ? LG : 0u - g.ym_wrap;
+  uint32_t p = (colour + y + z) & 1u;
+  const uint32_t pstep = g.dz & 1u;
+  const uint32_t wstep = g.RI * LG;
+  uint32_t w = g.r_first * LG + 2u * g.xg;
+  for (uint32_t row = g.r_first; row < g.R; row += g.RI, w += wstep) {
+    const uint2 c = *reinterpret_cast<const uint2*>(sp + w);
+    const uint32_t lw = sp[w + g.wl], rw = sp[w + g.wr];
+    const uint32_t wym = w + (YFIX ? ymo : (y ? 0u - LG : g.ym_wrap));
+    const uint32_t wyp = w + (YFIX ? ypo : ((y + 1 < L) ? LG : 0u - g.ym_wrap));
+    uint2 nbp[2 * D - 2];
+    nbp[0] = *reinterpret_cast<const uint2*>(sp + wym);
+    nbp[1] = *reinterpret_cast<const uint2*>(sp + wyp);
+    uint32_t wzm = 0;
+    if (D == 3) {
+      const uint32_t m = w - PS, q = w + PS;
+      wzm = __builtin_elementwise_min(m, m + NW);
+      const uint32_t wzp = __builtin_elementwise_min(q, q - NW);
+      nbp[2] = *reinterpret_cast<const uint2*>(sp + wzm);
+      nbp[3] = *reinterpret_cast<const uint2*>(sp + wzp);
+    }
+    uint32_t nb0[2 * D - 2], nb1[2 * D - 2], jn0[2 * D], jn1[2 * D];
+#pragma unroll
+    for (int k = 0; k < 2 * D - 2; ++k) {
+      nb0[k] = nbp[k].x;
+      nb1[k] = nbp[k].y;
+    }
+    if (EA) {
+      typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+      const u2v jx = __builtin_amdgcn_raw_buffer_load_b64(rj, 4u * w, 0, 0);
+      const uint32_t jxl = __builtin_amdgcn_raw_buffer_load_b32(rj, 4u * (w + g.wl), 0, 0);
+      const u2v jy = __builtin_amdgcn_raw_buffer_load_b64(rj, 4u * w, 4u * NW, 0);
+      const u2v jym = __builtin_amdgcn_raw_buffer_load_b64(rj, 4u * wym, 4u * NW, 0);
+      jn0[0] = __builtin_amdgcn_alignbit(jx.x, jxl, 28);   // bond (x-1, x)
+      jn0[1] = jx.x;                                       // bond (x, x+1)
+      jn1[0] = __builtin_amdgcn_alignbit(jx.y, jx.x, 28);
+      jn1[1] = jx.y;
+      jn0[2] = jym.x;
+      jn0[3] = jy.x;
+      jn1[2] = jym.y;
+      jn1[3] = jy.y;
+      if (D == 3) {
+        const u2v jz = __builtin_amdgcn_raw_buffer_load_b64(rj, 4u * w, 8u * NW, 0);
+        const u2v jzm = __builtin_amdgcn_raw_buffer_load_b64(rj, 4u * wzm, 8u * NW, 0);
+        jn0[4] = jzm.x;
+        jn0[5] = jz.x;
+        jn1[4] = jzm.y;
+        jn1[5] = jz.y;
+      }
+    }
+    const uint32_t S0 = nib_unsat<D, EA>(c.x, lw, c.y, nb0, jn0);
+    const uint32_t S1 = nib_unsat<D, EA>(c.y, c.x, rw, nb1, jn1);
+    uint32_t r0[4], r1[4];
+    philox_lane(w, U, K, r0);
+    philox_lane(w + 1u, U, K, r1);
+    *reinterpret_cast<uint2*>(sp + w) =
+        make_uint2(c.x ^ nib_flips<NEVER>(S0, p, r0, bound, nev), c.y ^ nib_flips<NEVER>(S1, p, r1, bound, nev));
+    if (YFIX) {
+      z += g.dz;
+      p ^= pstep;
+    } else {
+      y += g.dy;
+      z += g.dz;
+      if (y >= L) {
+        y -= L;
+        z += 1;
+      }
+      p = (colour + y + z) & 1u;
+    }
+  }
+}
+
 // n sweeps of lattice B (uniform parameters) in LDS, NEVER: the table has
 // classes with T == 0.
 template <int D, bool EA, int NT, bool NEVER>
@@ -226,6 +313,9 @@ __device__ __forceinline__ void batch_sweeps(const BatchLattice& B, const BatchC
   g.PS = g.L * g.LG;                               // words per plane (3D)
   const uint32_t tid = threadIdx.x;
   g.RI = NT / g.LG;                                // rows per iteration (>= 1: L <= 8192)
+  // rows of a fixed y per thread (a multiple of L rows per iteration) when that keeps at least 4/5
+  // of the threads busy (L = 48 at 1024 threads: 144 of 170 rows, L = 24 at 256: 72 of 85)
+  if (g.RI > g.L && g.RI % g.L != 0 && 5u * (g.RI - g.RI % g.L) >= 4u * g.RI) g.RI -= g.RI % g.L;
   const bool active = tid < g.RI * g.LG;           // active threads
   g.xg = tid % g.LG;
   g.r_first = tid / g.LG;
@@ -236,6 +326,22 @@ __device__ __forceinline__ void batch_sweeps(const BatchLattice& B, const BatchC
   g.ym_wrap = (g.L - 1) * g.LG;
   g.zm_wrap = (g.L - 1) * g.PS;
   const bool yfix = g.dy == 0;
+  // rows of an even number of words: pairs of words per thread (batch_colour2)
+  const bool pair = (g.LG & 1u) == 0;
+  BatchGeo g2 = g;
+  if (pair) {
+    const uint32_t PG = g.LG / 2;                  // pairs per row
+    g2.RI = NT / PG;
+    if (g2.RI > g.L && g2.RI % g.L != 0 && 5u * (g2.RI - g2.RI % g.L) >= 4u * g2.RI) g2.RI -= g2.RI % g.L;
+    g2.xg = tid % PG;
+    g2.r_first = tid / PG;
+    g2.dz = g2.RI / g.L;
+    g2.dy = g2.RI % g.L;
+    g2.wl = g2.xg ? 0u - 1u : g.LG - 1u;            // word left of the pair's first word
+    g2.wr = (g2.xg + 1 < PG) ? 2u : 2u - g.LG;      // word right of its second word
+  }
+  const bool active2 = pair && tid < g2.RI * (g.LG / 2);
+  const bool yfix2 = g2.dy == 0;
   // couplings by buffer loads: one descriptor over the d arrays of NW words, byte offsets per lane
   const __amdgpu_buffer_rsrc_t rj =
       __builtin_amdgcn_make_buffer_rsrc((void*)B.Jn, 0, (int)(4u * D * g.NW), 0x00020000);
@@ -246,7 +352,14 @@ __device__ __forceinline__ void batch_sweeps(const BatchLattice& B, const BatchC
 #pragma unroll 1
     for (uint32_t colour = 0; colour < 2; ++colour) {
       const PhiloxUniform U = philox_uniform(t, B.replica, colour, B.keys);
-      if (active) {
+      if (pair) {
+        if (active2) {
+          if (yfix2)
+            batch_colour2<D, EA, NEVER, true>(sp, bound, rj, g2, U, B.keys, colour, nev);
+          else
+            batch_colour2<D, EA, NEVER, false>(sp, bound, rj, g2, U, B.keys, colour, nev);
+        }
+      } else if (active) {
         if (yfix)
           batch_colour<D, EA, NEVER, true>(sp, bound, rj, g, U, B.keys, colour, nev);
         else
