@@ -80,8 +80,10 @@ __device__ __forceinline__ void sg_fetch(const int8_t* __restrict__ src, uint32_
   }
 }
 
-// Store fetched words into ring slot `slot` as nibble words, with the pads.
-template <int NT>
+// Store fetched words into ring slot `slot` as nibble words, with the pads:
+// word g of a slice row at OFF + g, word GPR-1 again at OFF - 1 and word 0 at
+// OFF + GPR (OFF = 1; 2 in the word-pair form, so that pairs are 8-byte aligned).
+template <int NT, uint32_t OFF>
 __device__ __forceinline__ void sg_store(uint32_t* slot, const StreamArgs& a, uint32_t tot, uint32_t RW,
                                          const uint2 (&v)[kFetch]) {
   const uint32_t GPR = a.GPR;
@@ -92,9 +94,9 @@ __device__ __forceinline__ void sg_store(uint32_t* slot, const StreamArgs& a, ui
     if (threadIdx.x + NT * q < tot) {
       const uint32_t x = pack_nibbles(v[q].x, v[q].y);
       uint32_t* row = slot + r * RW;
-      row[1 + g] = x;
-      if (g == 0) row[GPR + 1] = x;
-      if (g == GPR - 1) row[0] = x;
+      row[OFF + g] = x;
+      if (g == 0) row[OFF + GPR] = x;
+      if (g == GPR - 1) row[OFF - 1] = x;
     }
     g += dg;
     r += dr;
@@ -218,14 +220,157 @@ __device__ __forceinline__ void sg_units(const uint32_t* pm, uint32_t* pc, const
   }
 }
 
-template <int D, bool EA, bool NEVER, int NT>
+// Word-pair form (GPR even): thread units are pairs of adjacent words
+// (g, g+1), g even.  A pair reads each neighbour row with one 8-byte LDS
+// access and each coupling direction and side with one 8-byte load (3
+// coupling loads per word instead of 6); the x neighbours and the x bond
+// between the two words come from the pair itself; colour 1 stores the two
+// finished words as one 16-byte store.
+typedef uint32_t sg_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint2 ldg_pair(gu32* base, uint32_t i) {  // words i, i+1 (i even)
+  const sg_u2 v = *reinterpret_cast<const __attribute__((address_space(1))) sg_u2*>(
+      reinterpret_cast<gc8*>(base) + (uint64_t)(i << 2));
+  return make_uint2(v.x, v.y);
+}
+
+// Couplings of the pair at words w, w+1: x at the pair and the word left of
+// it, y at the pair and the row below, z at the pair and the plane below.
+template <int D>
+__device__ __forceinline__ void sg_jload2(gu32* Jn, uint32_t NW, uint32_t w, uint32_t g, uint32_t y, uint32_t z,
+                                          const StreamArgs& a, uint32_t (&j)[4 * D + 1]) {
+  const uint32_t GPR = a.GPR, L = a.L;
+  const uint32_t wl = g ? w - 1u : w + GPR - 1u;
+  j[0] = ldg_word(Jn, wl);
+  const uint2 jx = ldg_pair(Jn, w);
+  j[1] = jx.x;
+  j[2] = jx.y;
+  const uint32_t wym = (D == 3) ? (y ? w - GPR : w + (L - 1u) * GPR) : (z ? w - GPR : w + (L - 1u) * GPR);
+  const uint2 jym = ldg_pair(Jn, NW + wym), jy = ldg_pair(Jn, NW + w);
+  j[3] = jym.x;
+  j[4] = jym.y;
+  j[5] = jy.x;
+  j[6] = jy.y;
+  if (D == 3) {
+    const uint32_t wzm = z ? w - L * GPR : w + (L - 1u) * L * GPR;
+    const uint2 jzm = ldg_pair(Jn, 2 * NW + wzm), jz = ldg_pair(Jn, 2 * NW + w);
+    j[7] = jzm.x;
+    j[8] = jzm.y;
+    j[9] = jz.x;
+    j[10] = jz.y;
+  }
+}
+
+// Update the colour-C nibbles of the pair at word g (even) of slice row r;
+// returns the two new words.
+template <int D, bool EA, bool NEVER, uint32_t C>
+__device__ __forceinline__ uint2 sg_unit2(const uint32_t* pm, const uint32_t* pc, const uint32_t* pp, uint32_t r,
+                                          uint32_t g, uint32_t y, uint32_t z, uint32_t w, const StreamArgs& a,
+                                          const PhiloxUniform& U, const uint32_t* bound, uint32_t RW,
+                                          const uint32_t (&jr)[4 * D + 1]) {
+  const uint32_t o = r * RW + 2 + g;
+  const uint2 c = *reinterpret_cast<const uint2*>(pc + o);
+  const uint32_t lw = pc[o - 1], rw = pc[o + 2];
+  uint2 nbp[2 * D - 2];
+  if (D == 3) {
+    nbp[0] = *reinterpret_cast<const uint2*>(pc + o - RW);
+    nbp[1] = *reinterpret_cast<const uint2*>(pc + o + RW);
+    nbp[2] = *reinterpret_cast<const uint2*>(pm + o);
+    nbp[3] = *reinterpret_cast<const uint2*>(pp + o);
+  } else {
+    nbp[0] = *reinterpret_cast<const uint2*>(pm + o);
+    nbp[1] = *reinterpret_cast<const uint2*>(pp + o);
+  }
+  uint32_t nb0[2 * D - 2], nb1[2 * D - 2], jn0[2 * D], jn1[2 * D];
+#pragma unroll
+  for (int k = 0; k < 2 * D - 2; ++k) {
+    nb0[k] = nbp[k].x;
+    nb1[k] = nbp[k].y;
+  }
+  if (EA) {
+    jn0[0] = __builtin_amdgcn_alignbit(jr[1], jr[0], 28);  // bond (x-1, x) of each site
+    jn0[1] = jr[1];
+    jn1[0] = __builtin_amdgcn_alignbit(jr[2], jr[1], 28);
+    jn1[1] = jr[2];
+    jn0[2] = jr[3];
+    jn1[2] = jr[4];
+    jn0[3] = jr[5];
+    jn1[3] = jr[6];
+    if (D == 3) {
+      jn0[4] = jr[7];
+      jn1[4] = jr[8];
+      jn0[5] = jr[9];
+      jn1[5] = jr[10];
+    }
+  }
+  const uint32_t S0 = nib_unsat<D, EA>(c.x, lw, c.y, nb0, jn0);
+  const uint32_t S1 = nib_unsat<D, EA>(c.y, c.x, rw, nb1, jn1);
+  uint32_t r0[4], r1[4];
+  philox_lane(w, U, a.keys, r0);
+  philox_lane(w + 1u, U, a.keys, r1);
+  const uint32_t p = (C + y + z) & 1u;
+  return make_uint2(c.x ^ nib_flips<NEVER>(S0, p, r0, bound, a.never4),
+                    c.y ^ nib_flips<NEVER>(S1, p, r1, bound, a.never4));
+}
+
+// The colour-C pairs of one step: slice rows RB0 + u / (GPR/2), pairs
+// u % (GPR/2), u = thread + NT*q < n (pairs).  As sg_units.
+template <int D, bool EA, bool NEVER, int NT, uint32_t C>
+__device__ __forceinline__ void sg_units2(const uint32_t* pm, uint32_t* pc, const uint32_t* pp, uint32_t n,
+                                          uint32_t y0, uint32_t z, const StreamArgs& a, const PhiloxUniform& U,
+                                          const uint32_t* bound, uint32_t RW, gu32* Jn, uint32_t NW,
+                                          int8_t* __restrict__ dst) {
+  const uint32_t GPR = a.GPR, L = a.L, PG = GPR / 2;
+  constexpr uint32_t RB0 = (D == 3) ? (C == 0 ? 1u : 2u) : 0u;  // first slice row
+  const uint32_t dr = NT / PG, dg = NT - dr * PG;
+  uint32_t r = threadIdx.x / PG, q = threadIdx.x - r * PG;
+  auto ycoord = [&](uint32_t rr) -> uint32_t {
+    if (D != 3) return 0u;
+    return C == 0 ? wrap_sub2(y0 + rr, L) : y0 + rr - 2u;
+  };
+  auto word = [&](uint32_t y, uint32_t gg) -> uint32_t { return (D == 3) ? (z * L + y) * GPR + gg : z * GPR + gg; };
+  uint32_t jc[4 * D + 1] = {}, jx[4 * D + 1] = {};
+  if (EA && threadIdx.x < n) sg_jload2<D>(Jn, NW, word(ycoord(r + RB0), 2 * q), 2 * q, ycoord(r + RB0), z, a, jc);
+  for (uint32_t u = threadIdx.x; u < n; u += NT) {
+    const uint32_t rr = r + RB0, g = 2 * q;
+    const uint32_t y = ycoord(rr);
+    const uint32_t w = word(y, g);
+    uint32_t rn = r + dr, qn = q + dg;
+    if (qn >= PG) {
+      qn -= PG;
+      rn += 1;
+    }
+    if (EA && u + NT < n) sg_jload2<D>(Jn, NW, word(ycoord(rn + RB0), 2 * qn), 2 * qn, ycoord(rn + RB0), z, a, jx);
+    const uint2 v = sg_unit2<D, EA, NEVER, C>(pm, pc, pp, rr, g, y, z, w, a, U, bound, RW, jc);
+    if (C == 0) {
+      uint32_t* row = pc + rr * RW;
+      *reinterpret_cast<uint2*>(row + 2 + g) = v;
+      if (g == 0) row[2 + GPR] = v.x;
+      if (g + 2 == GPR) row[1] = v.y;
+    } else {
+      uint4 b;
+      unpack_nibbles(v.x, b.x, b.y);
+      unpack_nibbles(v.y, b.z, b.w);
+      reinterpret_cast<uint4*>(dst)[w >> 1] = b;
+    }
+    if (EA) {
+#pragma unroll
+      for (int k = 0; k < 4 * D + 1; ++k) jc[k] = jx[k];
+    }
+    r = rn;
+    q = qn;
+  }
+}
+
+template <int D, bool EA, bool NEVER, int NT, bool PAIR>
 __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, int8_t* __restrict__ dst,
                                                 const uint32_t* __restrict__ Jraw, StreamArgs a) {
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* bound = lds;  // first: constant-offset lookups
   uint32_t* ring = lds + 8;
   const uint32_t L = a.L, GPR = a.GPR;
-  const uint32_t RW = GPR + 2;
+  constexpr uint32_t OFF = PAIR ? 2u : 1u;  // index of word 0 in a slice row
+  const uint32_t RW = GPR + 2 * OFF;
   const uint32_t TY = (D == 3) ? a.TY : 1u;
   const uint32_t RP = (D == 3) ? TY + 4 : 1u;
   const uint32_t SB = RP * RW;
@@ -241,12 +386,12 @@ __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, 
   uint2 nxt[kFetch];
   for (uint32_t k = 0; k < 3; ++k) {
     sg_fetch<D, NT>(src, wrap_sub2(z0 + k, L), y0, a, tot, nxt);
-    sg_store<NT>(ring + k * SB, a, tot, RW, nxt);
+    sg_store<NT, OFF>(ring + k * SB, a, tot, RW, nxt);
   }
   __syncthreads();
   // units: colour 0 on slice rows 1..TY+2 (3D) / row 0 (2D); colour 1 on rows 2..TY+1 / row 0
-  const uint32_t U0n = (D == 3) ? (TY + 2) * GPR : GPR;
-  const uint32_t U1n = (D == 3) ? TY * GPR : GPR;
+  const uint32_t U0n = ((D == 3) ? (TY + 2) * GPR : GPR) / (PAIR ? 2u : 1u);
+  const uint32_t U1n = ((D == 3) ? TY * GPR : GPR) / (PAIR ? 2u : 1u);
   uint32_t sa = 1;  // slot of plane a = z0 - 1 + i
   for (uint32_t i = 0; i < H + 3; ++i) {
     const uint32_t s_m3 = sa >= 3 ? sa - 3 : sa + 3;   // a-3
@@ -256,13 +401,22 @@ __global__ __launch_bounds__(NT) void k_streamg(const int8_t* __restrict__ src, 
     const uint32_t s_p2 = sa <= 3 ? sa + 2 : sa - 4;   // a+2
     // plane a+2: loads issued now, stored after the compute of this step
     if (i <= H) sg_fetch<D, NT>(src, wrap_sub2(z0 + i + 3, L), y0, a, tot, nxt);
-    if (i <= H + 1)
-      sg_units<D, EA, NEVER, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0,
-                                    wrap_sub2(z0 + i + 1, L), a, U0, bound, RW, Jn, NW, dst);
-    if (i >= 3)
-      sg_units<D, EA, NEVER, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u, a,
-                                    U1, bound, RW, Jn, NW, dst);
-    if (i <= H) sg_store<NT>(ring + s_p2 * SB, a, tot, RW, nxt);
+    if (PAIR) {
+      if (i <= H + 1)
+        sg_units2<D, EA, NEVER, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0,
+                                       wrap_sub2(z0 + i + 1, L), a, U0, bound, RW, Jn, NW, dst);
+      if (i >= 3)
+        sg_units2<D, EA, NEVER, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u,
+                                       a, U1, bound, RW, Jn, NW, dst);
+    } else {
+      if (i <= H + 1)
+        sg_units<D, EA, NEVER, NT, 0>(ring + s_m1 * SB, ring + sa * SB, ring + s_p1 * SB, U0n, y0,
+                                      wrap_sub2(z0 + i + 1, L), a, U0, bound, RW, Jn, NW, dst);
+      if (i >= 3)
+        sg_units<D, EA, NEVER, NT, 1>(ring + s_m3 * SB, ring + s_m2 * SB, ring + s_m1 * SB, U1n, y0, z0 + i - 3u, a,
+                                      U1, bound, RW, Jn, NW, dst);
+    }
+    if (i <= H) sg_store<NT, OFF>(ring + s_p2 * SB, a, tot, RW, nxt);
     __syncthreads();
     sa = sa == 5 ? 0 : sa + 1;
   }
@@ -286,29 +440,41 @@ bool streamg_supported(const Lat& lat, const Tile& tile) {
 }
 
 size_t streamg_lds_bytes(const Lat& lat, const Tile& tile) {
-  const size_t RW = lat.L / 8 + 2;
+  const size_t RW = lat.L / 8 + (lat.L % 16 == 0 ? 4 : 2);  // the word-pair form's rows have two pads more
   const size_t RP = lat.d == 3 ? (size_t)tile.y + 4 : 1;
   return 32 + 6 * RP * RW * 4;
 }
 
-template <int D, bool EA, int NT>
-static hipError_t go_streamg(dim3 grid, size_t lds, bool never, const int8_t* src, int8_t* dst, const uint32_t* Jn,
-                             const StreamArgs& a, hipStream_t stream) {
+template <int D, bool EA, int NT, bool PAIR>
+static hipError_t go_streamg_p(dim3 grid, size_t lds, bool never, const int8_t* src, int8_t* dst, const uint32_t* Jn,
+                               const StreamArgs& a, hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_streamg<D, EA, true, NT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_streamg<D, EA, true, NT, PAIR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_streamg<D, EA, false, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              150 * 1024);
+      e = hipFuncSetAttribute((const void*)k_streamg<D, EA, false, NT, PAIR>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
   if (never)
-    hipLaunchKernelGGL((k_streamg<D, EA, true, NT>), grid, dim3(NT), lds, stream, src, dst, Jn, a);
+    hipLaunchKernelGGL((k_streamg<D, EA, true, NT, PAIR>), grid, dim3(NT), lds, stream, src, dst, Jn, a);
   else
-    hipLaunchKernelGGL((k_streamg<D, EA, false, NT>), grid, dim3(NT), lds, stream, src, dst, Jn, a);
+    hipLaunchKernelGGL((k_streamg<D, EA, false, NT, PAIR>), grid, dim3(NT), lds, stream, src, dst, Jn, a);
   return hipGetLastError();
+}
+
+// Rows of an even number of words (L % 16 == 0) run the word-pair form when
+// its units still cover every thread (colour-1 pairs of a step >= threads);
+// measured: 3D +-J L = 512 567 -> 647 attempts/ns, while with fewer pairs than
+// threads (2D rows, 3D L <= 256) the halved parallelism lost up to 18 %.
+template <int D, bool EA, int NT>
+static hipError_t go_streamg(dim3 grid, size_t lds, bool never, const int8_t* src, int8_t* dst, const uint32_t* Jn,
+                             const StreamArgs& a, hipStream_t stream) {
+  if (a.GPR % 2 == 0 && a.TY * (a.GPR / 2) >= (uint32_t)NT)
+    return go_streamg_p<D, EA, NT, true>(grid, lds, never, src, dst, Jn, a, stream);
+  return go_streamg_p<D, EA, NT, false>(grid, lds, never, src, dst, Jn, a, stream);
 }
 
 hipError_t launch_streamg(const Lat& lat, const uint32_t* Jn, const int8_t* src, int8_t* dst, uint32_t t,

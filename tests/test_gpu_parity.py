@@ -155,6 +155,8 @@ def test_ising3d_all_kernels(oracle_mod, kernel, tile, L):
     (RES, (0, 0, 0, 0), 64, 3), (RES, (0, 0, 0, 512), 40, 2),
     (STR, (0, 1, 8, 256), 64, 2), (STR, (0, 1, 6, 512), 1000, 2), (STR, (0, 8, 16, 256), 48, 3),
     (STR, (0, 16, 16, 512), 96, 3), (STR, (0, 8, 5, 256), 16, 3), (STR, (0, 0, 0, 0), 136, 3),
+    # the streaming kernel's word-pair form (rows of an even number of words, pairs >= threads)
+    (STR, (0, 32, 8, 256), 128, 3), (STR, (0, 1, 8, 256), 4096, 2),
 ])
 def test_ea_all_kernels(oracle_mod, kernel, tile, L, d):
     sched = [(3, b, 1) for b in [0.5, 1.2, 0.0, math.inf, 3.0]]
