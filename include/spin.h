@@ -482,7 +482,7 @@ uint64_t spin_msc_sweeps_done(const spin_msc* h);
  * one launch streamed over planes, with rows (3D: rows per workgroup,
  * dividing L, <= 32), planes (per strip), threads (256 or 512) and width
  * (sites of a row per workgroup: a multiple of 8 dividing L), 0 meaning the
- * default (8, 16, 512, L); streaming == 2 (3D, L = 512 only) is the
+ * default (8, 16, 512, L); streaming == 2 (3D, L = 128, 256 or 512) is the
  * register-column kernel, which reads every coupling word once per sweep:
  * rows 4 or 8 (default 8), planes even and dividing L (default 32), threads
  * 0 or 64 * (rows + 2), width 0 or L; streaming == 0 launches one kernel per

@@ -35,9 +35,10 @@ hipError_t launch_msc_phase(uint32_t* S, const uint32_t* J6, const MscArgs& a, u
 bool msc_stream_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW);
 hipError_t launch_msc_stream(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
                              uint32_t TY, uint32_t H, uint32_t NT, uint32_t XW, hipStream_t stream);
-// 3D L = 512 only: one sweep per launch with each row's z column in registers
-// and every coupling word read once (ping-pong src -> dst): TY = 4 or 8 rows
-// per workgroup (TY + 2 wavefronts), H planes per strip (even, dividing L).
+// 3D L = 128, 256 or 512: one sweep per launch with each row's z column in
+// registers and every coupling word read once (ping-pong src -> dst): TY = 4
+// or 8 rows per workgroup (TY + 2 wavefronts), H planes per strip (even,
+// dividing L).
 bool msc_col_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H);
 hipError_t launch_msc_col(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
                           uint32_t TY, uint32_t H, hipStream_t stream);

@@ -538,10 +538,6 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 namespace col {
 
-constexpr uint32_t L = 512;
-constexpr uint32_t RW = L;       // words per LDS row
-constexpr uint32_t HW = L / 2;   // words per parity half
-
 struct G8 {  // one group, natural site order: words 0-3 in lo, 4-7 in hi
   v4u lo, hi;
 };
@@ -561,10 +557,11 @@ __device__ __forceinline__ G8 ld_group(__amdgpu_buffer_rsrc_t r, uint32_t row, u
   return g;
 }
 
+template <uint32_t L>
 __device__ __forceinline__ H8 ld_split(__amdgpu_buffer_rsrc_t r, uint32_t row, uint32_t lane) {
   H8 g;
   g.h[0] = __builtin_amdgcn_raw_buffer_load_b128(r, 16u * lane, row, 0);
-  g.h[1] = __builtin_amdgcn_raw_buffer_load_b128(r, 4u * HW + 16u * lane, row, 0);
+  g.h[1] = __builtin_amdgcn_raw_buffer_load_b128(r, 2u * L + 16u * lane, row, 0);  // the odd-x half
   return g;
 }
 
@@ -640,11 +637,13 @@ struct Regs {
   uint32_t sA, sB, sN;  // LDS slots of planes a, b, a+1
 };
 
+template <uint32_t L>
 __device__ __forceinline__ uint32_t row_off(uint32_t z, uint32_t y) { return (z * L + y) * L * 4u; }
 
-template <int TY, int ROLE, uint32_t Q, bool C1>
+template <uint32_t L, int TY, int ROLE, uint32_t Q, bool C1>
 __device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
   using RL = Role<ROLE>;
+  constexpr uint32_t RW = L, HW = L / 2, GPR = L / 8;  // words per LDS row and parity half, groups per row
   constexpr uint32_t SS = (TY + 4) * RW, JS = (TY + 3) * RW;  // words per spin / y-bond slice
   constexpr uint32_t P = (RL::RP + Q + 1u) & 1u;
   const uint32_t lane = c.lane, r = c.r, y = c.y;
@@ -673,18 +672,18 @@ __device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
     }
   }
   // loads for the next step
-  R.s2 = ld_group(c.src, row_off(zs, y), lane);
-  R.jy1 = ld_split(c.jy, row_off(zs, y), lane);
-  R.jxn = ld_group(c.jx, row_off(zx, y), lane);
-  R.jzn = ld_split(c.jz, row_off(zx, y), lane);
-  if (ROLE == TOP || ROLE == BOT) R.hs = ld_group(c.src, row_off(zs, c.yh), lane);
-  if (ROLE == JH) R.hj = ld_split(c.jy, row_off(zs, c.yh), lane);
+  R.s2 = ld_group(c.src, row_off<L>(zs, y), lane);
+  R.jy1 = ld_split<L>(c.jy, row_off<L>(zs, y), lane);
+  R.jxn = ld_group(c.jx, row_off<L>(zx, y), lane);
+  R.jzn = ld_split<L>(c.jz, row_off<L>(zx, y), lane);
+  if (ROLE == TOP || ROLE == BOT) R.hs = ld_group(c.src, row_off<L>(zs, c.yh), lane);
+  if (ROLE == JH) R.hj = ld_split<L>(c.jy, row_off<L>(zs, c.yh), lane);
   // colour 0 on plane a
   const uint32_t* sA = c.ls + R.sA * SS;
   const uint32_t* jA = c.lj + R.sA * JS;
   const uint32_t o = P * HW + 4u * lane;
   uint32_t rnd[4];
-  philox_lane((a * L + y) * 64u + lane, c.U0, *c.keys, rnd);
+  philox_lane((a * L + y) * GPR + lane, c.U0, *c.keys, rnd);
   G8 na = R.sa;
   {
     const v4u ym = *reinterpret_cast<const v4u*>(sA + (r - 1) * RW + o);
@@ -700,7 +699,7 @@ __device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
   if (C1 && RL::OWN) {
     const uint32_t* sB = c.ls + R.sB * SS;
     const uint32_t* jB = c.lj + R.sB * JS;
-    philox_lane((b * L + y) * 64u + lane, c.U1, *c.keys, rnd);
+    philox_lane((b * L + y) * GPR + lane, c.U1, *c.keys, rnd);
     const v4u ym = *reinterpret_cast<const v4u*>(sB + (r - 1) * RW + o);
     const v4u yp = *reinterpret_cast<const v4u*>(sB + (r + 1) * RW + o);
     const v4u jy = *reinterpret_cast<const v4u*>(jB + r * RW + o);
@@ -709,8 +708,8 @@ __device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
     const uint32_t jl = P == 0 ? ror1(R.jxb.hi.w) : 0u;
     G8 nbk = R.sb;
     unit<P>(nbk, nb, R.jxb, jl, ym, yp, R.sbb, half<P>(na), jym, jy, R.jzbb, R.jzb.h[P], rnd, c.thr);
-    __builtin_amdgcn_raw_buffer_store_b128(nbk.lo, c.dst, 32u * lane, row_off(b, y), 0);
-    __builtin_amdgcn_raw_buffer_store_b128(nbk.hi, c.dst, 32u * lane + 16u, row_off(b, y), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(nbk.lo, c.dst, 32u * lane, row_off<L>(b, y), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(nbk.hi, c.dst, 32u * lane + 16u, row_off<L>(b, y), 0);
   }
   // the next step's registers (its active half is 1 - P)
   R.sbb = half<P ^ 1u>(R.sb);
@@ -729,22 +728,23 @@ __device__ __forceinline__ void step(const Ctx& c, Regs& R, uint32_t i) {
   __syncthreads();
 }
 
-template <int TY, int ROLE>
+template <uint32_t L, int TY, int ROLE>
 __device__ __forceinline__ void run(const Ctx& c) {
   using RL = Role<ROLE>;
+  constexpr uint32_t RW = L, HW = L / 2;
   constexpr uint32_t SS = (TY + 4) * RW, JS = (TY + 3) * RW;
   const uint32_t lane = c.lane, r = c.r, y = c.y;
   const uint32_t zm2 = (c.z0 + L - 2u) & (L - 1u), zm1 = (c.z0 + L - 1u) & (L - 1u);
   Regs R;
   // prologue: plane z0-1 into slot 0 (spins half P(r, step -1) = r & 1, all y bonds); registers for step 0
-  R.sb = ld_group(c.src, row_off(zm2, y), lane);
-  R.sa = ld_group(c.src, row_off(zm1, y), lane);
-  R.s1 = ld_group(c.src, row_off(c.z0, y), lane);
-  R.jxa = ld_group(c.jx, row_off(zm1, y), lane);
-  R.jza = ld_split(c.jz, row_off(zm1, y), lane);
-  R.jzb = ld_split(c.jz, row_off(zm2, y), lane);
-  const H8 jy0 = ld_split(c.jy, row_off(zm1, y), lane);
-  R.jy1 = ld_split(c.jy, row_off(c.z0, y), lane);
+  R.sb = ld_group(c.src, row_off<L>(zm2, y), lane);
+  R.sa = ld_group(c.src, row_off<L>(zm1, y), lane);
+  R.s1 = ld_group(c.src, row_off<L>(c.z0, y), lane);
+  R.jxa = ld_group(c.jx, row_off<L>(zm1, y), lane);
+  R.jza = ld_split<L>(c.jz, row_off<L>(zm1, y), lane);
+  R.jzb = ld_split<L>(c.jz, row_off<L>(zm2, y), lane);
+  const H8 jy0 = ld_split<L>(c.jy, row_off<L>(zm1, y), lane);
+  R.jy1 = ld_split<L>(c.jy, row_off<L>(c.z0, y), lane);
   R.jxb = R.jxa;
   R.sbb = v4u{0u, 0u, 0u, 0u};
   R.jzbb = v4u{0u, 0u, 0u, 0u};
@@ -757,20 +757,20 @@ __device__ __forceinline__ void run(const Ctx& c) {
   *reinterpret_cast<v4u*>(c.lj + r * RW + 4u * lane) = jy0.h[0];
   *reinterpret_cast<v4u*>(c.lj + r * RW + HW + 4u * lane) = jy0.h[1];
   if (ROLE == TOP) {  // row 0: half 0
-    const G8 h = ld_group(c.src, row_off(zm1, c.yh), lane);
+    const G8 h = ld_group(c.src, row_off<L>(zm1, c.yh), lane);
     *reinterpret_cast<v4u*>(c.ls + 4u * lane) = half<0>(h);
-    R.hs = ld_group(c.src, row_off(c.z0, c.yh), lane);
+    R.hs = ld_group(c.src, row_off<L>(c.z0, c.yh), lane);
   }
   if (ROLE == BOT) {  // row TY+3: half (TY+3) & 1 = 1
-    const G8 h = ld_group(c.src, row_off(zm1, c.yh), lane);
+    const G8 h = ld_group(c.src, row_off<L>(zm1, c.yh), lane);
     *reinterpret_cast<v4u*>(c.ls + (TY + 3) * RW + HW + 4u * lane) = half<1>(h);
-    R.hs = ld_group(c.src, row_off(c.z0, c.yh), lane);
+    R.hs = ld_group(c.src, row_off<L>(c.z0, c.yh), lane);
   }
   if (ROLE == JH) {
-    const H8 h = ld_split(c.jy, row_off(zm1, c.yh), lane);
+    const H8 h = ld_split<L>(c.jy, row_off<L>(zm1, c.yh), lane);
     *reinterpret_cast<v4u*>(c.lj + 4u * lane) = h.h[0];
     *reinterpret_cast<v4u*>(c.lj + HW + 4u * lane) = h.h[1];
-    R.hj = ld_split(c.jy, row_off(c.z0, c.yh), lane);
+    R.hj = ld_split<L>(c.jy, row_off<L>(c.z0, c.yh), lane);
   }
   (void)SS;
   (void)JS;
@@ -778,17 +778,17 @@ __device__ __forceinline__ void run(const Ctx& c) {
   R.sN = 1;
   R.sB = 2;
   __syncthreads();
-  step<TY, ROLE, 0, false>(c, R, 0u);
-  step<TY, ROLE, 1, false>(c, R, 1u);
+  step<L, TY, ROLE, 0, false>(c, R, 0u);
+  step<L, TY, ROLE, 1, false>(c, R, 1u);
   for (uint32_t i0 = 2; i0 < c.H + 2u; i0 += 2) {
-    step<TY, ROLE, 0, true>(c, R, i0);
-    step<TY, ROLE, 1, true>(c, R, i0 + 1u);
+    step<L, TY, ROLE, 0, true>(c, R, i0);
+    step<L, TY, ROLE, 1, true>(c, R, i0 + 1u);
   }
 }
 
 }  // namespace col
 
-template <int TY>
+template <uint32_t L, int TY>
 __global__ __launch_bounds__(64 * (TY + 2)) void k_msc_col(const uint32_t* __restrict__ src,
                                                            uint32_t* __restrict__ dst,
                                                            const uint32_t* __restrict__ J, MscArgs a,
@@ -796,6 +796,7 @@ __global__ __launch_bounds__(64 * (TY + 2)) void k_msc_col(const uint32_t* __res
   using namespace col;
   extern __shared__ __align__(16) uint32_t lds[];
   constexpr uint32_t Nw = L * L * L;
+  constexpr uint32_t RW = L, GPR = L / 8;
   Ctx c;
   c.src = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(Nw * 4u), 0x00020000);
   c.dst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(Nw * 4u), 0x00020000);
@@ -817,48 +818,54 @@ __global__ __launch_bounds__(64 * (TY + 2)) void k_msc_col(const uint32_t* __res
   const uint32_t y0 = (tile % nslab) * TY;
   c.z0 = (tile / nslab) * H;
   c.H = H;
-  c.lane = threadIdx.x & 63u;
+  // a row has GPR <= 64 groups: with GPR < 64 the wavefront holds 64 / GPR copies of the row, lane l
+  // working on group l mod GPR; the copies load, compute and store the same values, and the
+  // wavefront rotates give every lane its periodic neighbour within the row
+  c.lane = threadIdx.x & (GPR - 1u);
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   c.r = wave + 1u;
   c.y = (y0 + L - 2u + c.r) & (L - 1u);
   c.yh = (wave == (uint32_t)TY + 1u) ? (y0 + TY + 1u) & (L - 1u) : (y0 + L - 2u) & (L - 1u);
   if (wave == 0)
-    run<TY, TOP>(c);
+    run<L, TY, TOP>(c);
   else if (wave == 1)
-    run<TY, JH>(c);
+    run<L, TY, JH>(c);
   else if (wave == (uint32_t)TY + 1u)
-    run<TY, BOT>(c);
+    run<L, TY, BOT>(c);
   else if (c.r & 1u)
-    run<TY, ODD>(c);
+    run<L, TY, ODD>(c);
   else
-    run<TY, EVEN>(c);
+    run<L, TY, EVEN>(c);
 }
 
-size_t msc_col_lds(uint32_t TY) { return (size_t)(3 * (TY + 4) + 3 * (TY + 3)) * col::RW * 4; }
+size_t msc_col_lds(uint32_t TY, uint32_t L) { return (size_t)(3 * (TY + 4) + 3 * (TY + 3)) * L * 4; }
 
 bool msc_col_supported(uint32_t L, uint32_t d, uint32_t TY, uint32_t H) {
-  return d == 3 && L == col::L && (TY == 4 || TY == 8) && H >= 2 && H % 2 == 0 && L % H == 0;
+  return d == 3 && (L == 128 || L == 256 || L == 512) && (TY == 4 || TY == 8) && H >= 2 && H % 2 == 0 &&
+         L % H == 0;
 }
 
-template <int TY>
+template <uint32_t L, int TY>
 static hipError_t go_msc_col(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t H,
                              hipStream_t stream) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_msc_col<TY>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)msc_col_lds(TY));
+    hipError_t e = hipFuncSetAttribute((const void*)k_msc_col<L, TY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)msc_col_lds(TY, L));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const dim3 grid((col::L / TY) * (col::L / H));
-  hipLaunchKernelGGL((k_msc_col<TY>), grid, dim3(64 * (TY + 2)), msc_col_lds(TY), stream, src, dst, J, a, H);
+  const dim3 grid((L / TY) * (L / H));
+  hipLaunchKernelGGL((k_msc_col<L, TY>), grid, dim3(64 * (TY + 2)), msc_col_lds(TY, L), stream, src, dst, J, a, H);
   return hipGetLastError();
 }
 
 hipError_t launch_msc_col(const uint32_t* src, uint32_t* dst, const uint32_t* J, const MscArgs& a, uint32_t d,
                           uint32_t TY, uint32_t H, hipStream_t stream) {
   if (!msc_col_supported(a.L, d, TY, H)) return hipErrorInvalidValue;
-  return TY == 8 ? go_msc_col<8>(src, dst, J, a, H, stream) : go_msc_col<4>(src, dst, J, a, H, stream);
+  if (a.L == 512) return TY == 8 ? go_msc_col<512, 8>(src, dst, J, a, H, stream) : go_msc_col<512, 4>(src, dst, J, a, H, stream);
+  if (a.L == 256) return TY == 8 ? go_msc_col<256, 8>(src, dst, J, a, H, stream) : go_msc_col<256, 4>(src, dst, J, a, H, stream);
+  return TY == 8 ? go_msc_col<128, 8>(src, dst, J, a, H, stream) : go_msc_col<128, 4>(src, dst, J, a, H, stream);
 }
 
 // E and M of the 32 systems: per workgroup, counts of unsatisfied bonds and

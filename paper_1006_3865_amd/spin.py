@@ -664,7 +664,7 @@ class Msc:
 
     @property
     def kernel(self):
-        """0: one launch per colour; 1: streamed over planes; 2: register columns (3D L = 512)."""
+        """0: one launch per colour; 1: streamed over planes; 2: register columns (3D L = 128, 256, 512)."""
         return int(load().spin_msc_kernel(self.h))
 
     def synchronize(self):

@@ -93,14 +93,16 @@ def boundary_sites(L, rows, planes):
     return np.array([(z * L + y) * L + x for z in zs for y in ys for x in xs], dtype=np.int64)
 
 
-@pytest.mark.parametrize("kernel", [None, (1, 8, 128, 512), (2, 8, 32), (2, 4, 16), (2, 8, 512)])
-def test_msc_full_size_sampled_sites(oracle_mod, kernel):
+@pytest.mark.parametrize("L,kernel", [(512, None), (512, (1, 8, 128, 512)), (512, (2, 8, 32)), (512, (2, 4, 16)),
+                                      (512, (2, 8, 512)), (256, (2, 4, 64)), (256, (2, 8, 256)),
+                                      (128, (2, 4, 32))])
+def test_msc_full_size_sampled_sites(oracle_mod, L, kernel):
     """The 3D L = 512 handle: the launch shape the benchmark times (the default, register columns), the
     plane-streaming kernel and other register-column shapes; one sweep checked site by site on a sample that includes every tile edge.  A
     colour-0 site is decided from the state before the sweep (its neighbours are colour 1), a colour-1
     site from its old value and the final colour-0 neighbours; each decision is the oracle's rule
     (Eq. 2) with the shared Philox word of the site."""
-    L, d = 512, 3
+    d = 3
     N = L ** d
     cs, seed, r0, p0 = workloads.seed(0x11), workloads.seed(0x10), 0, 0
     beta = workloads.ea_betas()[7]
@@ -148,19 +150,21 @@ def test_msc_full_size_sampled_sites(oracle_mod, kernel):
             assert int(new[s]) == expect, ("system", b, "site", s, "colour", c)
 
 
-@pytest.mark.parametrize("shape", [(8, 32), (4, 64), (8, 2)])
-def test_msc_column_kernel_equals_streaming_kernel(shape):
-    """The register-column kernel (3D L = 512) against the plane-streaming kernel, whose chain is the
-    oracle's at every size it was compared on: all 32 systems' spins (as the words of every site) and
-    the 32 energies and magnetisations after every sweep, over sweeps at several temperatures."""
+@pytest.mark.parametrize("L,shape", [(512, (8, 32)), (512, (4, 64)), (512, (8, 2)), (256, (4, 64)), (256, (8, 16)),
+                                     (128, (4, 32)), (128, (8, 128))])
+def test_msc_column_kernel_equals_streaming_kernel(L, shape):
+    """The register-column kernel (3D L = 512, 256, 128; below 512 a wavefront holds several copies of
+    a row) against the plane-streaming kernel, whose chain is the oracle's at every size it was
+    compared on: all 32 systems' spins (as the words of every site) and the 32 energies and
+    magnetisations after every sweep, over sweeps at several temperatures."""
     import torch
-    L, d = 512, 3
+    d = 3
     cs, seed, r0, p0 = workloads.seed(0x64), workloads.seed(0x65), 3, 11
     note("msc column vs stream", shape)
     a = spin.Msc(L, d, cs, r0, seed, p0)
     b = spin.Msc(L, d, cs, r0, seed, p0)
     a.set_kernel(2, shape[0], shape[1])
-    b.set_kernel(1, 8, 64, 512)
+    b.set_kernel(1, 8, 16, 512 if L >= 256 else 256)
     for beta in (workloads.ea_betas()[3], math.inf, 0.0, 3.0):
         Ea, Ma = a.sweep_record(2, beta, 1)
         Eb, Mb = b.sweep_record(2, beta, 1)
@@ -181,7 +185,7 @@ def test_msc_column_kernel_shapes():
     m.set_kernel(2, 8, 32, 640)
     m.set_kernel(2, 4, 2)
     m.close()
-    s = spin.Msc(256, 3, 1, 0, 1)
+    s = spin.Msc(64, 3, 1, 0, 1)     # the register-column kernel takes L = 128, 256 and 512
     with pytest.raises(spin.SpinError):
         s.set_kernel(2, 8, 32)
     s.close()
