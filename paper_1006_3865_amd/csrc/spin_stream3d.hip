@@ -256,9 +256,10 @@ __global__ __launch_bounds__(64 * W) void k_stream3d(const int8_t* __restrict__ 
 // the site flipped -- and M from the owned sites' final bytes.
 typedef uint32_t u32x2r __attribute__((ext_vector_type(2)));
 
-template <int TY>
+template <uint32_t LL, int TY>
 struct Col3Ctx {
-  static constexpr uint32_t L = 512;
+  static constexpr uint32_t L = LL;
+  static constexpr uint32_t GPR = LL / 8;        // groups per row (<= 64)
   static constexpr uint32_t RP = TY + 4;         // rows of a slice
   static constexpr uint32_t PB = RP * L;         // bytes of a slice
   static constexpr int W = TY / 2 + 1;
@@ -268,6 +269,7 @@ struct Col3Ctx {
   const RoundKeys* keys;
   PhiloxUniform U0, U1;
   uint32_t never4, y0, z0, H, lane, wave;
+  uint32_t cnt;       // 1 on the first copy of a row in the wavefront (the one that counts E/M), else 0
   uint32_t yrow[2];   // y of the wave's two rows
   uint32_t yhalo;     // y of the halo row the edge wave loads
 };
@@ -315,9 +317,9 @@ struct Col3Regs {
   uint32_t sA, sB, sN;  // ring slots of planes a, a-1, a+1
 };
 
-template <int TY>
-__device__ __forceinline__ uint2 col3_load(const Col3Ctx<TY>& c, uint32_t z, uint32_t y) {
-  constexpr uint32_t L = Col3Ctx<TY>::L;
+template <uint32_t LL, int TY>
+__device__ __forceinline__ uint2 col3_load(const Col3Ctx<LL, TY>& c, uint32_t z, uint32_t y) {
+  constexpr uint32_t L = Col3Ctx<LL, TY>::L;
   const u32x2r v = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * c.lane, (z * L + y) * L, 0);
   return make_uint2(v.x, v.y);
 }
@@ -325,11 +327,11 @@ __device__ __forceinline__ uint2 col3_load(const Col3Ctx<TY>& c, uint32_t z, uin
 // Step i of the pipeline (Q = i & 1; C1: colour 1 runs, i.e. i >= 2).  Row j
 // of the wave has y parity (1 + j) & 1 and plane a = z0-1+i parity (i+1) & 1
 // (z0 is even), so the active parity of row j is (Q + j) & 1 in both colours.
-template <int TY, int EDGE, bool NEVER, bool MEAS, uint32_t Q, bool C1>
-__device__ __forceinline__ void col3_step(const Col3Ctx<TY>& c, Col3Regs& R, uint32_t i, int8_t* base,
+template <uint32_t LL, int TY, int EDGE, bool NEVER, bool MEAS, uint32_t Q, bool C1>
+__device__ __forceinline__ void col3_step(const Col3Ctx<LL, TY>& c, Col3Regs& R, uint32_t i, int8_t* base,
                                           uint32_t& unsat4, uint32_t& neg) {
-  using X = Col3Ctx<TY>;
-  constexpr uint32_t L = X::L, PB = X::PB;
+  using X = Col3Ctx<LL, TY>;
+  constexpr uint32_t L = X::L, PB = X::PB, GPR = X::GPR;
   constexpr bool OWN0 = EDGE != 1, OWN1 = EDGE != 2;  // row j is owned (not the ring)
   constexpr uint32_t P0 = Q, P1 = Q ^ 1u;             // active parity of rows 0 and 1
   // load plane a+2 (the last step reloads plane z0+H+1, which nothing reads, so that the load is
@@ -348,9 +350,9 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<TY>& c, Col3Regs& R, uin
   const uint2 up0 = *reinterpret_cast<const uint2*>(pA);
   const uint2 dn1 = *reinterpret_cast<const uint2*>(pA + 3 * L);
   uint2 ya0[2];
-  ya0[0] = col3_unit<P0, NEVER, false>(R.xa[0], up0, R.xa[1], R.ya1[0], R.xa1[0], (a * L + c.yrow[0]) * 64u + c.lane,
+  ya0[0] = col3_unit<P0, NEVER, false>(R.xa[0], up0, R.xa[1], R.ya1[0], R.xa1[0], (a * L + c.yrow[0]) * GPR + c.lane,
                                        c.U0, *c.keys, c.bound, c.never4, none);
-  ya0[1] = col3_unit<P1, NEVER, false>(R.xa[1], R.xa[0], dn1, R.ya1[1], R.xa1[1], (a * L + c.yrow[1]) * 64u + c.lane,
+  ya0[1] = col3_unit<P1, NEVER, false>(R.xa[1], R.xa[0], dn1, R.ya1[1], R.xa1[1], (a * L + c.yrow[1]) * GPR + c.lane,
                                        c.U0, *c.keys, c.bound, c.never4, none);
   *reinterpret_cast<uint2*>(pA + L) = ya0[0];
   *reinterpret_cast<uint2*>(pA + 2 * L) = ya0[1];
@@ -363,14 +365,15 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<TY>& c, Col3Regs& R, uin
     uint32_t add = 0;
     if (OWN0)
       fin[0] = col3_unit<P0, NEVER, MEAS>(R.ya1[0], upB, R.ya1[1], R.ya2[0], ya0[0],
-                                          (b * L + c.yrow[0]) * 64u + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+                                          (b * L + c.yrow[0]) * GPR + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
     if (OWN1)
       fin[1] = col3_unit<P1, NEVER, MEAS>(R.ya1[1], R.ya1[0], dnB, R.ya2[1], ya0[1],
-                                          (b * L + c.yrow[1]) * 64u + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+                                          (b * L + c.yrow[1]) * GPR + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
     if (MEAS) {
-      unsat4 += add;
-      if (OWN0) neg += __popc(fin[0].x & 0x80808080u) + __popc(fin[0].y & 0x80808080u);
-      if (OWN1) neg += __popc(fin[1].x & 0x80808080u) + __popc(fin[1].y & 0x80808080u);
+      // only the first copy of the row in the wavefront counts
+      unsat4 += c.cnt * add;
+      if (OWN0) neg += c.cnt * (__popc(fin[0].x & 0x80808080u) + __popc(fin[0].y & 0x80808080u));
+      if (OWN1) neg += c.cnt * (__popc(fin[1].x & 0x80808080u) + __popc(fin[1].y & 0x80808080u));
     }
   }
   // plane a+1 as loaded, for colour 0 of the next step
@@ -403,9 +406,9 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<TY>& c, Col3Regs& R, uin
   __syncthreads();
 }
 
-template <int TY, int EDGE, bool NEVER, bool MEAS>
-__device__ __forceinline__ void col3_run(const Col3Ctx<TY>& c, uint32_t& unsat4, uint32_t& neg) {
-  using X = Col3Ctx<TY>;
+template <uint32_t LL, int TY, int EDGE, bool NEVER, bool MEAS>
+__device__ __forceinline__ void col3_run(const Col3Ctx<LL, TY>& c, uint32_t& unsat4, uint32_t& neg) {
+  using X = Col3Ctx<LL, TY>;
   constexpr uint32_t L = X::L;
   // LDS address of (slot 0, row 2w, this lane's group); rows 2w .. 2w+3 of a slot sit at +0 .. +3L
   int8_t* base = c.ring + 2u * c.wave * L + 8u * c.lane;
@@ -434,20 +437,20 @@ __device__ __forceinline__ void col3_run(const Col3Ctx<TY>& c, uint32_t& unsat4,
   R.sN = 1;
   __syncthreads();
   // steps 0 and 1 (planes z0-1 and z0 for colour 0; no owned plane for colour 1 yet), then pairs
-  col3_step<TY, EDGE, NEVER, MEAS, 0, false>(c, R, 0u, base, unsat4, neg);
-  col3_step<TY, EDGE, NEVER, MEAS, 1, false>(c, R, 1u, base, unsat4, neg);
+  col3_step<LL, TY, EDGE, NEVER, MEAS, 0, false>(c, R, 0u, base, unsat4, neg);
+  col3_step<LL, TY, EDGE, NEVER, MEAS, 1, false>(c, R, 1u, base, unsat4, neg);
   const uint32_t steps = c.H + 2;
   for (uint32_t i0 = 2; i0 < steps; i0 += 2) {
-    col3_step<TY, EDGE, NEVER, MEAS, 0, true>(c, R, i0, base, unsat4, neg);
-    col3_step<TY, EDGE, NEVER, MEAS, 1, true>(c, R, i0 + 1u, base, unsat4, neg);
+    col3_step<LL, TY, EDGE, NEVER, MEAS, 0, true>(c, R, i0, base, unsat4, neg);
+    col3_step<LL, TY, EDGE, NEVER, MEAS, 1, true>(c, R, i0 + 1u, base, unsat4, neg);
   }
 }
 
-template <int TY, bool NEVER, bool MEAS>
+template <uint32_t LL, int TY, bool NEVER, bool MEAS>
 __global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __restrict__ src,
                                                                 int8_t* __restrict__ dst, PhaseArgs a,
                                                                 uint32_t H, Record rec) {
-  using X = Col3Ctx<TY>;
+  using X = Col3Ctx<LL, TY>;
   constexpr uint32_t L = X::L;
   constexpr int W = X::W;
   __shared__ __align__(16) int8_t lds[32 + 3 * X::PB];
@@ -469,7 +472,11 @@ __global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __
   c.y0 = (tile % nslab) * TY;
   c.z0 = (tile / nslab) * H;
   c.H = H;
-  c.lane = threadIdx.x & 63;
+  // a row has GPR <= 64 groups: with GPR < 64 the wavefront holds 64 / GPR copies of its rows, lane l
+  // working on group l mod GPR; the copies load, compute and store the same values, the wavefront
+  // rotates give every lane its periodic x neighbour, and only the first copy counts E and M
+  c.lane = threadIdx.x & (X::GPR - 1u);
+  c.cnt = (threadIdx.x & 63u) < X::GPR ? 1u : 0u;
   c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int j = 0; j < 2; ++j) c.yrow[j] = wrap_row(c.y0 + 2u * c.wave + 1u + j, 2u, L);
@@ -477,21 +484,22 @@ __global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __
   if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
   uint32_t unsat4 = 0, neg = 0;
   if (c.wave == 0)
-    col3_run<TY, 1, NEVER, MEAS>(c, unsat4, neg);
+    col3_run<LL, TY, 1, NEVER, MEAS>(c, unsat4, neg);
   else if (c.wave == (uint32_t)(W - 1))
-    col3_run<TY, 2, NEVER, MEAS>(c, unsat4, neg);
+    col3_run<LL, TY, 2, NEVER, MEAS>(c, unsat4, neg);
   else
-    col3_run<TY, 0, NEVER, MEAS>(c, unsat4, neg);
+    col3_run<LL, TY, 0, NEVER, MEAS>(c, unsat4, neg);
   if (MEAS) {
     __shared__ int64_t red[W];
     record_block<64 * W>((int64_t)(unsat4 >> 2), (int64_t)neg, rec, red);
   }
 }
 
-// Register-column kernel (k_stream3r): L = 512, tile.y = TY in {8, 16} with
-// TY/2 + 1 waves (320 or 576 threads), tile.z = H even.
+// Register-column kernel (k_stream3r): L = 128, 256 or 512, tile.y = TY in
+// {8, 16} with TY/2 + 1 waves (320 or 576 threads), tile.z = H even.
 static bool col3_shape(const Lat& lat, const Tile& tile) {
-  if (lat.J != nullptr || lat.d != 3 || lat.L != 512 || (uint32_t)tile.x != lat.L) return false;
+  if (lat.J != nullptr || lat.d != 3 || (uint32_t)tile.x != lat.L) return false;
+  if (lat.L != 128 && lat.L != 256 && lat.L != 512) return false;
   const bool ok = (tile.y == 16 && tile.threads == 576) || (tile.y == 8 && tile.threads == 320);
   return ok && tile.z >= 2 && tile.z % 2 == 0 && lat.L % (uint32_t)tile.z == 0;
 }
@@ -514,7 +522,7 @@ uint32_t stream3d_record_parts(const Lat& lat, const Tile& tile) {
   return (lat.L / (uint32_t)tile.y) * (lat.L / (uint32_t)tile.z);
 }
 
-template <int TY>
+template <uint32_t LL, int TY>
 static hipError_t gocol3(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
                          uint32_t H, const Record* rec, hipStream_t stream) {
   dim3 grid((lat.L / TY) * (lat.L / H));
@@ -522,14 +530,14 @@ static hipError_t gocol3(const Lat& lat, const int8_t* src, int8_t* dst, const P
   const Record r = rec ? *rec : Record{nullptr};
   if (rec) {
     if (never)
-      hipLaunchKernelGGL((k_stream3r<TY, true, true>), grid, block, 0, stream, src, dst, a, H, r);
+      hipLaunchKernelGGL((k_stream3r<LL, TY, true, true>), grid, block, 0, stream, src, dst, a, H, r);
     else
-      hipLaunchKernelGGL((k_stream3r<TY, false, true>), grid, block, 0, stream, src, dst, a, H, r);
+      hipLaunchKernelGGL((k_stream3r<LL, TY, false, true>), grid, block, 0, stream, src, dst, a, H, r);
   } else {
     if (never)
-      hipLaunchKernelGGL((k_stream3r<TY, true, false>), grid, block, 0, stream, src, dst, a, H, r);
+      hipLaunchKernelGGL((k_stream3r<LL, TY, true, false>), grid, block, 0, stream, src, dst, a, H, r);
     else
-      hipLaunchKernelGGL((k_stream3r<TY, false, false>), grid, block, 0, stream, src, dst, a, H, r);
+      hipLaunchKernelGGL((k_stream3r<LL, TY, false, false>), grid, block, 0, stream, src, dst, a, H, r);
   }
   return hipGetLastError();
 }
@@ -552,8 +560,12 @@ hipError_t launch_stream3d(const Lat& lat, const int8_t* src, int8_t* dst, const
   const uint32_t H = (uint32_t)tile.z;
   if (col3_shape(lat, tile)) {
     if (measured) *measured = (rec != nullptr);
-    if (tile.y == 16) return gocol3<16>(lat, src, dst, a, never, H, rec, stream);
-    return gocol3<8>(lat, src, dst, a, never, H, rec, stream);
+    if (lat.L == 512) return tile.y == 16 ? gocol3<512, 16>(lat, src, dst, a, never, H, rec, stream)
+                                          : gocol3<512, 8>(lat, src, dst, a, never, H, rec, stream);
+    if (lat.L == 256) return tile.y == 16 ? gocol3<256, 16>(lat, src, dst, a, never, H, rec, stream)
+                                          : gocol3<256, 8>(lat, src, dst, a, never, H, rec, stream);
+    return tile.y == 16 ? gocol3<128, 16>(lat, src, dst, a, never, H, rec, stream)
+                        : gocol3<128, 8>(lat, src, dst, a, never, H, rec, stream);
   }
   if (lat.L == 512) {
     if (tile.y == 8 && tile.threads == 640) return gostream3<8, 10, 1>(lat, src, dst, a, never, H, stream);

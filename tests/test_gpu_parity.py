@@ -139,6 +139,9 @@ CASES_3D = [
     (STR, (0, 8, 7, 256), 72), (STR, (0, 32, 16, 256), 128), (STR, (0, 16, 3, 512), 48),
     (TIL, (16, 4, 4, 64), 16), (TIL, (16, 4, 4, 64), 32), (TIL, (32, 8, 4, 128), 64),
     (TIL, (64, 8, 8, 256), 64), (TIL, (128, 8, 4, 256), 128),
+    # register-column plane streaming below L = 512 (the wavefront holds copies of its rows)
+    (FUS, (256, 16, 16, 576), 256), (FUS, (256, 8, 32, 320), 256), (FUS, (128, 16, 8, 576), 128),
+    (FUS, (128, 8, 128, 320), 128),
 ]
 
 
@@ -186,7 +189,18 @@ def test_auto_picks_stream(oracle_mod, model, L, d):
                  cseed=workloads.seed(0x11) if model else None, tag="auto-stream")
 
 
-@pytest.mark.parametrize("model,L", [(0, 160), (1, 200), (0, 256), (1, 384)])
+def test_auto_3d_L256_register_columns(oracle_mod):
+    """3D Ising L = 256 runs the register-column plane streaming by default (16-row slabs, strips of
+    8 planes; the wavefront holds two copies of each row), with and without records."""
+    seed = workloads.seed(0x256)
+    lat = make(0, 256, 3, seed, 1)
+    assert lat.kernel == FUS and lat.tile == (256, 16, 8, 576), (spin.KERNEL_NAMES[lat.kernel], lat.tile)
+    lat.close()
+    compare_runs(oracle_mod, 0, 256, 3, seed, [(1, B_3D, 1), (2, 0.3, 0), (1, 0.9, 1)], replica=1,
+                 tag="auto-3d-L256")
+
+
+@pytest.mark.parametrize("model,L", [(0, 160), (1, 200), (0, 320), (1, 384)])
 def test_auto_3d_stream_defaults(oracle_mod, model, L):
     """Large 3D lattices stream with the size-dependent default tiles (slab rows, strip planes and
     threads chosen by L); the bits are the oracle's."""
