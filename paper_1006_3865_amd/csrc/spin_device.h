@@ -10,6 +10,10 @@
 
 namespace spin {
 
+// Philox4x32 round multipliers.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+
 // Three-input XOR in one VALU op (v_bitop3_b32, truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -22,8 +26,8 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
                                        const RoundKeys& K, uint32_t r[4]) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
     const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, K.k0[i]);
     const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, K.k1[i]);
     c1 = (uint32_t)p1;
@@ -43,41 +47,56 @@ struct PhiloxUniform {
   uint32_t x1;      // round 1: hi(M0*c0) ^ x1          -> c2 after round 1
   uint32_t x2;      // round 2: hi(M1*c2) ^ x2          -> c0 after round 2
   uint32_t x3;      // round 2: c3_after_round1 ^ x3    -> c2 after round 2 (x3 = hi(M0*u0) ^ k1[1])
-  uint32_t u3;      // round 2: lo(M0*u0)               -> c3 after round 2
+  uint32_t x4;      // round 3: hi(M0*c0) ^ x4          -> c2 after round 3 (x4 = lo(M0*u0) ^ k1[2],
+                    //          lo(M0*u0) being c3 after round 2)
 };
 
 __device__ __forceinline__ PhiloxUniform philox_uniform(uint32_t c1, uint32_t c2, uint32_t c3,
                                                         const RoundKeys& K) {
   PhiloxUniform U;
-  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
   const uint32_t u0 = (uint32_t)(p1 >> 32) ^ c1 ^ K.k0[0];  // c0 after round 1
   const uint32_t u1 = (uint32_t)p1;                         // c1 after round 1
   U.x1 = c3 ^ K.k1[0];
   U.x2 = u1 ^ K.k0[1];
-  const uint64_t q0 = (uint64_t)0xD2511F53u * u0;
+  const uint64_t q0 = (uint64_t)kPhiloxM0 * u0;
   U.x3 = (uint32_t)(q0 >> 32) ^ K.k1[1];
-  U.u3 = (uint32_t)q0;
+  U.x4 = (uint32_t)q0 ^ K.k1[2];
   return U;
 }
 
-// Philox4x32-10 of counter (c0, c1, c2, c3) given U = philox_uniform(c1, c2, c3).
-__device__ __forceinline__ void philox_lane(uint32_t c0, const PhiloxUniform& U, const RoundKeys& K,
-                                            uint32_t r[4]) {
+// Waits for the round keys' scalar loads before a loop.  Scalar loads and LDS
+// reads share one wait counter: a key first used inside the loop would make
+// every iteration wait there for all LDS reads in flight, not only the first.
+__device__ __forceinline__ void keys_resident(const RoundKeys& K) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) asm volatile("" ::"s"(K.k0[i]), "s"(K.k1[i]));
+}
+
+// Philox4x32-10 of counter (c0, c1, c2, c3) given U = philox_uniform(c1, c2, c3)
+// and the first product p0 = M0 * c0.
+__device__ __forceinline__ void philox_from_p0(uint64_t p0, const PhiloxUniform& U, const RoundKeys& K,
+                                               uint32_t r[4]) {
   // round 1
-  const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
   const uint32_t a2 = (uint32_t)(p0 >> 32) ^ U.x1;
   const uint32_t a3 = (uint32_t)p0;
   // round 2 (c0 after round 1 is uniform: its product is in U)
-  const uint64_t p1 = (uint64_t)0xCD9E8D57u * a2;
-  uint32_t d0 = (uint32_t)(p1 >> 32) ^ U.x2;
-  uint32_t d1 = (uint32_t)p1;
-  uint32_t d2 = a3 ^ U.x3;
-  uint32_t d3 = U.u3;
-  // rounds 3..10
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * a2;
+  const uint32_t b0 = (uint32_t)(p1 >> 32) ^ U.x2;
+  const uint32_t b1 = (uint32_t)p1;
+  const uint32_t b2 = a3 ^ U.x3;
+  // round 3 (c3 after round 2 is uniform: folded with its key into x4)
+  const uint64_t p2 = (uint64_t)kPhiloxM0 * b0;
+  const uint64_t p3 = (uint64_t)kPhiloxM1 * b2;
+  uint32_t d0 = xor3((uint32_t)(p3 >> 32), b1, K.k0[2]);
+  uint32_t d1 = (uint32_t)p3;
+  uint32_t d2 = (uint32_t)(p2 >> 32) ^ U.x4;
+  uint32_t d3 = (uint32_t)p2;
+  // rounds 4..10
 #pragma unroll
-  for (int i = 2; i < 10; ++i) {
-    const uint64_t q0 = (uint64_t)0xD2511F53u * d0;
-    const uint64_t q1 = (uint64_t)0xCD9E8D57u * d2;
+  for (int i = 3; i < 10; ++i) {
+    const uint64_t q0 = (uint64_t)kPhiloxM0 * d0;
+    const uint64_t q1 = (uint64_t)kPhiloxM1 * d2;
     const uint32_t n0 = xor3((uint32_t)(q1 >> 32), d1, K.k0[i]);
     const uint32_t n2 = xor3((uint32_t)(q0 >> 32), d3, K.k1[i]);
     d1 = (uint32_t)q1;
@@ -86,6 +105,28 @@ __device__ __forceinline__ void philox_lane(uint32_t c0, const PhiloxUniform& U,
     d2 = n2;
   }
   r[0] = d0; r[1] = d1; r[2] = d2; r[3] = d3;
+}
+
+// Philox4x32-10 of counter (c0, c1, c2, c3) given U = philox_uniform(c1, c2, c3).
+__device__ __forceinline__ void philox_lane(uint32_t c0, const PhiloxUniform& U, const RoundKeys& K,
+                                            uint32_t r[4]) {
+  philox_from_p0((uint64_t)kPhiloxM0 * c0, U, K, r);
+}
+
+// philox_lane for the counter c0 = base + v with base uniform, v per lane and
+// base + v < 2^32: M0 * c0 = M0 * v + M0 * base, one multiply-add whose 64-bit
+// addend mbase = M0 * base (philox_base) is computed on the scalar unit.
+// The empty asm keeps the compiler from folding the product back into
+// M0 * (base + v), which costs a vector add before the multiply.
+__device__ __forceinline__ uint64_t philox_base(uint32_t base) {
+  uint64_t m = (uint64_t)kPhiloxM0 * base;
+  asm volatile("" : "+s"(m));
+  return m;
+}
+
+__device__ __forceinline__ void philox_lane_split(uint32_t v, uint64_t mbase, const PhiloxUniform& U,
+                                                  const RoundKeys& K, uint32_t r[4]) {
+  philox_from_p0((uint64_t)kPhiloxM0 * v + mbase, U, K, r);
 }
 
 // ---------------------------------------------------------------------------

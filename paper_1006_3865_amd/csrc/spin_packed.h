@@ -29,17 +29,20 @@ __device__ __forceinline__ uint32_t gather_bytes(uint32_t lo, uint32_t hi, uint3
 // Selector of the bytes of parity P of an 8-byte group.
 __device__ __forceinline__ uint32_t sel_active(uint32_t P) { return P ? 0x07050301u : 0x06040200u; }
 
-// 4u per active site, packed (u = unsatisfied bonds among the 2 + NO neighbours).
-template <int NO>
+// 4u per active site, packed (u = unsatisfied bonds among the 2 + NO neighbours);
+// 8u with SB = kSignBit8 (bit 3 of each byte carries the sign as well).
+constexpr uint32_t kSignBit8 = 0x08080808u;
+
+template <int NO, uint32_t SB = kSignBit>
 __device__ __forceinline__ uint32_t unsat_packed(uint32_t P, uint32_t c0, uint32_t c1, uint32_t lw, uint32_t rw,
                                                  const uint32_t (&o0)[NO], const uint32_t (&o1)[NO]) {
   const uint32_t sa = sel_active(P), so = sel_active(P ^ 1u);
   const uint32_t A = gather_bytes(c0, c1, sa);
   const uint32_t I = gather_bytes(c0, c1, so);
   const uint32_t N = __builtin_amdgcn_perm(I, P ? rw : lw, P ? 0x00070605u : 0x06050403u);
-  uint32_t S = ((A ^ I) & kSignBit) + ((A ^ N) & kSignBit);
+  uint32_t S = ((A ^ I) & SB) + ((A ^ N) & SB);
 #pragma unroll
-  for (int i = 0; i < NO; ++i) S += (A ^ gather_bytes(o0[i], o1[i], sa)) & kSignBit;
+  for (int i = 0; i < NO; ++i) S += (A ^ gather_bytes(o0[i], o1[i], sa)) & SB;
   return S;
 }
 
@@ -90,6 +93,73 @@ __device__ __forceinline__ void apply_packed_count(uint32_t P, uint32_t& c0, uin
   constexpr uint32_t K = 0x01010101u * (8u * (uint32_t)D);
   const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
   acc = __builtin_amdgcn_sad_u8(Sf, 0u, acc);
+}
+
+// Pair table: the bounds of two packed sites in one 8-byte LDS entry.  With
+// 8u per byte, the low 16 bits of the packed dword, 8 u0 + 2048 u1, are the
+// byte offset of the entry {bound[u0], bound[u1]} of packed sites 0 and 1, the
+// high 16 bits that of sites 2 and 3: two shifts or masks and two 8-byte LDS
+// reads where the 4u form takes four extractions and four reads.  Z is the
+// largest u (the coordination number); the table spans pair_words(Z) dwords.
+constexpr uint32_t pair_words(int Z) { return 2u * (uint32_t)Z + 512u * (uint32_t)Z + 2u; }
+
+template <int Z>
+__device__ __forceinline__ void fill_pair(uint32_t* pair, const uint32_t* bound, uint32_t t) {
+  if (t < (uint32_t)((Z + 1) * (Z + 1))) {
+    const uint32_t u0 = t % (uint32_t)(Z + 1), u1 = t / (uint32_t)(Z + 1);
+    pair[2u * u0 + 512u * u1] = bound[u0];
+    pair[2u * u0 + 512u * u1 + 1u] = bound[u1];
+  }
+}
+
+// The two pair-table entries of a packed dword S of 8u values: the bounds of
+// packed sites 0..3 (byte address pair_lds).
+__device__ __forceinline__ uint4 lookup_pair(uint32_t S, const char* pair_lds) {
+  const uint2 b01 = *(const uint2*)(pair_lds + (S & 0xFFFFu));
+  const uint2 b23 = *(const uint2*)(pair_lds + (S >> 16));
+  return make_uint4(b01.x, b01.y, b23.x, b23.y);
+}
+
+// apply_packed for a packed dword S of 8u values with the bounds b from
+// lookup_pair; never8 = 8 never_level.
+template <bool NEVER>
+__device__ __forceinline__ void apply_pair(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S, uint4 b,
+                                           const uint32_t r[4], uint32_t never8) {
+  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
+  if (NEVER) {
+    a0 = a0 && (S & 0xFFu) >= never8;
+    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
+    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
+    a3 = a3 && (S >> 24) >= never8;
+  }
+  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
+  c0 = xor3(c0, a0 ? ma : 0u, a1 ? mb : 0u);
+  c1 = xor3(c1, a2 ? ma : 0u, a3 ? mb : 0u);
+}
+
+// apply_pair that also adds to acc four times the number of unsatisfied bonds
+// of the four active sites after the update (D: lattice dimension): a flipped
+// site's byte becomes 16D - S_m (no byte borrows: S_m <= 16D); the bytes are
+// multiples of 8, so halving the dword halves every byte without a carry from
+// the byte above, and one v_sad_u8 against zero sums them.
+template <bool NEVER, int D>
+__device__ __forceinline__ void apply_pair_count(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S, uint4 b,
+                                                 const uint32_t r[4], uint32_t never8, uint32_t& acc) {
+  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
+  if (NEVER) {
+    a0 = a0 && (S & 0xFFu) >= never8;
+    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
+    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
+    a3 = a3 && (S >> 24) >= never8;
+  }
+  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
+  const uint32_t d0 = (a0 ? ma : 0u) ^ (a1 ? mb : 0u), d1 = (a2 ? ma : 0u) ^ (a3 ? mb : 0u);
+  c0 ^= d0;
+  c1 ^= d1;
+  const uint32_t F = gather_bytes(d0, d1, sel_active(P));  // 0xFE at the packed sites that flipped
+  constexpr uint32_t K = 0x01010101u * (16u * (uint32_t)D);
+  const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
+  acc = __builtin_amdgcn_sad_u8(Sf >> 1, 0u, acc);
 }
 
 }  // namespace spin

@@ -243,34 +243,43 @@ __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
 // rows, and colour 1 reads them 4 steps later.  A barrier after every 4th
 // step orders each such write before its read and each read before the slot
 // is written again (written in step k-1 for row k, read in step k+3,
-// rewritten in step k+7).  No spin row goes through LDS.
+// rewritten in step k+7).  No spin row goes through LDS.  The two edge
+// writes are made by every lane, the other lanes into 64 words of their own
+// after the slot's edge words, so that no branch on the lane is taken.
+// Accept bounds come from the pair table (8u per packed byte, spin_packed.h),
+// and the first Philox product takes the row's part of the counter as a
+// scalar addend.
 template <int NT, int G>
 struct Col2Ctx {
   static constexpr uint32_t L = 8u * NT * G;
   static constexpr uint32_t GPR = L / 8;
   static constexpr uint32_t W = NT / 64;
   static constexpr uint32_t NS = W * G;  // segments per row
+  static constexpr uint32_t SW = 2 * NS + 64;  // words per ring slot: [segment NS][lo, hi], then 64 spare
+  static constexpr uint32_t PW = (pair_words(4) + 15u) & ~15u;  // pair table words, rounded to 64 bytes
   __amdgpu_buffer_rsrc_t rsrc, rdst;
-  uint32_t* edge;                        // LDS: [slot 8][segment NS][lo, hi]
-  const uint32_t* bound;
+  uint32_t* edge;                        // LDS: [slot 8][SW]
+  const char* pair;
   const RoundKeys* keys;
   PhiloxUniform U0, U1;
-  uint32_t never4, y0, H, t, lane;
+  uint32_t never8, y0, H, t, lane;
   uint32_t eoff[G];                      // byte offset in a row of this lane's edge word
   uint32_t lnb[G], rnb[G];               // LDS word of the left segment's high word, the right one's low word
-  uint32_t own[G];                       // LDS word of this segment's low word
+  uint32_t wlo[G], whi[G];               // LDS words the lane's low and high results go to (spare unless lane 0 / 63)
 };
 
 template <uint32_t P, bool NEVER>
-__device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t nb, uint32_t c0,
-                                           const PhiloxUniform& U, const RoundKeys& K, const uint32_t* bound,
-                                           uint32_t never4) {
-  uint32_t rnd[4];
-  philox_lane(c0, U, K, rnd);
+__device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t nb, uint32_t v, uint64_t mbase,
+                                           const PhiloxUniform& U, const RoundKeys& K, const char* pair,
+                                           uint32_t never8) {
+  // the bounds first, so that their LDS reads are in flight during the rounds
   const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
-  const uint32_t Sp = unsat_packed<2>(P, c.x, c.y, nb, nb, o0, o1);
+  const uint32_t Sp = unsat_packed<2, kSignBit8>(P, c.x, c.y, nb, nb, o0, o1);
+  const uint4 b = lookup_pair(Sp, pair);
+  uint32_t rnd[4];
+  philox_lane_split(v, mbase, U, K, rnd);
   uint32_t c0n = c.x, c1n = c.y;
-  apply_packed<NEVER>(P, c0n, c1n, Sp, rnd, bound, never4);
+  apply_pair<NEVER>(P, c0n, c1n, Sp, b, rnd, never8);
   return make_uint2(c0n, c1n);
 }
 
@@ -289,7 +298,7 @@ template <int NT, int G, bool NEVER, uint32_t S>
 __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8][G], uint32_t (&E)[8][G],
                                           uint32_t i) {
   using C = Col2Ctx<NT, G>;
-  constexpr uint32_t L = C::L, GPR = C::GPR, NS = C::NS;
+  constexpr uint32_t L = C::L, GPR = C::GPR;
   if (i >= c.H + 5) return;
   // row a+2 = strip row i+3 (steps after i = H reload row H+3, which nothing reads)
   const uint32_t yl = wrap_row(c.y0 + (i <= c.H ? i : c.H) + 3u, 2u, L);
@@ -303,29 +312,29 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
     // colour 0 on row a (strip row i+1, register slot S+1); a has the parity of i+1
     constexpr uint32_t P = (S + 1u) & 1u;
     const uint32_t y = wrap_row(c.y0 + i + 1u, 2u, L);
-    uint32_t* slot = c.edge + ((S + 1u) & 7u) * (2u * NS);
+    uint32_t* slot = c.edge + ((S + 1u) & 7u) * C::SW;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 1) & 7][j];
       const uint32_t nb = col2_xnb<P>(cc, E[(S + 1) & 7][j]);
-      const uint2 n = col2_unit<P, NEVER>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, y * GPR + c.t + NT * j, c.U0,
-                                          *c.keys, c.bound, c.never4);
+      const uint2 n = col2_unit<P, NEVER>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, c.t,
+                                          philox_base(y * GPR + NT * j), c.U0, *c.keys, c.pair, c.never8);
       R[(S + 1) & 7][j] = n;
-      if (c.lane == 0) slot[c.own[j]] = n.x;
-      if (c.lane == 63) slot[c.own[j] + 1u] = n.y;
+      slot[c.wlo[j]] = n.x;
+      slot[c.whi[j]] = n.y;
     }
   }
   if (i >= 5) {
     // colour 1 on row b (strip row i-3, register slot S+5); 1 + b has the parity of i
     constexpr uint32_t P = S & 1u;
     const uint32_t y = c.y0 + i - 5u;
-    const uint32_t* slot = c.edge + ((S + 5u) & 7u) * (2u * NS);
+    const uint32_t* slot = c.edge + ((S + 5u) & 7u) * C::SW;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 5) & 7][j];
       const uint32_t nb = col2_xnb<P>(cc, slot[P == 0 ? c.lnb[j] : c.rnb[j]]);
-      const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, y * GPR + c.t + NT * j,
-                                          c.U1, *c.keys, c.bound, c.never4);
+      const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, c.t,
+                                          philox_base(y * GPR + NT * j), c.U1, *c.keys, c.pair, c.never8);
       R[(S + 5) & 7][j] = n;
       const u32x2 w = {n.x, n.y};
       __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * (c.t + NT * j), y * L, 0);
@@ -339,16 +348,16 @@ __global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src,
                                                  PhaseArgs a, uint32_t H) {
   using C = Col2Ctx<NT, G>;
   constexpr uint32_t L = C::L, NS = C::NS;
-  __shared__ __align__(16) uint32_t lds[8 + 8 * 2 * NS];
+  __shared__ __align__(16) uint32_t lds[C::PW + 8 * C::SW];
   C c;
   c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(L * L), 0x00020000);
   c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(L * L), 0x00020000);
-  c.bound = lds;
-  c.edge = lds + 8;
+  c.pair = (const char*)lds;
+  c.edge = lds + C::PW;
   c.keys = &a.keys;
   c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
   c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
-  c.never4 = a.never4;
+  c.never8 = 2u * a.never4;
   c.y0 = blockIdx.x * H;
   c.H = H;
   c.t = threadIdx.x;
@@ -358,11 +367,13 @@ __global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src,
   for (int j = 0; j < G; ++j) {
     const uint32_t g = c.t + NT * j, s = wave + C::W * j;
     c.eoff[j] = c.lane == 0 ? (g ? 8u * g - 4u : L - 4u) : (c.lane == 63 ? (8u * (g + 1u)) % L : 8u * g);
-    c.own[j] = 2u * s;
+    c.wlo[j] = c.lane == 0 ? 2u * s : 2u * NS + c.lane;
+    c.whi[j] = c.lane == 63 ? 2u * s + 1u : 2u * NS + c.lane;
     c.lnb[j] = 2u * ((s + NS - 1u) % NS) + 1u;
     c.rnb[j] = 2u * ((s + 1u) % NS);
   }
-  if (threadIdx.x < 8) lds[threadIdx.x] = a.bound[threadIdx.x];
+  fill_pair<4>(lds, a.bound, threadIdx.x);
+  keys_resident(a.keys);
   uint2 R[8][G];
   uint32_t E[8][G];
   // prologue: strip rows 0, 1, 2 (y0-2, y0-1, y0)

@@ -263,12 +263,13 @@ struct Col3Ctx {
   static constexpr uint32_t RP = TY + 4;         // rows of a slice
   static constexpr uint32_t PB = RP * L;         // bytes of a slice
   static constexpr int W = TY / 2 + 1;
+  static constexpr uint32_t PW = (pair_words(6) + 15u) & ~15u;  // pair table words, rounded to 64 bytes
   __amdgpu_buffer_rsrc_t rsrc, rdst;
   int8_t* ring;
-  const uint32_t* bound;
+  const char* pair;
   const RoundKeys* keys;
   PhiloxUniform U0, U1;
-  uint32_t never4, y0, z0, H, lane, wave;
+  uint32_t never8, y0, z0, H, lane, wave;
   uint32_t cnt;       // 1 on the first copy of a row in the wavefront (the one that counts E/M), else 0
   uint32_t yrow[2];   // y of the wave's two rows
   uint32_t yhalo;     // y of the halo row the edge wave loads
@@ -285,23 +286,26 @@ __device__ __forceinline__ uint32_t xnb(uint2 c) {
 }
 
 // One colour unit of a group with active parity P: centre c, y neighbours
-// ym, yp, z neighbours zm, zp; Philox counter base c0.  Returns the new group;
-// with MEAS adds 4 x the unsatisfied bonds of the active sites after the
-// update to acc.
+// ym, yp, z neighbours zm, zp; Philox counter base + lane, with mbase =
+// philox_base(base).  Returns the new group; with MEAS adds 4 x the
+// unsatisfied bonds of the active sites after the update to acc.  The
+// bounds come from the pair table (8u per packed byte), read before the
+// Philox rounds so that the LDS reads are in flight during them.
 template <uint32_t P, bool NEVER, bool MEAS>
-__device__ __forceinline__ uint2 col3_unit(uint2 c, uint2 ym, uint2 yp, uint2 zm, uint2 zp, uint32_t c0,
-                                           const PhiloxUniform& U, const RoundKeys& K, const uint32_t* bound,
-                                           uint32_t never4, uint32_t& acc) {
-  uint32_t rnd[4];
-  philox_lane(c0, U, K, rnd);
+__device__ __forceinline__ uint2 col3_unit(uint2 c, uint2 ym, uint2 yp, uint2 zm, uint2 zp, uint32_t lane,
+                                           uint64_t mbase, const PhiloxUniform& U, const RoundKeys& K,
+                                           const char* pair, uint32_t never8, uint32_t& acc) {
   const uint32_t nb = xnb<P>(c);
   const uint32_t o0[4] = {ym.x, yp.x, zm.x, zp.x}, o1[4] = {ym.y, yp.y, zm.y, zp.y};
-  const uint32_t Sp = unsat_packed<4>(P, c.x, c.y, nb, nb, o0, o1);
+  const uint32_t Sp = unsat_packed<4, kSignBit8>(P, c.x, c.y, nb, nb, o0, o1);
+  const uint4 b = lookup_pair(Sp, pair);
+  uint32_t rnd[4];
+  philox_lane_split(lane, mbase, U, K, rnd);
   uint32_t c0n = c.x, c1n = c.y;
   if (MEAS) {
-    apply_packed_count<NEVER, 3>(P, c0n, c1n, Sp, rnd, bound, never4, acc);
+    apply_pair_count<NEVER, 3>(P, c0n, c1n, Sp, b, rnd, never8, acc);
   } else {
-    apply_packed<NEVER>(P, c0n, c1n, Sp, rnd, bound, never4);
+    apply_pair<NEVER>(P, c0n, c1n, Sp, b, rnd, never8);
   }
   return make_uint2(c0n, c1n);
 }
@@ -350,10 +354,12 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<LL, TY>& c, Col3Regs& R,
   const uint2 up0 = *reinterpret_cast<const uint2*>(pA);
   const uint2 dn1 = *reinterpret_cast<const uint2*>(pA + 3 * L);
   uint2 ya0[2];
-  ya0[0] = col3_unit<P0, NEVER, false>(R.xa[0], up0, R.xa[1], R.ya1[0], R.xa1[0], (a * L + c.yrow[0]) * GPR + c.lane,
-                                       c.U0, *c.keys, c.bound, c.never4, none);
-  ya0[1] = col3_unit<P1, NEVER, false>(R.xa[1], R.xa[0], dn1, R.ya1[1], R.xa1[1], (a * L + c.yrow[1]) * GPR + c.lane,
-                                       c.U0, *c.keys, c.bound, c.never4, none);
+  ya0[0] = col3_unit<P0, NEVER, false>(R.xa[0], up0, R.xa[1], R.ya1[0], R.xa1[0], c.lane,
+                                       philox_base((a * L + c.yrow[0]) * GPR), c.U0, *c.keys, c.pair, c.never8,
+                                       none);
+  ya0[1] = col3_unit<P1, NEVER, false>(R.xa[1], R.xa[0], dn1, R.ya1[1], R.xa1[1], c.lane,
+                                       philox_base((a * L + c.yrow[1]) * GPR), c.U0, *c.keys, c.pair, c.never8,
+                                       none);
   *reinterpret_cast<uint2*>(pA + L) = ya0[0];
   *reinterpret_cast<uint2*>(pA + 2 * L) = ya0[1];
   // colour 1 on plane b = a-1 (owned rows)
@@ -364,11 +370,13 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<LL, TY>& c, Col3Regs& R,
     const uint2 dnB = *reinterpret_cast<const uint2*>(pB + 3 * L);
     uint32_t add = 0;
     if (OWN0)
-      fin[0] = col3_unit<P0, NEVER, MEAS>(R.ya1[0], upB, R.ya1[1], R.ya2[0], ya0[0],
-                                          (b * L + c.yrow[0]) * GPR + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+      fin[0] = col3_unit<P0, NEVER, MEAS>(R.ya1[0], upB, R.ya1[1], R.ya2[0], ya0[0], c.lane,
+                                          philox_base((b * L + c.yrow[0]) * GPR), c.U1, *c.keys, c.pair, c.never8,
+                                          add);
     if (OWN1)
-      fin[1] = col3_unit<P1, NEVER, MEAS>(R.ya1[1], R.ya1[0], dnB, R.ya2[1], ya0[1],
-                                          (b * L + c.yrow[1]) * GPR + c.lane, c.U1, *c.keys, c.bound, c.never4, add);
+      fin[1] = col3_unit<P1, NEVER, MEAS>(R.ya1[1], R.ya1[0], dnB, R.ya2[1], ya0[1], c.lane,
+                                          philox_base((b * L + c.yrow[1]) * GPR), c.U1, *c.keys, c.pair, c.never8,
+                                          add);
     if (MEAS) {
       // only the first copy of the row in the wavefront counts
       unsat4 += c.cnt * add;
@@ -453,16 +461,16 @@ __global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __
   using X = Col3Ctx<LL, TY>;
   constexpr uint32_t L = X::L;
   constexpr int W = X::W;
-  __shared__ __align__(16) int8_t lds[32 + 3 * X::PB];
+  __shared__ __align__(16) int8_t lds[4 * X::PW + 3 * X::PB];
   X c;
   c.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, (int)(L * L * L), 0x00020000);
   c.rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, (int)(L * L * L), 0x00020000);
-  c.ring = lds + 32;
-  c.bound = reinterpret_cast<const uint32_t*>(lds);
+  c.ring = lds + 4 * X::PW;
+  c.pair = (const char*)lds;
   c.keys = &a.keys;
   c.U0 = philox_uniform(a.t, a.replica, 0u, a.keys);
   c.U1 = philox_uniform(a.t, a.replica, 1u, a.keys);
-  c.never4 = a.never4;
+  c.never8 = 2u * a.never4;
   // workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles (all slabs
   // of its strips), so that the halo rows of neighbouring slabs are read from the same L2
   const uint32_t nslab = L / TY;
@@ -481,7 +489,8 @@ __global__ __launch_bounds__(64 * (TY / 2 + 1)) void k_stream3r(const int8_t* __
 #pragma unroll
   for (int j = 0; j < 2; ++j) c.yrow[j] = wrap_row(c.y0 + 2u * c.wave + 1u + j, 2u, L);
   c.yhalo = (c.wave == 0) ? wrap_row(c.y0, 2u, L) : wrap_row(c.y0 + TY + 3u, 2u, L);
-  if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = a.bound[threadIdx.x];
+  fill_pair<6>(reinterpret_cast<uint32_t*>(lds), a.bound, threadIdx.x);
+  keys_resident(a.keys);
   uint32_t unsat4 = 0, neg = 0;
   if (c.wave == 0)
     col3_run<LL, TY, 1, NEVER, MEAS>(c, unsat4, neg);
