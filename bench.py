@@ -568,6 +568,9 @@ def bench_serving(torch, serve, workloads, jobs):
             "results_identical": bool(same)}
 
 
+SETTLE_S = 0.3  # seconds of untimed sweeps before a single-lattice job's warm-up steps
+
+
 def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0, 0, 0), so_sweeps=200):
     """One single-lattice workload: `steps` steps of 10 sweeps with the workload's E/M records, on
     lattices created and initialised before the timed region; then `so_sweeps` back-to-back sweeps
@@ -599,6 +602,15 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
     for lat, _ in lats:
         lat.synchronize()
 
+    # clock settle: a cold GPU needs tens of milliseconds under load before it reaches its steady
+    # clock (back-to-back repeats of 600 sweeps at 2D L=8192: 1644, then 1851 and 1864 attempts/ns),
+    # so the same sweeps run for SETTLE_S seconds before the warm-up steps; like them they only
+    # advance the chains
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < SETTLE_S:
+        for lat, b in lats:
+            lat.sweep(sweeps_per_step, b)
+        torch.cuda.synchronize()
     # warmup (advances the same chains; the kernels' cost does not depend on the state)
     for i in range(warmup):
         for lat, b in lats:
@@ -627,6 +639,7 @@ def lattice_job(torch, spin, workloads, name, steps, warmup, kern=0, tile=(0, 0,
     for lat, _ in lats:
         lat.close()
     res = {"workload": name, "kernel": kname, "lattices": len(lats), "steps": steps, "warmup": warmup,
+           "settle_s": SETTLE_S,
            "sweeps_per_step": sweeps_per_step, "record_every": every,
            "value": round(steps * sweeps_per_step * N * len(lats) / (wall * 1e9), 2),
            "ms_per_step": round(wall * 1e3 / max(1, steps), 4)}
