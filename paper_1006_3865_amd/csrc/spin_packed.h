@@ -162,4 +162,50 @@ __device__ __forceinline__ void apply_pair_count(uint32_t P, uint32_t& c0, uint3
   acc = __builtin_amdgcn_sad_u8(Sf >> 1, 0u, acc);
 }
 
+// Parity-split form of an 8-site group: x = its even bytes (sites 8g, 8g+2,
+// 8g+4, 8g+6), y = its odd bytes, so that the active sites of either colour
+// are one dword as they stand and a row neighbour's are the same half of its
+// group.  Loaded groups are split once, stored groups joined once.
+__device__ __forceinline__ uint2 split_group(uint32_t c0, uint32_t c1) {
+  return make_uint2(gather_bytes(c0, c1, 0x06040200u), gather_bytes(c0, c1, 0x07050301u));
+}
+__device__ __forceinline__ uint2 join_group(uint2 s) {
+  return make_uint2(gather_bytes(s.x, s.y, 0x05010400u), gather_bytes(s.x, s.y, 0x07030602u));
+}
+
+// Decisions of a packed dword of 8u values S (bounds b from lookup_pair) applied to the
+// active half A of a parity-split group: byte m of A is packed site m.
+template <bool NEVER>
+__device__ __forceinline__ uint32_t apply_split(uint32_t A, uint32_t S, uint4 b, const uint32_t r[4],
+                                                uint32_t never8) {
+  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
+  if (NEVER) {
+    a0 = a0 && (S & 0xFFu) >= never8;
+    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
+    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
+    a3 = a3 && (S >> 24) >= never8;
+  }
+  return xor3(xor3(A, a0 ? 0xFEu : 0u, a1 ? 0xFE00u : 0u), a2 ? 0xFE0000u : 0u, a3 ? 0xFE000000u : 0u);
+}
+
+// apply_split that also adds to acc four times the number of unsatisfied
+// bonds of the four active sites after the update (D: lattice dimension), as
+// apply_pair_count does; the flip mask of the packed sites is the XOR itself.
+template <bool NEVER, int D>
+__device__ __forceinline__ uint32_t apply_split_count(uint32_t A, uint32_t S, uint4 b, const uint32_t r[4],
+                                                      uint32_t never8, uint32_t& acc) {
+  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
+  if (NEVER) {
+    a0 = a0 && (S & 0xFFu) >= never8;
+    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
+    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
+    a3 = a3 && (S >> 24) >= never8;
+  }
+  const uint32_t F = xor3(a0 ? 0xFEu : 0u, a1 ? 0xFE00u : 0u, a2 ? 0xFE0000u : 0u) ^ (a3 ? 0xFE000000u : 0u);
+  constexpr uint32_t K = 0x01010101u * (16u * (uint32_t)D);
+  const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
+  acc = __builtin_amdgcn_sad_u8(Sf >> 1, 0u, acc);
+  return A ^ F;
+}
+
 }  // namespace spin

@@ -239,13 +239,16 @@ __global__ __launch_bounds__(NT) void k_stream2d(const int8_t* __restrict__ src,
 // lane 0 the word left of its segment, lane 63 the word right of it (the
 // others a word of their own group).  Colour 1 needs the neighbouring
 // segment's colour-0 result: after colour 0 on a row, lane 0 of each
-// segment puts its low word and lane 63 its high word into an LDS ring of 8
-// rows, and colour 1 reads them 4 steps later.  A barrier after every 4th
+// segment puts its even half (byte 0: the segment's first site) and lane 63
+// its odd half (byte 3: its last site) into an LDS ring of 8 rows, and
+// colour 1 reads them 4 steps later.  A barrier after every 4th
 // step orders each such write before its read and each read before the slot
 // is written again (written in step k-1 for row k, read in step k+3,
 // rewritten in step k+7).  No spin row goes through LDS.  The two edge
 // writes are made by every lane, the other lanes into 64 words of their own
 // after the slot's edge words, so that no branch on the lane is taken.
+// Groups are held parity-split (split_group: even bytes, odd bytes), so a
+// colour unit's active sites and their row neighbours need no gathering.
 // Accept bounds come from the pair table (8u per packed byte, spin_packed.h),
 // and the first Philox product takes the row's part of the counter as a
 // scalar addend.
@@ -268,19 +271,27 @@ struct Col2Ctx {
   uint32_t wlo[G], whi[G];               // LDS words the lane's low and high results go to (spare unless lane 0 / 63)
 };
 
+// One colour unit of a parity-split group c (x: even bytes, y: odd bytes)
+// with active parity P: y neighbours up, dn (split), x neighbour dword nb
+// (natural layout: its byte 3 is the site left of the group for P = 0, its
+// byte 0 the site right of it for P = 1); Philox counter base + v with mbase
+// = philox_base(base).  The other half of the group holds the neighbours on
+// one side, moved by one byte with nb's boundary byte shifted in those on
+// the other.  The bounds are read before the Philox rounds so that their LDS
+// reads are in flight during them.
 template <uint32_t P, bool NEVER>
 __device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t nb, uint32_t v, uint64_t mbase,
                                            const PhiloxUniform& U, const RoundKeys& K, const char* pair,
                                            uint32_t never8) {
-  // the bounds first, so that their LDS reads are in flight during the rounds
-  const uint32_t o0[2] = {up.x, dn.x}, o1[2] = {up.y, dn.y};
-  const uint32_t Sp = unsat_packed<2, kSignBit8>(P, c.x, c.y, nb, nb, o0, o1);
-  const uint4 b = lookup_pair(Sp, pair);
+  const uint32_t A = P ? c.y : c.x, I = P ? c.x : c.y;
+  const uint32_t N = __builtin_amdgcn_perm(I, nb, P ? 0x00070605u : 0x06050403u);
+  const uint32_t S = ((A ^ I) & kSignBit8) + ((A ^ N) & kSignBit8) + ((A ^ (P ? up.y : up.x)) & kSignBit8) +
+                     ((A ^ (P ? dn.y : dn.x)) & kSignBit8);
+  const uint4 b = lookup_pair(S, pair);
   uint32_t rnd[4];
   philox_lane_split(v, mbase, U, K, rnd);
-  uint32_t c0n = c.x, c1n = c.y;
-  apply_pair<NEVER>(P, c0n, c1n, Sp, b, rnd, never8);
-  return make_uint2(c0n, c1n);
+  const uint32_t An = apply_split<NEVER>(A, S, b, rnd, never8);
+  return P ? make_uint2(c.x, An) : make_uint2(An, c.y);
 }
 
 // x neighbour dword for active parity P (P = 0: the high dword of the group to
@@ -305,7 +316,7 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
 #pragma unroll
   for (int j = 0; j < G; ++j) {
     const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * (c.t + NT * j), yl * L, 0);
-    R[(S + 3) & 7][j] = make_uint2(w.x, w.y);
+    R[(S + 3) & 7][j] = split_group(w.x, w.y);
     E[(S + 3) & 7][j] = __builtin_amdgcn_raw_buffer_load_b32(c.rsrc, c.eoff[j], yl * L, 0);
   }
   if (i <= c.H + 1) {
@@ -336,7 +347,8 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
       const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, c.t,
                                           philox_base(y * GPR + NT * j), c.U1, *c.keys, c.pair, c.never8);
       R[(S + 5) & 7][j] = n;
-      const u32x2 w = {n.x, n.y};
+      const uint2 o = join_group(n);
+      const u32x2 w = {o.x, o.y};
       __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * (c.t + NT * j), y * L, 0);
     }
   }
@@ -383,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src,
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * (c.t + NT * j), y * L, 0);
-      R[k][j] = make_uint2(w.x, w.y);
+      R[k][j] = split_group(w.x, w.y);
       E[k][j] = __builtin_amdgcn_raw_buffer_load_b32(c.rsrc, c.eoff[j], y * L, 0);
     }
   }

@@ -275,39 +275,39 @@ struct Col3Ctx {
   uint32_t yhalo;     // y of the halo row the edge wave loads
 };
 
-// x neighbour dword of a group for active parity P: P = 0 needs the high
-// dword of the group to the left (lane - 1), P = 1 the low dword of the group
-// to the right (lane + 1); a row is one wavefront, so the rotates wrap x
-// periodically.
+// x neighbour dword of a parity-split group for active parity P: P = 0 needs
+// the odd half of the group to the left (lane - 1; its byte 3 is the site
+// left of the group), P = 1 the even half of the group to the right (lane + 1;
+// its byte 0); a row is one wavefront, so the rotates wrap x periodically.
 template <uint32_t P>
 __device__ __forceinline__ uint32_t xnb(uint2 c) {
   if (P == 0) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.y, 0x13C, 0xF, 0xF, false);  // wave_ror:1
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.x, 0x134, 0xF, 0xF, false);             // wave_rol:1
 }
 
-// One colour unit of a group with active parity P: centre c, y neighbours
-// ym, yp, z neighbours zm, zp; Philox counter base + lane, with mbase =
-// philox_base(base).  Returns the new group; with MEAS adds 4 x the
-// unsatisfied bonds of the active sites after the update to acc.  The
-// bounds come from the pair table (8u per packed byte), read before the
-// Philox rounds so that the LDS reads are in flight during them.
+// One colour unit of a parity-split group c (x: even bytes, y: odd bytes,
+// split_group) with active parity P: y neighbours ym, yp, z neighbours zm,
+// zp (split); Philox counter base + lane, with mbase = philox_base(base).
+// Returns the new group; with MEAS adds 4 x the unsatisfied bonds of the
+// active sites after the update to acc.  The active half and the neighbours'
+// halves of the same parity need no gathering; the bounds come from the pair
+// table (8u per packed byte), read before the Philox rounds so that the LDS
+// reads are in flight during them.
 template <uint32_t P, bool NEVER, bool MEAS>
 __device__ __forceinline__ uint2 col3_unit(uint2 c, uint2 ym, uint2 yp, uint2 zm, uint2 zp, uint32_t lane,
                                            uint64_t mbase, const PhiloxUniform& U, const RoundKeys& K,
                                            const char* pair, uint32_t never8, uint32_t& acc) {
-  const uint32_t nb = xnb<P>(c);
-  const uint32_t o0[4] = {ym.x, yp.x, zm.x, zp.x}, o1[4] = {ym.y, yp.y, zm.y, zp.y};
-  const uint32_t Sp = unsat_packed<4, kSignBit8>(P, c.x, c.y, nb, nb, o0, o1);
-  const uint4 b = lookup_pair(Sp, pair);
+  const uint32_t A = P ? c.y : c.x, I = P ? c.x : c.y;
+  const uint32_t N = __builtin_amdgcn_perm(I, xnb<P>(c), P ? 0x00070605u : 0x06050403u);
+  const uint32_t S = ((A ^ I) & kSignBit8) + ((A ^ N) & kSignBit8) + ((A ^ (P ? ym.y : ym.x)) & kSignBit8) +
+                     ((A ^ (P ? yp.y : yp.x)) & kSignBit8) + ((A ^ (P ? zm.y : zm.x)) & kSignBit8) +
+                     ((A ^ (P ? zp.y : zp.x)) & kSignBit8);
+  const uint4 b = lookup_pair(S, pair);
   uint32_t rnd[4];
   philox_lane_split(lane, mbase, U, K, rnd);
-  uint32_t c0n = c.x, c1n = c.y;
-  if (MEAS) {
-    apply_pair_count<NEVER, 3>(P, c0n, c1n, Sp, b, rnd, never8, acc);
-  } else {
-    apply_pair<NEVER>(P, c0n, c1n, Sp, b, rnd, never8);
-  }
-  return make_uint2(c0n, c1n);
+  const uint32_t An = MEAS ? apply_split_count<NEVER, 3>(A, S, b, rnd, never8, acc)
+                           : apply_split<NEVER>(A, S, b, rnd, never8);
+  return P ? make_uint2(c.x, An) : make_uint2(An, c.y);
 }
 
 // Register state of one wave: its two rows' z columns and, on the edge
@@ -325,7 +325,7 @@ template <uint32_t LL, int TY>
 __device__ __forceinline__ uint2 col3_load(const Col3Ctx<LL, TY>& c, uint32_t z, uint32_t y) {
   constexpr uint32_t L = Col3Ctx<LL, TY>::L;
   const u32x2r v = __builtin_amdgcn_raw_buffer_load_b64(c.rsrc, 8u * c.lane, (z * L + y) * L, 0);
-  return make_uint2(v.x, v.y);
+  return split_group(v.x, v.y);
 }
 
 // Step i of the pipeline (Q = i & 1; C1: colour 1 runs, i.e. i >= 2).  Row j
@@ -391,11 +391,13 @@ __device__ __forceinline__ void col3_step(const Col3Ctx<LL, TY>& c, Col3Regs& R,
   if (EDGE == 2) *reinterpret_cast<uint2*>(pN + 3 * L) = R.xh1;
   if (C1) {
     if (OWN0) {
-      const u32x2r w = {fin[0].x, fin[0].y};
+      const uint2 o = join_group(fin[0]);
+      const u32x2r w = {o.x, o.y};
       __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * c.lane, (b * L + c.yrow[0]) * L, 0);
     }
     if (OWN1) {
-      const u32x2r w = {fin[1].x, fin[1].y};
+      const uint2 o = join_group(fin[1]);
+      const u32x2r w = {o.x, o.y};
       __builtin_amdgcn_raw_buffer_store_b64(w, c.rdst, 8u * c.lane, (b * L + c.yrow[1]) * L, 0);
     }
   }
