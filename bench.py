@@ -46,11 +46,12 @@ BYTES_PER_ATTEMPT = 2.0  # int8 spin read once and written once per sweep (Ising
 LDS_PEAK_GBS = 256 * 128 * 2.4
 LDS_BYTES_PER_ATTEMPT = {2: 112 / 8.0, 3: 144 / 8.0}
 # The 3D register-column kernel (L = 512) keeps z columns and the wave's own rows in registers: per
-# 8-site group and sweep it stores the loaded row and the colour-0 result (16 B), reads one 8-byte
-# y neighbour per colour unit (16 B) and four bounds per unit (32 B): 64 B per 8 attempts.
-LDS_BYTES_PER_ATTEMPT_3R = 64 / 8.0
+# 8-site group and sweep it stores the loaded row and the colour-0 result (16 B), reads per colour
+# unit the active-parity half of one y neighbour (4 B; groups are held parity-split) and the bounds
+# of its four sites (two 8-byte pair-table entries, 16 B): 56 B per 8 attempts.
+LDS_BYTES_PER_ATTEMPT_3R = 56 / 8.0
 # The 2D register-column form keeps every row of its column in registers: per 8-site group and sweep
-# four bounds per colour unit (32 B) and one 4-byte segment-end word for colour 1 (4 B).
+# the bounds of four sites per colour unit (32 B) and one 4-byte segment-end word for colour 1 (4 B).
 LDS_BYTES_PER_ATTEMPT_2C = 36 / 8.0
 
 

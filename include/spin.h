@@ -185,7 +185,7 @@ int spin_set_stream(spin_lattice* h, void* stream);
  * lattice.  Results are bit-identical for every accepted choice.  2D Ising
  * in SPIN_KERNEL_FUSED with full rows (tile_x == L >= 4096): tile_y is the
  * strip height (even, >= 4) and tile_z 0 the row-streaming kernel, 1 its
- * register-column form (sweeps that record E/M run the former). */
+ * register-column form; both count E/M inside the sweep when a record is due. */
 int spin_set_kernel(spin_lattice* h, int kernel, int tile_x, int tile_y, int tile_z, int threads);
 
 /* Sec. 3, steps 1-7, with the generalized multi-hit of the paragraph after

@@ -811,11 +811,9 @@ hipError_t launch_fused_sweep(const Lat& lat, const int8_t* src, int8_t* dst, ui
   if ((uint32_t)tile.x == lat.L && tile.x >= 4096) {
     int G = 0;
     stream2d_shape(lat.L, tile.threads, &G);
-    // the register-column kernel does not count E/M: a sweep that records runs the row-streaming
-    // kernel, which counts inside the sweep (same chain)
-    if (tile.z == 1 && rec == nullptr)
-      return launch_stream2c(lat, src, dst, a, never, (uint32_t)tile.y, tile.threads, G, stream);
+    // both forms count E/M inside the sweep when asked, into one partial per workgroup (L / tile.y)
     if (measured) *measured = (rec != nullptr);
+    if (tile.z == 1) return launch_stream2c(lat, src, dst, a, never, (uint32_t)tile.y, rec, tile.threads, G, stream);
     return launch_stream2d(lat, src, dst, a, never, (uint32_t)tile.y, rec, tile.threads, G, stream);
   }
   if (tile.x == 512 && tile.threads == 256) {

@@ -49,10 +49,10 @@ inline PhaseArgs phase_args(const Lat& lat, uint32_t t, uint32_t colour, const A
 bool stream2d_shape(uint32_t L, int threads, int* G);
 hipError_t launch_stream2d(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
                            uint32_t H, const Record* rec, int threads, int G, hipStream_t stream);
-// The register-column form of the same sweep (k_stream2c, no E/M counting),
-// same shapes.
+// The register-column form of the same sweep (k_stream2c), same shapes; with
+// rec it also counts E/M inside the sweep into one partial per workgroup.
 hipError_t launch_stream2c(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
-                           uint32_t H, int threads, int G, hipStream_t stream);
+                           uint32_t H, const Record* rec, int threads, int G, hipStream_t stream);
 
 // 3D Ising streaming sweep: tile.x == L, tile.y = rows per workgroup, tile.z =
 // planes per strip, tile.threads = 64 * waves.  L = 512 with (16, 576) or

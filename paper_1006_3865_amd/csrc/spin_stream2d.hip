@@ -278,11 +278,12 @@ struct Col2Ctx {
 // = philox_base(base).  The other half of the group holds the neighbours on
 // one side, moved by one byte with nb's boundary byte shifted in those on
 // the other.  The bounds are read before the Philox rounds so that their LDS
-// reads are in flight during them.
-template <uint32_t P, bool NEVER>
+// reads are in flight during them.  With MEAS adds 4 x the unsatisfied bonds
+// of the active sites after the update to acc.
+template <uint32_t P, bool NEVER, bool MEAS>
 __device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t nb, uint32_t v, uint64_t mbase,
                                            const PhiloxUniform& U, const RoundKeys& K, const char* pair,
-                                           uint32_t never8) {
+                                           uint32_t never8, uint32_t& acc) {
   const uint32_t A = P ? c.y : c.x, I = P ? c.x : c.y;
   const uint32_t N = __builtin_amdgcn_perm(I, nb, P ? 0x00070605u : 0x06050403u);
   const uint32_t S = ((A ^ I) & kSignBit8) + ((A ^ N) & kSignBit8) + ((A ^ (P ? up.y : up.x)) & kSignBit8) +
@@ -290,7 +291,8 @@ __device__ __forceinline__ uint2 col2_unit(uint2 c, uint2 up, uint2 dn, uint32_t
   const uint4 b = lookup_pair(S, pair);
   uint32_t rnd[4];
   philox_lane_split(v, mbase, U, K, rnd);
-  const uint32_t An = apply_split<NEVER>(A, S, b, rnd, never8);
+  const uint32_t An = MEAS ? apply_split_count<NEVER, 2>(A, S, b, rnd, never8, acc)
+                           : apply_split<NEVER>(A, S, b, rnd, never8);
   return P ? make_uint2(c.x, An) : make_uint2(An, c.y);
 }
 
@@ -305,9 +307,9 @@ __device__ __forceinline__ uint32_t col2_xnb(uint2 c, uint32_t end) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)end, (int)c.x, 0x130, 0xF, 0xF, false);
 }
 
-template <int NT, int G, bool NEVER, uint32_t S>
+template <int NT, int G, bool NEVER, bool MEAS, uint32_t S>
 __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8][G], uint32_t (&E)[8][G],
-                                          uint32_t i) {
+                                          uint32_t i, uint32_t& unsat4, uint32_t& neg) {
   using C = Col2Ctx<NT, G>;
   constexpr uint32_t L = C::L, GPR = C::GPR;
   if (i >= c.H + 5) return;
@@ -328,8 +330,10 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 1) & 7][j];
       const uint32_t nb = col2_xnb<P>(cc, E[(S + 1) & 7][j]);
-      const uint2 n = col2_unit<P, NEVER>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, c.t,
-                                          philox_base(y * GPR + NT * j), c.U0, *c.keys, c.pair, c.never8);
+      uint32_t none = 0;
+      const uint2 n = col2_unit<P, NEVER, false>(cc, R[S & 7][j], R[(S + 2) & 7][j], nb, c.t,
+                                                 philox_base(y * GPR + NT * j), c.U0, *c.keys, c.pair, c.never8,
+                                                 none);
       R[(S + 1) & 7][j] = n;
       slot[c.wlo[j]] = n.x;
       slot[c.whi[j]] = n.y;
@@ -344,8 +348,11 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
     for (int j = 0; j < G; ++j) {
       const uint2 cc = R[(S + 5) & 7][j];
       const uint32_t nb = col2_xnb<P>(cc, slot[P == 0 ? c.lnb[j] : c.rnb[j]]);
-      const uint2 n = col2_unit<P, NEVER>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, c.t,
-                                          philox_base(y * GPR + NT * j), c.U1, *c.keys, c.pair, c.never8);
+      const uint2 n = col2_unit<P, NEVER, MEAS>(cc, R[(S + 4) & 7][j], R[(S + 6) & 7][j], nb, c.t,
+                                                philox_base(y * GPR + NT * j), c.U1, *c.keys, c.pair, c.never8,
+                                                unsat4);
+      // the group is final: count its negative spins
+      if (MEAS) neg += __popc(n.x & 0x80808080u) + __popc(n.y & 0x80808080u);
       R[(S + 5) & 7][j] = n;
       const uint2 o = join_group(n);
       const u32x2 w = {o.x, o.y};
@@ -355,9 +362,9 @@ __device__ __forceinline__ void col2_step(const Col2Ctx<NT, G>& c, uint2 (&R)[8]
   if ((S & 3u) == 3u) __syncthreads();
 }
 
-template <int NT, int G, bool NEVER>
+template <int NT, int G, bool NEVER, bool MEAS>
 __global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src, int8_t* __restrict__ dst,
-                                                 PhaseArgs a, uint32_t H) {
+                                                 PhaseArgs a, uint32_t H, Record rec) {
   using C = Col2Ctx<NT, G>;
   constexpr uint32_t L = C::L, NS = C::NS;
   __shared__ __align__(16) uint32_t lds[C::PW + 8 * C::SW];
@@ -407,16 +414,24 @@ __global__ __launch_bounds__(NT) void k_stream2c(const int8_t* __restrict__ src,
       E[k][j] = 0u;
     }
   __syncthreads();
+  // with MEAS: 4 x the unsatisfied bonds of the strip's colour-1 sites after their update (every
+  // bond joins a colour-0 and a colour-1 site, and the colour-0 sites are final by then) and the
+  // negative spins of its final groups
+  uint32_t unsat4 = 0, neg = 0;
   const uint32_t steps = H + 5;
   for (uint32_t i0 = 0; i0 < steps; i0 += 8) {
-    col2_step<NT, G, NEVER, 0>(c, R, E, i0 + 0);
-    col2_step<NT, G, NEVER, 1>(c, R, E, i0 + 1);
-    col2_step<NT, G, NEVER, 2>(c, R, E, i0 + 2);
-    col2_step<NT, G, NEVER, 3>(c, R, E, i0 + 3);
-    col2_step<NT, G, NEVER, 4>(c, R, E, i0 + 4);
-    col2_step<NT, G, NEVER, 5>(c, R, E, i0 + 5);
-    col2_step<NT, G, NEVER, 6>(c, R, E, i0 + 6);
-    col2_step<NT, G, NEVER, 7>(c, R, E, i0 + 7);
+    col2_step<NT, G, NEVER, MEAS, 0>(c, R, E, i0 + 0, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 1>(c, R, E, i0 + 1, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 2>(c, R, E, i0 + 2, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 3>(c, R, E, i0 + 3, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 4>(c, R, E, i0 + 4, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 5>(c, R, E, i0 + 5, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 6>(c, R, E, i0 + 6, unsat4, neg);
+    col2_step<NT, G, NEVER, MEAS, 7>(c, R, E, i0 + 7, unsat4, neg);
+  }
+  if (MEAS) {
+    __shared__ int64_t red[NT / 64];
+    record_block<NT>((int64_t)(unsat4 >> 2), (int64_t)neg, rec, red);
   }
 }
 
@@ -453,22 +468,30 @@ static hipError_t gostream(const Lat& lat, const int8_t* src, int8_t* dst, const
 
 template <int NT, int G>
 static hipError_t gocol2(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
-                         uint32_t H, hipStream_t stream) {
+                         uint32_t H, const Record* rec, hipStream_t stream) {
   dim3 grid(lat.L / H);
-  if (never)
-    hipLaunchKernelGGL((k_stream2c<NT, G, true>), grid, dim3(NT), 0, stream, src, dst, a, H);
-  else
-    hipLaunchKernelGGL((k_stream2c<NT, G, false>), grid, dim3(NT), 0, stream, src, dst, a, H);
+  const Record r = rec ? *rec : Record{nullptr};
+  if (rec) {
+    if (never)
+      hipLaunchKernelGGL((k_stream2c<NT, G, true, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2c<NT, G, false, true>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  } else {
+    if (never)
+      hipLaunchKernelGGL((k_stream2c<NT, G, true, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+    else
+      hipLaunchKernelGGL((k_stream2c<NT, G, false, false>), grid, dim3(NT), 0, stream, src, dst, a, H, r);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_stream2c(const Lat& lat, const int8_t* src, int8_t* dst, const PhaseArgs& a, bool never,
-                           uint32_t H, int threads, int G, hipStream_t stream) {
-  if (threads == 1024 && G == 1) return gocol2<1024, 1>(lat, src, dst, a, never, H, stream);
-  if (threads == 1024 && G == 2) return gocol2<1024, 2>(lat, src, dst, a, never, H, stream);
-  if (threads == 512 && G == 1) return gocol2<512, 1>(lat, src, dst, a, never, H, stream);
-  if (threads == 512 && G == 2) return gocol2<512, 2>(lat, src, dst, a, never, H, stream);
-  if (threads == 256 && G == 2) return gocol2<256, 2>(lat, src, dst, a, never, H, stream);
+                           uint32_t H, const Record* rec, int threads, int G, hipStream_t stream) {
+  if (threads == 1024 && G == 1) return gocol2<1024, 1>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 1024 && G == 2) return gocol2<1024, 2>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 512 && G == 1) return gocol2<512, 1>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 512 && G == 2) return gocol2<512, 2>(lat, src, dst, a, never, H, rec, stream);
+  if (threads == 256 && G == 2) return gocol2<256, 2>(lat, src, dst, a, never, H, rec, stream);
   return hipErrorInvalidValue;
 }
 

@@ -283,10 +283,10 @@ def test_ising2d_streaming_rows(oracle_mod, tile, L):
     ((8192, 16, 1, 1024), 8192), ((8192, 32, 1, 512), 8192), ((8192, 4, 1, 1024), 8192),
 ])
 def test_ising2d_register_columns(oracle_mod, tile, L):
-    """Register-column form of the row-streaming kernel (tile_z = 1): sweeps without records run it,
-    sweeps that record run the row-streaming kernel; both continue one chain.  Several strips, one
-    and two 8-site groups per thread, the periodic x wrap between the first and last segment, and
-    betas with T == 0 entries (3, inf) and 0."""
+    """Register-column form of the row-streaming kernel (tile_z = 1), with and without E/M counted
+    inside the sweep (records every 2 and 5 sweeps, one of them at a beta with T == 0 entries).
+    Several strips, one and two 8-site groups per thread, the periodic x wrap between the first
+    and last segment, and betas with T == 0 entries (3, inf) and 0."""
     sched = [(3, B_CRIT, 0), (2, 3.0, 2), (5, 0.6, 5), (1, 0.0, 0), (2, math.inf, 0), (4, 0.3, 0)]
     compare_runs(oracle_mod, 0, L, 2, workloads.seed(0x90 + L), sched, replica=2, kernel=FUS, tile=tile,
                  tag="columns")
