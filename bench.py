@@ -333,8 +333,10 @@ def bench_coarse(torch, spin, workloads, sizes=(1024, 8192), tiles=(16, 32, 64),
         for T in tiles:
             for k in hits:
                 lat.set_schedule(spin.SPIN_SCHEDULE_COARSE, T, k)
-                n = max(2, int(4e9 / (k * L * L)))
-                n = min(n, 400)
+                # about 3e10 attempts per point (tens of milliseconds): shorter windows catch the
+                # GPU's clock still rising and scatter by several per cent
+                n = max(2, int(3e10 / (k * L * L)))
+                n = min(n, 2000)
                 lat.sweep(1, workloads.BETA_2D_CRIT)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(stream)
