@@ -72,29 +72,6 @@ __device__ __forceinline__ void apply_packed(uint32_t P, uint32_t& c0, uint32_t&
   c1 = xor3(c1, f2, f3);
 }
 
-// apply_packed that also adds to acc four times the number of unsatisfied
-// bonds of the four active sites after the update (D: lattice dimension).
-// S holds 4u per site before it; a flipped site has 2D - u unsatisfied bonds
-// afterwards (every one of its bonds changes), so its byte becomes 8D - S_m
-// (no byte borrows: S_m <= 8D).  One v_sad_u8 against zero sums the bytes.
-template <bool NEVER, int D>
-__device__ __forceinline__ void apply_packed_count(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S,
-                                                   const uint32_t r[4], const uint32_t* bound_lds, uint32_t never4,
-                                                   uint32_t& acc) {
-  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
-  const uint32_t f0 = flip_mask<NEVER>(S & 0xFFu, r[0], ma, bound_lds, never4);
-  const uint32_t f1 = flip_mask<NEVER>(__builtin_amdgcn_perm(0u, S, 0x0C0C0C01u), r[1], mb, bound_lds, never4);
-  const uint32_t f2 = flip_mask<NEVER>(__builtin_amdgcn_ubfe(S, 16u, 8u), r[2], ma, bound_lds, never4);
-  const uint32_t f3 = flip_mask<NEVER>(S >> 24, r[3], mb, bound_lds, never4);
-  const uint32_t d0 = f0 ^ f1, d1 = f2 ^ f3;
-  c0 ^= d0;
-  c1 ^= d1;
-  const uint32_t F = gather_bytes(d0, d1, sel_active(P));  // 0xFE at the packed sites that flipped
-  constexpr uint32_t K = 0x01010101u * (8u * (uint32_t)D);
-  const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
-  acc = __builtin_amdgcn_sad_u8(Sf, 0u, acc);
-}
-
 // Pair table: the bounds of two packed sites in one 8-byte LDS entry.  With
 // 8u per byte, the low 16 bits of the packed dword, 8 u0 + 2048 u1, are the
 // byte offset of the entry {bound[u0], bound[u1]} of packed sites 0 and 1, the
@@ -118,48 +95,6 @@ __device__ __forceinline__ uint4 lookup_pair(uint32_t S, const char* pair_lds) {
   const uint2 b01 = *(const uint2*)(pair_lds + (S & 0xFFFFu));
   const uint2 b23 = *(const uint2*)(pair_lds + (S >> 16));
   return make_uint4(b01.x, b01.y, b23.x, b23.y);
-}
-
-// apply_packed for a packed dword S of 8u values with the bounds b from
-// lookup_pair; never8 = 8 never_level.
-template <bool NEVER>
-__device__ __forceinline__ void apply_pair(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S, uint4 b,
-                                           const uint32_t r[4], uint32_t never8) {
-  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
-  if (NEVER) {
-    a0 = a0 && (S & 0xFFu) >= never8;
-    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
-    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
-    a3 = a3 && (S >> 24) >= never8;
-  }
-  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
-  c0 = xor3(c0, a0 ? ma : 0u, a1 ? mb : 0u);
-  c1 = xor3(c1, a2 ? ma : 0u, a3 ? mb : 0u);
-}
-
-// apply_pair that also adds to acc four times the number of unsatisfied bonds
-// of the four active sites after the update (D: lattice dimension): a flipped
-// site's byte becomes 16D - S_m (no byte borrows: S_m <= 16D); the bytes are
-// multiples of 8, so halving the dword halves every byte without a carry from
-// the byte above, and one v_sad_u8 against zero sums them.
-template <bool NEVER, int D>
-__device__ __forceinline__ void apply_pair_count(uint32_t P, uint32_t& c0, uint32_t& c1, uint32_t S, uint4 b,
-                                                 const uint32_t r[4], uint32_t never8, uint32_t& acc) {
-  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
-  if (NEVER) {
-    a0 = a0 && (S & 0xFFu) >= never8;
-    a1 = a1 && __builtin_amdgcn_perm(0u, S, 0x0C0C0C01u) >= never8;
-    a2 = a2 && __builtin_amdgcn_ubfe(S, 16u, 8u) >= never8;
-    a3 = a3 && (S >> 24) >= never8;
-  }
-  const uint32_t ma = 0xFEu << (8u * P), mb = 0xFEu << (8u * P + 16u);
-  const uint32_t d0 = (a0 ? ma : 0u) ^ (a1 ? mb : 0u), d1 = (a2 ? ma : 0u) ^ (a3 ? mb : 0u);
-  c0 ^= d0;
-  c1 ^= d1;
-  const uint32_t F = gather_bytes(d0, d1, sel_active(P));  // 0xFE at the packed sites that flipped
-  constexpr uint32_t K = 0x01010101u * (16u * (uint32_t)D);
-  const uint32_t Sf = S ^ ((S ^ (K - S)) & F);
-  acc = __builtin_amdgcn_sad_u8(Sf >> 1, 0u, acc);
 }
 
 // Parity-split form of an 8-site group: x = its even bytes (sites 8g, 8g+2,
@@ -189,8 +124,12 @@ __device__ __forceinline__ uint32_t apply_split(uint32_t A, uint32_t S, uint4 b,
 }
 
 // apply_split that also adds to acc four times the number of unsatisfied
-// bonds of the four active sites after the update (D: lattice dimension), as
-// apply_pair_count does; the flip mask of the packed sites is the XOR itself.
+// bonds of the four active sites after the update (D: lattice dimension): a
+// flipped site has 2D - u unsatisfied bonds afterwards (every one of its bonds
+// changes), so its byte becomes 16D - S_m (no byte borrows: S_m <= 16D); the
+// bytes are multiples of 8, so halving the dword halves every byte without a
+// carry from the byte above, and one v_sad_u8 against zero sums them.  The
+// flip mask of the packed sites is the XOR itself.
 template <bool NEVER, int D>
 __device__ __forceinline__ uint32_t apply_split_count(uint32_t A, uint32_t S, uint4 b, const uint32_t r[4],
                                                       uint32_t never8, uint32_t& acc) {
