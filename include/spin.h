@@ -176,6 +176,14 @@ uint64_t spin_sweeps_done(const spin_lattice* h);
  * state together with spin_set_spins).  index + later sweeps < 2^32. */
 int spin_set_sweeps_done(spin_lattice* h, uint64_t t);
 
+/* Sec. 4 (many independent runs of one system): the third Philox counter
+ * word of later updates becomes `replica`; spins and sweep index stay, so the
+ * chain continues as that replica's from the present state (the hot start of
+ * a new handle also draws with the replica it was created with).
+ * SPIN_ESTATE in the LCG draw modes, whose generators were seeded from the
+ * replica when the mode was set. */
+int spin_set_replica(spin_lattice* h, uint32_t replica);
+
 /* Enqueue later work on this hipStream_t (NULL = null stream). */
 int spin_set_stream(spin_lattice* h, void* stream);
 

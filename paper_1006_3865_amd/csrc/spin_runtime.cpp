@@ -958,6 +958,14 @@ int spin_set_sweeps_done(spin_lattice* h, uint64_t t) {
   return SPIN_OK;
 }
 
+int spin_set_replica(spin_lattice* h, uint32_t replica) {
+  if (!h) return fail(SPIN_EINVAL, "NULL handle");
+  if (h->rng != SPIN_RNG_PHILOX)
+    return fail(SPIN_ESTATE, "the LCG draw modes seed their generators from the replica when the mode is set");
+  h->replica = replica;
+  return SPIN_OK;
+}
+
 int spin_set_stream(spin_lattice* h, void* stream) {
   if (!h) return fail(SPIN_EINVAL, "NULL handle");
   h->stream = (hipStream_t)stream;

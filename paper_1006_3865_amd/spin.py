@@ -62,6 +62,7 @@ SIGNATURES = {
     "spin_get_couplings": (_c.c_int, [_P, _i8p, _c.c_size_t]),
     "spin_sweeps_done": (_c.c_uint64, [_P]),
     "spin_set_sweeps_done": (_c.c_int, [_P, _c.c_uint64]),
+    "spin_set_replica": (_c.c_int, [_P, _c.c_uint32]),
     "spin_set_stream": (_c.c_int, [_P, _c.c_void_p]),
     "spin_set_kernel": (_c.c_int, [_P, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "spin_get_kernel": (_c.c_int, [_P]),
@@ -269,6 +270,10 @@ def spin_set_sweeps_done(h, t):
     return _check(load().spin_set_sweeps_done(h, t))
 
 
+def spin_set_replica(h, replica):
+    return _check(load().spin_set_replica(h, replica))
+
+
 def spin_set_stream(h, stream):
     return _check(load().spin_set_stream(h, stream))
 
@@ -416,6 +421,10 @@ class Lattice:
     @t.setter
     def t(self, value):
         spin_set_sweeps_done(self.h, value)
+
+    def set_replica(self, replica):
+        """Later updates draw as replica `replica` (spins and sweep index stay)."""
+        spin_set_replica(self.h, replica)
 
     def set_kernel(self, kernel, tile_x=0, tile_y=0, tile_z=0, threads=0):
         spin_set_kernel(self.h, kernel, tile_x, tile_y, tile_z, threads)

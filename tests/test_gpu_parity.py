@@ -242,6 +242,35 @@ def test_resume_from_saved_state(oracle_mod):
     b.close()
 
 
+def test_set_replica_continues_as_that_replica(oracle_mod):
+    """spin_set_replica: after it the chain is the given replica's from the present state (equal to
+    a handle created with that replica and resumed from the same spins and sweep index, and unlike
+    the old replica's continuation); refused in an LCG draw mode."""
+    L, s = 256, workloads.seed(52)
+    a = make(0, L, 2, s)
+    a.sweep(7, 0.5)
+    saved, t = a.spins(), a.t
+    a.set_replica(3)
+    a.sweep(5, 0.5)
+    b = make(0, L, 2, s, replica=3)
+    b.set_spins(saved)
+    b.t = t
+    b.sweep(5, 0.5)
+    c = make(0, L, 2, s)
+    c.set_spins(saved)
+    c.t = t
+    c.sweep(5, 0.5)
+    np.testing.assert_array_equal(a.spins(), b.spins())
+    assert not np.array_equal(a.spins(), c.spins())
+    d = make(0, 64, 2, s)
+    d.set_rng(spin.SPIN_RNG_LCG32_ARRAY)
+    with pytest.raises(spin.SpinError) as ei:
+        d.set_replica(1)
+    assert ei.value.code == spin.SPIN_ESTATE
+    for h in (a, b, c, d):
+        h.close()
+
+
 def test_device_records_and_torch_stream(oracle_mod, gpu):
     torch = gpu
     L, s = 512, workloads.seed(52)
