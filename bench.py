@@ -832,7 +832,7 @@ def main():
         "config": {"workload": args.workload, "model": "ising", "L": cfg["L"], "d": cfg["d"],
                    "betas": [float(b) for b in cfg["betas"]], "sweeps_per_step": head["sweeps_per_step"],
                    "record_every": cfg["every"], "lattices": head["lattices"], "kernel": head["kernel"],
-                   "parallelism": "single GPU"},
+                   "untimed_settle_s": head["settle_s"], "parallelism": "single GPU"},
         "sweep_only_attempts_per_ns": head["sweep_only_attempts_per_ns"],
         "hbm_frac_sweep_only": head["hbm_frac_sweep_only"],
         "roofline": head["roofline"],
