@@ -20,6 +20,7 @@
 
 #include "spin_internal.h"
 #include "spin_nibble.h"
+#include "spin_packed.h"
 
 namespace spin {
 
@@ -33,6 +34,25 @@ struct CoarseArgs {
   uint32_t replica;
   uint32_t q;        // tile parity of this launch
 };
+
+// nib_flips with the bounds from the pair table (spin_packed.h): the active
+// nibbles' counts 2u, shifted to 8u per byte, give the byte offsets of two
+// 8-byte entries (sites 0 and 1, sites 2 and 3) in two operations where four
+// extractions were; never8 = 8 never_level.
+template <bool NEVER>
+__device__ __forceinline__ uint32_t nib_flips_pair(uint32_t S, uint32_t p, const uint32_t r[4], const char* pair,
+                                                   uint32_t never8) {
+  const uint32_t T = ((S >> (4u * p)) & 0x0F0F0F0Fu) << 2;  // byte i: 8u of active nibble i
+  const uint4 b = lookup_pair(T, pair);
+  bool a0 = r[0] <= b.x, a1 = r[1] <= b.y, a2 = r[2] <= b.z, a3 = r[3] <= b.w;
+  if (NEVER) {
+    a0 = a0 && (T & 0xFFu) >= never8;
+    a1 = a1 && __builtin_amdgcn_perm(0u, T, 0x0C0C0C01u) >= never8;
+    a2 = a2 && __builtin_amdgcn_ubfe(T, 16u, 8u) >= never8;
+    a3 = a3 && (T >> 24) >= never8;
+  }
+  return (xor3(a0 ? 0xEu : 0u, a1 ? 0xE00u : 0u, a2 ? 0xE0000u : 0u) ^ (a3 ? 0xE000000u : 0u)) << (4u * p);
+}
 
 __device__ __forceinline__ uint32_t wrap_m1(uint32_t v, uint32_t n) {  // (v - 1) mod n for v < 2n
   uint32_t w = v + n - 1u;
@@ -49,7 +69,11 @@ __global__ __launch_bounds__(NT) void k_coarse(int8_t* __restrict__ spins, const
   constexpr uint32_t PW = RR * RW;                   // words per LDS plane
   constexpr uint32_t NWL = PL * PW;                  // words of the LDS block
   constexpr uint32_t U = (D == 3) ? T * T * TW : T * TW;  // units (tile words) per colour step
-  __shared__ uint32_t bound[8];
+  // accept bounds: the pair table (8 KB) for 2D tiles of edge 32 and 64, the per-u table otherwise
+  // (with the small workgroups of smaller tiles, or the 12 KB table of 3D, LDS would cost
+  // workgroups per CU: 2D T = 16 lost 25 % at k = 1 with it)
+  constexpr bool PAIR = D == 2 && T >= 32;
+  __shared__ __align__(16) uint32_t bound[PAIR ? pair_words(4) : 8];
   __shared__ uint32_t sp[NWL];
   __shared__ uint32_t jl[EA ? D * NWL : 1];
   const uint32_t L = a.L, GPR = L / 8;
@@ -65,7 +89,10 @@ __global__ __launch_bounds__(NT) void k_coarse(int8_t* __restrict__ spins, const
   const uint32_t by = byz % nby, bz = (D == 3) ? byz / nby : 0u;
   const uint32_t bx = 2u * bxh + ((by + bz + a.q) & 1u);
   const uint32_t x0w = bx * TW, y0 = by * T, z0 = bz * T;  // first word column, row, plane
-  if (threadIdx.x < 8) bound[threadIdx.x] = a.bound[threadIdx.x];
+  if (PAIR)
+    fill_pair<4>(bound, a.bound, threadIdx.x);
+  else if (threadIdx.x < 8)
+    bound[threadIdx.x] = a.bound[threadIdx.x];
   gu32* Jn = as_global(Jraw);
   // load the tile and its boundary layer
   for (uint32_t i = threadIdx.x; i < NWL; i += NT) {
@@ -117,7 +144,8 @@ __global__ __launch_bounds__(NT) void k_coarse(int8_t* __restrict__ spins, const
         uint32_t rnd[4];
         philox_lane(w, Uph, a.keys, rnd);
         const uint32_t p = (c + y + z) & 1u;
-        sp[o] = cv ^ nib_flips<NEVER>(S, p, rnd, bound, a.never4);
+        sp[o] = cv ^ (PAIR ? nib_flips_pair<NEVER>(S, p, rnd, (const char*)bound, 2u * a.never4)
+                           : nib_flips<NEVER>(S, p, rnd, bound, a.never4));
       }
       __syncthreads();
     }
