@@ -85,6 +85,8 @@ def test_null_handle_and_bad_beta(lib):
     assert lib.spin_threshold_table(float("nan"), 2, T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) == spin.SPIN_EINVAL
     assert lib.spin_threshold_table(-0.1, 2, T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) == spin.SPIN_EINVAL
     assert lib.spin_threshold_table(0.5, 4, T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) == spin.SPIN_EINVAL
+    assert lib.spin_set_replica(None, 1) == spin.SPIN_EINVAL
+    assert lib.spin_set_sweeps_done(None, 1) == spin.SPIN_EINVAL
     lib.spin_free(None)  # NULL-safe
 
 
